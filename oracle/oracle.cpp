@@ -1,0 +1,536 @@
+// CPU oracle for the EMT nodal-analysis time loop — TEST INFRASTRUCTURE ONLY.
+//
+// Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+// may load this library. It shares no code with the GPU library: it reads the
+// same network description (branch list, parameters, events) and nothing else.
+//
+// What it computes (the paper, Sec. III-A, lists the four basic processes of
+// an EMTP-type solver: update each component's Norton equivalent (history
+// current and conductance), assemble nodal injected currents, factorise the
+// nodal conductance matrix, forward/back substitute for node voltages; the
+// formulas are the textbook trapezoidal companion models of the EMTP method
+// the paper cites as its reference [2]):
+//
+//   companion (per in-service branch b, time step dt):
+//     series R-L (and source impedance):  g = 1/(R + 2L/dt),
+//                                         beta = (2L/dt - R) g, gamma = g
+//     capacitor:                          g = 2C/dt, beta = -1, gamma = -g
+//     resistor / closed switch:           g = 1/R,   beta = gamma = 0
+//     out-of-service branch:              g = beta = gamma = 0, u = i = 0
+//   state at step 0: v_0 = 0, i_0 = 0, u_0 = A^T v_0 - e_0 (zero state,
+//     sources active from t = 0), unless an initial state is supplied.
+//   for n = 1..T (t_n = n dt):
+//     apply the events of step n (switches change, G is re-assembled and
+//       re-factorised: the new topology produces v_n);
+//     h_n   = beta * i_{n-1} + gamma * u_{n-1}              (history current)
+//     e_n   = E cos(omega t_n + phase)       (source branches; 0 elsewhere)
+//     rhs_n = A (g * e_n - h_n)                          (nodal injections)
+//     v_n   = G^{-1} rhs_n,  G = A diag(g) A^T    (dense LU, partial pivot)
+//     u_n   = A^T v_n - e_n,  i_n = g * u_n + h_n         (branch update)
+//   A is the node-by-branch incidence matrix (+1 at k_b, -1 at m_b, ground
+//   rows dropped), u_b is the voltage across the branch's passive part and
+//   i_b flows from k_b to m_b.
+//
+// Discrete adjoint of that recursion (reverse time, hbar_{T+1} = 0):
+//     ibar_n = beta_{n+1} hbar_{n+1}
+//     q_n    = gamma_{n+1} hbar_{n+1} + g_n ibar_n            (= ubar_n)
+//     vbar_n = dJ/dv_n + A q_n,   w_n = G_n^{-T} vbar_n
+//     hbar_n = ibar_n - A^T w_n
+//     gbar += hbar_n u_n, betabar += hbar_n i_{n-1}, gammabar += hbar_n u_{n-1}
+//   then the chain rule to the per-line parameters (R_l, L_l, C_l).
+//
+// Everything is plain loops over dense arrays in the scalar type T (double,
+// or std::complex<double> for complex-step differentiation; pivots are chosen
+// by |Re| so that the complex run stays analytic).
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4 };
+
+}  // namespace
+
+extern "C" {
+
+// Network description as plain arrays (layout mirrors the generator's
+// Network object; the GPU library has its own declaration of this shape).
+struct OracleNet {
+  int32_t n_nodes, n_branches;
+  const int32_t *k, *m, *kind;
+  const double *R, *L, *C, *E, *omega, *phase;
+  const int32_t *line;
+  int32_t n_params;
+  const uint8_t *in_service0;  // may be null: all in service, switches open
+  int32_t n_events;
+  const int64_t *ev_step;
+  const int32_t *ev_branch;
+  const uint8_t *ev_in_service;
+  int32_t n_rec;
+  const int32_t *rec_nodes;  // may be null: every node
+};
+
+}  // extern "C"
+
+namespace {
+
+using cplx = std::complex<double>;
+
+inline double re(double x) { return x; }
+inline double re(const cplx &x) { return x.real(); }
+
+template <class T>
+struct Companions {
+  std::vector<T> g, beta, gamma;
+};
+
+// Per-branch R, L, C with the line parameters theta applied (series branch:
+// R_l, L_l; each shunt capacitor of a pi-section: C_l / 2).
+template <class T>
+void branch_values(const OracleNet &net, const T *theta, int b, T &R, T &L, T &C) {
+  R = T(net.R[b]);
+  L = T(net.L[b]);
+  C = T(net.C[b]);
+  const int l = net.line[b];
+  if (theta && l >= 0) {
+    if (net.kind[b] == K_RL) {
+      R = theta[3 * l + 0];
+      L = theta[3 * l + 1];
+    } else if (net.kind[b] == K_C) {
+      C = theta[3 * l + 2] / 2.0;
+    }
+  }
+}
+
+template <class T>
+void companions(const OracleNet &net, const T *theta, double dt,
+                const std::vector<uint8_t> &ins, Companions<T> &c) {
+  const int B = net.n_branches;
+  c.g.assign(B, T(0));
+  c.beta.assign(B, T(0));
+  c.gamma.assign(B, T(0));
+  for (int b = 0; b < B; ++b) {
+    if (!ins[b]) continue;
+    T R, L, C;
+    branch_values(net, theta, b, R, L, C);
+    switch (net.kind[b]) {
+      case K_RL:
+      case K_SRC: {
+        T g = T(1) / (R + T(2) * L / dt);
+        c.g[b] = g;
+        c.beta[b] = (T(2) * L / dt - R) * g;
+        c.gamma[b] = g;
+        break;
+      }
+      case K_C: {
+        T g = T(2) * C / dt;
+        c.g[b] = g;
+        c.beta[b] = T(-1);
+        c.gamma[b] = -g;
+        break;
+      }
+      default: {  // resistor or closed switch
+        c.g[b] = T(1) / R;
+        break;
+      }
+    }
+  }
+}
+
+// Dense LU with partial pivoting (row swaps), in place, row-major n x n.
+template <class T>
+struct DenseLU {
+  int n = 0;
+  std::vector<T> a;
+  std::vector<int> piv;
+
+  bool factor(const std::vector<T> &G, int n_) {
+    n = n_;
+    a = G;
+    piv.resize(n);
+    for (int j = 0; j < n; ++j) {
+      int p = j;
+      double best = std::fabs(re(a[(size_t)j * n + j]));
+      for (int i = j + 1; i < n; ++i) {
+        double v = std::fabs(re(a[(size_t)i * n + j]));
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      piv[j] = p;
+      if (best == 0.0) return false;
+      if (p != j)
+        for (int c = 0; c < n; ++c) std::swap(a[(size_t)j * n + c], a[(size_t)p * n + c]);
+      const T d = a[(size_t)j * n + j];
+      for (int i = j + 1; i < n; ++i) {
+        T f = a[(size_t)i * n + j] / d;
+        a[(size_t)i * n + j] = f;
+        if (f == T(0)) continue;
+        T *ri = &a[(size_t)i * n];
+        const T *rj = &a[(size_t)j * n];
+        for (int c = j + 1; c < n; ++c) ri[c] -= f * rj[c];
+      }
+    }
+    return true;
+  }
+
+  // Solve G x = b: P G = L U.
+  void solve(std::vector<T> &x) const {
+    for (int j = 0; j < n; ++j)
+      if (piv[j] != j) std::swap(x[j], x[piv[j]]);
+    for (int i = 0; i < n; ++i) {
+      T s = x[i];
+      const T *ri = &a[(size_t)i * n];
+      for (int c = 0; c < i; ++c) s -= ri[c] * x[c];
+      x[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      T s = x[i];
+      const T *ri = &a[(size_t)i * n];
+      for (int c = i + 1; c < n; ++c) s -= ri[c] * x[c];
+      x[i] = s / ri[i];
+    }
+  }
+
+  // Solve G^T x = b: G^T = U^T L^T P, so U^T y = b, L^T z = y, x = P^T z.
+  void solve_transposed(std::vector<T> &x) const {
+    for (int i = 0; i < n; ++i) {
+      T s = x[i];
+      for (int c = 0; c < i; ++c) s -= a[(size_t)c * n + i] * x[c];
+      x[i] = s / a[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      T s = x[i];
+      for (int c = i + 1; c < n; ++c) s -= a[(size_t)c * n + i] * x[c];
+      x[i] = s;
+    }
+    for (int j = n - 1; j >= 0; --j)
+      if (piv[j] != j) std::swap(x[j], x[piv[j]]);
+  }
+};
+
+template <class T>
+void assemble(const OracleNet &net, const Companions<T> &c, std::vector<T> &G) {
+  const int N = net.n_nodes;
+  G.assign((size_t)N * N, T(0));
+  for (int b = 0; b < net.n_branches; ++b) {
+    const int k = net.k[b], m = net.m[b];
+    const T g = c.g[b];
+    if (k >= 0) G[(size_t)k * N + k] += g;
+    if (m >= 0) G[(size_t)m * N + m] += g;
+    if (k >= 0 && m >= 0) {
+      G[(size_t)k * N + m] -= g;
+      G[(size_t)m * N + k] -= g;
+    }
+  }
+}
+
+inline double emf(const OracleNet &net, int b, int64_t n, double dt) {
+  if (net.kind[b] != K_SRC) return 0.0;
+  const double t = (double)n * dt;
+  return net.E[b] * std::cos(net.omega[b] * t + net.phase[b]);
+}
+
+bool valid(const OracleNet &net, double dt, int64_t T) {
+  if (!(dt > 0) || T < 0 || net.n_nodes <= 0 || net.n_branches < 0) return false;
+  for (int b = 0; b < net.n_branches; ++b) {
+    const int k = net.k[b], m = net.m[b];
+    if (k < -1 || k >= net.n_nodes || m < -1 || m >= net.n_nodes) return false;
+    if (k < 0 && m < 0) return false;
+    if (net.kind[b] < 0 || net.kind[b] > 4) return false;
+  }
+  for (int j = 0; j < net.n_events; ++j) {
+    if (net.ev_step[j] < 1) return false;
+    if (net.ev_branch[j] < 0 || net.ev_branch[j] >= net.n_branches) return false;
+  }
+  for (int r = 0; r < net.n_rec; ++r)
+    if (net.rec_nodes && (net.rec_nodes[r] < 0 || net.rec_nodes[r] >= net.n_nodes)) return false;
+  return true;
+}
+
+inline int rec_node(const OracleNet &net, int r) { return net.rec_nodes ? net.rec_nodes[r] : r; }
+
+// One forward run. Optional outputs may be null. Trajectories have T+1 rows
+// (row 0 = initial state). Returns 0 on success, 1 on bad input, 2 on a
+// singular conductance matrix.
+template <class T>
+int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
+            const double *v0, const double *i0, T *rec, T *v_traj, T *i_traj, T *u_traj,
+            std::vector<int> *topo_of_step, std::vector<Companions<T>> *topos,
+            std::vector<DenseLU<T>> *lus) {
+  if (!valid(net, dt, Tn)) return 1;
+  const int N = net.n_nodes, B = net.n_branches;
+  std::vector<uint8_t> ins(B);
+  for (int b = 0; b < B; ++b)
+    ins[b] = net.in_service0 ? net.in_service0[b] : (net.kind[b] == K_SWITCH ? 0 : 1);
+
+  Companions<T> c;
+  companions(net, theta, dt, ins, c);
+  std::vector<T> G;
+  assemble(net, c, G);
+  DenseLU<T> lu;
+  if (!lu.factor(G, N)) return 2;
+  if (topos) {
+    topos->clear();
+    topos->push_back(c);
+  }
+  if (lus) {
+    lus->clear();
+    lus->push_back(lu);
+  }
+  if (topo_of_step) topo_of_step->assign(Tn + 1, 0);
+
+  std::vector<T> v(N, T(0)), i(B, T(0)), u(B, T(0)), h(B), e(B), x(N);
+  if (v0)
+    for (int a = 0; a < N; ++a) v[a] = T(v0[a]);
+  if (i0)
+    for (int b = 0; b < B; ++b) i[b] = ins[b] ? T(i0[b]) : T(0);
+  for (int b = 0; b < B; ++b) {
+    if (!ins[b]) continue;
+    T vk = net.k[b] >= 0 ? v[net.k[b]] : T(0);
+    T vm = net.m[b] >= 0 ? v[net.m[b]] : T(0);
+    u[b] = vk - vm - emf(net, b, 0, dt);
+  }
+  if (v_traj) std::copy(v.begin(), v.end(), v_traj);
+  if (i_traj) std::copy(i.begin(), i.end(), i_traj);
+  if (u_traj) std::copy(u.begin(), u.end(), u_traj);
+
+  // Events sorted by step (stable order within a step).
+  std::vector<int> ev(net.n_events);
+  for (int j = 0; j < net.n_events; ++j) ev[j] = j;
+  std::stable_sort(ev.begin(), ev.end(),
+                   [&](int a, int b) { return net.ev_step[a] < net.ev_step[b]; });
+  size_t next_ev = 0;
+  int topo = 0;
+
+  for (int64_t n = 1; n <= Tn; ++n) {
+    bool changed = false;
+    while (next_ev < ev.size() && net.ev_step[ev[next_ev]] == n) {
+      const int j = ev[next_ev++];
+      ins[net.ev_branch[j]] = net.ev_in_service[j] ? 1 : 0;
+      changed = true;
+    }
+    while (next_ev < ev.size() && net.ev_step[ev[next_ev]] < n) ++next_ev;
+    if (changed) {
+      companions(net, theta, dt, ins, c);
+      assemble(net, c, G);
+      if (!lu.factor(G, N)) return 2;
+      ++topo;
+      if (topos) topos->push_back(c);
+      if (lus) lus->push_back(lu);
+    }
+    if (topo_of_step) (*topo_of_step)[n] = topo;
+
+    for (int b = 0; b < B; ++b) {
+      h[b] = c.beta[b] * i[b] + c.gamma[b] * u[b];
+      e[b] = T(emf(net, b, n, dt));
+    }
+    std::fill(x.begin(), x.end(), T(0));
+    for (int b = 0; b < B; ++b) {
+      const T j = c.g[b] * e[b] - h[b];
+      if (net.k[b] >= 0) x[net.k[b]] += j;
+      if (net.m[b] >= 0) x[net.m[b]] -= j;
+    }
+    lu.solve(x);
+    v = x;
+    for (int b = 0; b < B; ++b) {
+      if (!ins[b]) {
+        u[b] = T(0);
+        i[b] = T(0);
+        continue;
+      }
+      T vk = net.k[b] >= 0 ? v[net.k[b]] : T(0);
+      T vm = net.m[b] >= 0 ? v[net.m[b]] : T(0);
+      u[b] = vk - vm - e[b];
+      i[b] = c.g[b] * u[b] + h[b];
+    }
+    if (rec)
+      for (int r = 0; r < net.n_rec; ++r) rec[(size_t)(n - 1) * net.n_rec + r] = v[rec_node(net, r)];
+    if (v_traj) std::copy(v.begin(), v.end(), v_traj + (size_t)n * N);
+    if (i_traj) std::copy(i.begin(), i.end(), i_traj + (size_t)n * B);
+    if (u_traj) std::copy(u.begin(), u.end(), u_traj + (size_t)n * B);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Forward run in double. rec: [T][n_rec]. Trajectories (nullable): [T+1][N]
+// node voltages, [T+1][B] branch currents and passive-branch voltages.
+int oracle_run(const OracleNet *net, const double *theta, double dt, int64_t T,
+               const double *v0, const double *i0, double *rec, double *v_traj,
+               double *i_traj, double *u_traj) {
+  return forward<double>(*net, theta, dt, T, v0, i0, rec, v_traj, i_traj, u_traj, nullptr,
+                         nullptr, nullptr);
+}
+
+// Complex-step loss: theta = theta_re + i*theta_im, J = sum_n sum_r
+// (v_{n,r} - target_{n,r})^2 evaluated in complex arithmetic.
+int oracle_loss_complex(const OracleNet *net, const double *theta_re, const double *theta_im,
+                        double dt, int64_t T, const double *target, double *J_re,
+                        double *J_im) {
+  std::vector<cplx> th(net->n_params);
+  for (int p = 0; p < net->n_params; ++p) th[p] = cplx(theta_re[p], theta_im[p]);
+  std::vector<cplx> rec((size_t)T * net->n_rec);
+  int st = forward<cplx>(*net, th.data(), dt, T, nullptr, nullptr, rec.data(), nullptr,
+                         nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (st) return st;
+  cplx J(0);
+  for (size_t q = 0; q < rec.size(); ++q) {
+    cplx d = rec[q] - target[q];
+    J += d * d;
+  }
+  *J_re = J.real();
+  *J_im = J.imag();
+  return 0;
+}
+
+// Vector-Jacobian product of the recorded waveform: given dJ/drec [T][n_rec],
+// returns dJ/dtheta [n_params] and (nullable) the per-branch adjoints of the
+// companion coefficients g, beta, gamma.
+int oracle_adjoint(const OracleNet *net, const double *theta, double dt, int64_t T,
+                   const double *dJ_drec, double *grad, double *gbar_out,
+                   double *betabar_out, double *gammabar_out) {
+  const int N = net->n_nodes, B = net->n_branches;
+  std::vector<double> i_traj((size_t)(T + 1) * B), u_traj((size_t)(T + 1) * B);
+  std::vector<int> topo_of_step;
+  std::vector<Companions<double>> topos;
+  std::vector<DenseLU<double>> lus;
+  int st = forward<double>(*net, theta, dt, T, nullptr, nullptr, nullptr, nullptr,
+                           i_traj.data(), u_traj.data(), &topo_of_step, &topos, &lus);
+  if (st) return st;
+
+  std::vector<double> gbar(B, 0), bbar(B, 0), cbar(B, 0);
+  std::vector<double> hbar_next(B, 0), beta_next(B, 0), gamma_next(B, 0);
+  std::vector<double> ibar(B), q(B), hbar(B), x(N);
+  for (int64_t n = T; n >= 1; --n) {
+    const Companions<double> &c = topos[topo_of_step[n]];
+    const DenseLU<double> &lu = lus[topo_of_step[n]];
+    for (int b = 0; b < B; ++b) {
+      const bool on = c.g[b] != 0.0;
+      ibar[b] = beta_next[b] * hbar_next[b];
+      q[b] = on ? gamma_next[b] * hbar_next[b] + c.g[b] * ibar[b] : 0.0;
+    }
+    std::fill(x.begin(), x.end(), 0.0);
+    for (int r = 0; r < net->n_rec; ++r) x[rec_node(*net, r)] += dJ_drec[(size_t)(n - 1) * net->n_rec + r];
+    for (int b = 0; b < B; ++b) {
+      if (net->k[b] >= 0) x[net->k[b]] += q[b];
+      if (net->m[b] >= 0) x[net->m[b]] -= q[b];
+    }
+    lu.solve_transposed(x);
+    const double *un = &u_traj[(size_t)n * B];
+    const double *up = &u_traj[(size_t)(n - 1) * B];
+    const double *ip = &i_traj[(size_t)(n - 1) * B];
+    for (int b = 0; b < B; ++b) {
+      const bool on = c.g[b] != 0.0;
+      double wk = net->k[b] >= 0 ? x[net->k[b]] : 0.0;
+      double wm = net->m[b] >= 0 ? x[net->m[b]] : 0.0;
+      hbar[b] = on ? ibar[b] - (wk - wm) : 0.0;
+      gbar[b] += hbar[b] * un[b];
+      bbar[b] += hbar[b] * ip[b];
+      cbar[b] += hbar[b] * up[b];
+      hbar_next[b] = hbar[b];
+      beta_next[b] = c.beta[b];
+      gamma_next[b] = c.gamma[b];
+    }
+  }
+
+  // Chain rule to the line parameters.
+  if (grad) {
+    std::fill(grad, grad + net->n_params, 0.0);
+    for (int b = 0; b < B; ++b) {
+      const int l = net->line[b];
+      if (l < 0) continue;
+      double R, L, C;
+      branch_values<double>(*net, theta, b, R, L, C);
+      if (net->kind[b] == K_RL) {
+        const double g0 = 1.0 / (R + 2.0 * L / dt);
+        const double g2 = g0 * g0;
+        grad[3 * l + 0] += (gbar[b] + cbar[b]) * (-g2) + bbar[b] * (-(4.0 * L / dt) * g2);
+        grad[3 * l + 1] += (gbar[b] + cbar[b]) * (-(2.0 / dt) * g2) + bbar[b] * ((4.0 * R / dt) * g2);
+      } else if (net->kind[b] == K_C) {
+        grad[3 * l + 2] += (gbar[b] - cbar[b]) / dt;
+      }
+    }
+  }
+  if (gbar_out) std::copy(gbar.begin(), gbar.end(), gbar_out);
+  if (betabar_out) std::copy(bbar.begin(), bbar.end(), betabar_out);
+  if (gammabar_out) std::copy(cbar.begin(), cbar.end(), gammabar_out);
+  return 0;
+}
+
+// Many independent scenarios, OpenMP over scenarios (the CPU baseline for
+// batched workloads). thetas: per-scenario pointers (entries may be null);
+// recs: per-scenario outputs [T][n_rec]. Returns the first nonzero status.
+int oracle_run_batch(const OracleNet *nets, int n_scen, const double *const *thetas,
+                     double dt, int64_t T, double *const *recs, int n_threads) {
+  int status = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : status)
+#endif
+  for (int s = 0; s < n_scen; ++s) {
+    int st = forward<double>(nets[s], thetas ? thetas[s] : nullptr, dt, T, nullptr, nullptr,
+                             recs[s], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    status = std::max(status, st);
+  }
+  return status;
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// Test hooks: the dense conductance matrix of a topology, and the LU solver.
+int oracle_assemble(const OracleNet *net, const double *theta, double dt,
+                    const uint8_t *in_service, double *G_out) {
+  std::vector<uint8_t> ins(in_service, in_service + net->n_branches);
+  Companions<double> c;
+  companions(*net, theta, dt, ins, c);
+  std::vector<double> G;
+  assemble(*net, c, G);
+  std::copy(G.begin(), G.end(), G_out);
+  return 0;
+}
+
+int oracle_companions(const OracleNet *net, const double *theta, double dt,
+                      const uint8_t *in_service, double *g, double *beta, double *gamma) {
+  std::vector<uint8_t> ins(in_service, in_service + net->n_branches);
+  Companions<double> c;
+  companions(*net, theta, dt, ins, c);
+  std::copy(c.g.begin(), c.g.end(), g);
+  std::copy(c.beta.begin(), c.beta.end(), beta);
+  std::copy(c.gamma.begin(), c.gamma.end(), gamma);
+  return 0;
+}
+
+int oracle_lu_solve(int n, const double *G, const double *b, double *x, int transposed) {
+  DenseLU<double> lu;
+  std::vector<double> Gv(G, G + (size_t)n * n);
+  if (!lu.factor(Gv, n)) return 2;
+  std::vector<double> xv(b, b + n);
+  if (transposed)
+    lu.solve_transposed(xv);
+  else
+    lu.solve(xv);
+  std::copy(xv.begin(), xv.end(), x);
+  return 0;
+}
+
+}  // extern "C"

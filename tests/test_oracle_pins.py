@@ -1,0 +1,474 @@
+"""Pins of the CPU oracle against things other than itself.
+
+The paper prints no waveform, circuit data or worked example, so every pin
+here comes from mathematics: discrete and continuous closed forms, exact
+invariants of the trapezoidal rule, an independent state-space formulation,
+matrix-exponential solutions, library special cases, linearity, and
+derivative identities (complex step, finite differences).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_1903_01081_amd import netgen
+from paper_1903_01081_amd.netgen import CAP, RES, RL, SRC, SWITCH
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b| (the relative error used throughout)."""
+    scale = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (scale if scale > 0 else 1.0)
+
+
+# ---------------------------------------------------------------------------
+# P1: R-L step response (DC source into a resistor).
+# ---------------------------------------------------------------------------
+
+def _rl_step_net(E, Rs, Ls, Rl):
+    return netgen.circuit(1, [
+        dict(k=0, m=-1, kind=SRC, R=Rs, L=Ls, E=E, omega=0.0, phase=0.0),
+        dict(k=0, m=-1, kind=RES, R=Rl),
+    ])
+
+
+def test_rl_step_discrete_closed_form(oracle_mod):
+    E, Rs, Ls, Rl = 2.0, 0.5, 10e-3, 7.5
+    Rt = Rs + Rl
+    dt, T = 50e-6, 3000
+    net = _rl_step_net(E, Rs, Ls, Rl)
+    rec, v, i, u = oracle_mod.run(net, dt, T, trajectories=True)
+    a = dt * Rt / (2 * Ls)
+    rho = (1 - a) / (1 + a)
+    n = np.arange(T + 1)
+    i_exact = -(E / Rt) * (1 - rho ** n)       # source-branch current, node -> ground
+    assert rel_err(i[:, 0], i_exact) < 1e-13
+    v_exact = -Rl * i_exact                    # resistor carries the opposite current
+    assert rel_err(v[1:, 0], v_exact[1:]) < 1e-13
+
+
+def test_rl_step_continuous_second_order(oracle_mod):
+    E, Rs, Ls, Rl = 1.0, 0.5, 10e-3, 4.5
+    Rt, tau = Rs + Rl, 10e-3 / 5.0
+    errs = []
+    for dt in (tau / 40, tau / 80, tau / 160):
+        T = int(round(5 * tau / dt))
+        net = _rl_step_net(E, Rs, Ls, Rl)
+        _, _, i, _ = oracle_mod.run(net, dt, T, trajectories=True)
+        t = np.arange(T + 1) * dt
+        i_c = -(E / Rt) * (1 - np.exp(-t * Rt / Ls))
+        errs.append(np.max(np.abs(i[:, 0] - i_c)) / (E / Rt))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.8 < r1 < 4.2 and 3.8 < r2 < 4.2, errs
+    assert errs[1] < 2e-4
+
+
+# ---------------------------------------------------------------------------
+# P2: series R-L-C ringing (DC source charging a capacitor).
+# ---------------------------------------------------------------------------
+
+def _rlc(E, R, L, C):
+    return netgen.circuit(1, [
+        dict(k=0, m=-1, kind=SRC, R=R, L=L, E=E, omega=0.0, phase=0.0),
+        dict(k=0, m=-1, kind=CAP, C=C),
+    ])
+
+
+def _rlc_modes(E, R, L, C):
+    # x = [v_C, j] with j the current into the node; eigenvalues of the
+    # continuous system and eigenvectors r = [1, lambda C].
+    alpha = R / (2 * L)
+    wd = math.sqrt(1 / (L * C) - alpha ** 2)
+    lp, lm = complex(-alpha, wd), complex(-alpha, -wd)
+    cp = -E * lm / (lm - lp)
+    cm = E * lp / (lm - lp)
+    return lp, lm, cp, cm
+
+
+def test_rlc_discrete_closed_form(oracle_mod):
+    E, R, L, C = 1.0, 2.0, 10e-3, 20e-6
+    dt, T = 20e-6, 6000
+    net = _rlc(E, R, L, C)
+    rec = oracle_mod.run(net, dt, T)
+    lp, lm, cp, cm = _rlc_modes(E, R, L, C)
+    zp = (1 + lp * dt / 2) / (1 - lp * dt / 2)
+    zm = (1 + lm * dt / 2) / (1 - lm * dt / 2)
+    n = np.arange(1, T + 1)
+    v_exact = (E + cp * zp ** n + cm * zm ** n).real
+    assert rel_err(rec[:, 0], v_exact) < 1e-12
+
+
+def test_rlc_continuous_second_order(oracle_mod):
+    E, R, L, C = 1.0, 2.0, 10e-3, 20e-6
+    lp, lm, cp, cm = _rlc_modes(E, R, L, C)
+    errs = []
+    t_end = 4e-3
+    for dt in (40e-6, 20e-6, 10e-6):
+        T = int(round(t_end / dt))
+        rec = oracle_mod.run(_rlc(E, R, L, C), dt, T)
+        t = np.arange(1, T + 1) * dt
+        v_c = (E + cp * np.exp(lp * t) + cm * np.exp(lm * t)).real
+        errs.append(np.max(np.abs(rec[:, 0] - v_c)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.7 < r1 < 4.3 and 3.7 < r2 < 4.3, errs
+
+
+# ---------------------------------------------------------------------------
+# P3: lossless L-C tank conserves energy under the trapezoidal rule.
+# ---------------------------------------------------------------------------
+
+def test_lc_tank_energy_conserved(oracle_mod):
+    L, C, V0 = 5e-3, 30e-6, 1.3
+    dt, T = 50e-6, 4000
+    net = netgen.circuit(1, [dict(k=0, m=-1, kind=CAP, C=C),
+                             dict(k=0, m=-1, kind=RL, R=0.0, L=L)])
+    _, v, i, u = oracle_mod.run(net, dt, T, v0=[V0], i0=[0.0, 0.0], trajectories=True)
+    energy = 0.5 * C * v[:, 0] ** 2 + 0.5 * L * i[:, 1] ** 2
+    drift = np.max(np.abs(energy - energy[0])) / energy[0]
+    assert drift < 1e-12
+    # and it really oscillates at the discrete frequency
+    assert np.min(v[:, 0]) < -0.9 * V0
+
+
+# ---------------------------------------------------------------------------
+# P4 / P5: per-branch trapezoidal energy balance, Tellegen, KCL — on full
+# grids, with events. Together with the initial state these relations
+# determine the trajectory, so they check every step of the oracle.
+# ---------------------------------------------------------------------------
+
+def _emf_test_side(net, t):
+    e = np.zeros((t.shape[0], net.n_branches))
+    s = net.kind == SRC
+    e[:, s] = net.E[s] * np.cos(np.outer(t, net.omega[s]) + net.phase[s])
+    return e
+
+
+def _in_service_per_step(net, T):
+    ins = np.repeat(net.in_service0[None, :].astype(bool), T + 1, axis=0)
+    for st, b, on in zip(net.ev_step, net.ev_branch, net.ev_in_service):
+        if st <= T:
+            ins[st:, b] = bool(on)
+    return ins
+
+
+def _incidence(net):
+    A = np.zeros((net.n_nodes, net.n_branches))
+    for b in range(net.n_branches):
+        if net.k[b] >= 0:
+            A[net.k[b], b] += 1
+        if net.m[b] >= 0:
+            A[net.m[b], b] -= 1
+    return A
+
+
+def _check_balance(net, dt, T, v, i, tol=1e-12):
+    A = _incidence(net)
+    t = np.arange(T + 1) * dt
+    e = _emf_test_side(net, t)
+    ins = _in_service_per_step(net, T)
+    vb = v @ A                              # branch terminal voltage a_b^T v
+    u = np.where(ins, vb - e, 0.0)          # passive-part voltage
+    ia, ua = 0.5 * (i[1:] + i[:-1]), 0.5 * (u[1:] + u[:-1])
+    both = ins[1:] & ins[:-1]
+    # inductive branches: L/2 (i_n^2 - i_{n-1}^2) = dt (u_avg i_avg - R i_avg^2)
+    ind = (net.kind == RL) | (net.kind == SRC)
+    lhs = 0.5 * net.L * (i[1:] ** 2 - i[:-1] ** 2)
+    rhs = dt * (ua * ia - net.R * ia ** 2)
+    scale = np.max(np.abs(dt * ua * ia)[:, ind])
+    bad = np.abs(lhs - rhs)[:, ind][both[:, ind]]
+    assert bad.max() / scale < tol, ("inductive balance", bad.max() / scale)
+    cap = net.kind == CAP
+    if cap.any():
+        lhs = 0.5 * net.C * (u[1:] ** 2 - u[:-1] ** 2)
+        rhs = dt * ua * ia
+        scale = np.max(np.abs(rhs[:, cap]))
+        bad = np.abs(lhs - rhs)[:, cap][both[:, cap]]
+        assert bad.max() / scale < tol, ("capacitive balance", bad.max() / scale)
+    res = (net.kind == RES) | (net.kind == SWITCH)
+    if res.any():
+        on = ins[1:, res]
+        err = np.abs(i[1:, res] - u[1:, res] / net.R[res])[on]
+        if err.size:
+            assert err.max() / max(np.abs(i[1:, res]).max(), 1e-300) < tol
+    # Tellegen with two-point averages
+    tel = np.sum(0.5 * (vb[1:] + vb[:-1]) * ia, axis=1)
+    tel_scale = np.sum(np.abs(0.5 * (vb[1:] + vb[:-1]) * ia), axis=1)
+    assert np.max(np.abs(tel) / np.maximum(tel_scale, 1e-300)) < tol
+    # KCL at every node and step, relative to the node's peak incident current
+    # magnitude over the run (near a zero crossing the currents at a node are
+    # tiny differences of O(peak) terms, so a per-step scale would measure
+    # rounding of those terms, not a KCL violation)
+    kcl = i @ A.T
+    kcl_scale = np.max(np.abs(i) @ np.abs(A.T), axis=0)
+    ratio = np.abs(kcl) / np.where(kcl_scale > 0, kcl_scale, 1.0)
+    assert ratio.max() < tol, ("KCL", ratio.max())
+
+
+def test_config0_balance_and_kcl(oracle_mod):
+    nets, sim = netgen.config0()
+    net = nets[0]
+    _, v, i, u = oracle_mod.run(net, sim["dt"], sim["n_steps"], trajectories=True)
+    _check_balance(net, sim["dt"], sim["n_steps"], v, i)
+
+
+def test_grid_with_removal_balance_and_kcl(oracle_mod):
+    net = netgen.small_grid(11, 12, fault_step=150, remove_series=7, remove_step=150, n_mon=10)
+    dt, T = 20e-6, 400
+    _, v, i, u = oracle_mod.run(net, dt, T, trajectories=True)
+    _check_balance(net, dt, T, v, i)
+    # the removed branch carries nothing afterwards, the fault switches do
+    rb = int(net.ev_branch[net.ev_in_service == 0][0])
+    assert np.all(i[150:, rb] == 0.0)
+    sw = net.ev_branch[net.ev_in_service == 1]
+    assert np.all(i[:150, sw] == 0.0) and np.abs(i[150:, sw]).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# P7: an independent state-space trapezoidal formulation (x = [node
+# voltages; inductive branch currents]) must give the same trajectory.
+# ---------------------------------------------------------------------------
+
+def _state_space_run(net, dt, T):
+    N, B = net.n_nodes, net.n_branches
+    A = _incidence(net)
+    ind = np.where((net.kind == RL) | (net.kind == SRC))[0]
+    cap = np.where(net.kind == CAP)[0]
+    res = np.where((net.kind == RES) | (net.kind == SWITCH))[0]
+    Cm = A[:, cap] @ np.diag(net.C[cap]) @ A[:, cap].T
+    Cinv = np.linalg.inv(Cm)
+    nL = ind.size
+    ins_all = _in_service_per_step(net, T)
+
+    def system(ins):
+        on_L = ins[ind].astype(float)
+        Gr = A[:, res] @ np.diag(np.where(ins[res], 1.0 / net.R[res], 0.0)) @ A[:, res].T
+        M = np.zeros((N + nL, N + nL))
+        M[:N, :N] = -Cinv @ Gr
+        M[:N, N:] = -Cinv @ (A[:, ind] * on_L)
+        M[N:, :N] = (A[:, ind].T / net.L[ind][:, None]) * on_L[:, None]
+        M[N:, N:] = -np.diag(net.R[ind] / net.L[ind] * on_L)
+        return M, on_L
+
+    def forcing(t, on_L):
+        f = np.zeros(N + nL)
+        e = _emf_test_side(net, np.array([t]))[0]
+        f[N:] = -e[ind] / net.L[ind] * on_L
+        return f
+
+    x = np.zeros(N + nL)
+    out = np.zeros((T + 1, N))
+    M_prev, on_prev = system(ins_all[0])
+    I = np.eye(N + nL)
+    for n in range(1, T + 1):
+        M, on_L = system(ins_all[n])
+        keep = np.concatenate([np.ones(N, bool), on_L > 0])
+        rhs = x + 0.5 * dt * (M_prev @ x + forcing((n - 1) * dt, on_prev) + forcing(n * dt, on_L))
+        K = I - 0.5 * dt * M
+        xn = np.zeros_like(x)
+        xn[keep] = np.linalg.solve(K[np.ix_(keep, keep)], rhs[keep])
+        x = xn
+        out[n] = x[:N]
+        M_prev, on_prev = M, on_L
+    return out
+
+
+def test_state_space_matches_config0(oracle_mod):
+    nets, sim = netgen.config0()
+    net = nets[0]
+    T = 2400   # spans the fault at step 2000
+    rec = oracle_mod.run(net, sim["dt"], T)
+    ss = _state_space_run(net, sim["dt"], T)
+    assert rel_err(rec, ss[1:]) < 1e-11
+
+
+def test_state_space_matches_n1_grid(oracle_mod):
+    net = netgen.small_grid(5, 8, fault_step=60, remove_series=4, remove_step=60)
+    dt, T = 20e-6, 200
+    rec = oracle_mod.run(net, dt, T)
+    ss = _state_space_run(net, dt, T)
+    assert rel_err(rec, ss[1:]) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# P6: matrix exponential (exact continuous solution) on a tiny grid with
+# sinusoidal forcing, via an augmented rotation state; order-2 convergence.
+# ---------------------------------------------------------------------------
+
+def test_expm_exact_solution_second_order(oracle_mod):
+    net = netgen.small_grid(21, 3, n_lines=3, n_gen=1, n_load=1)
+    N = net.n_nodes
+    ind = np.where((net.kind == RL) | (net.kind == SRC))[0]
+    cap = np.where(net.kind == CAP)[0]
+    A = _incidence(net)
+    Cinv = np.linalg.inv(A[:, cap] @ np.diag(net.C[cap]) @ A[:, cap].T)
+    nL = ind.size
+    M = np.zeros((N + nL, N + nL))
+    M[:N, N:] = -Cinv @ A[:, ind]
+    M[N:, :N] = A[:, ind].T / net.L[ind][:, None]
+    M[N:, N:] = -np.diag(net.R[ind] / net.L[ind])
+    # e_b(t) = E cos(w t + p) = E cos p * c(t) - E sin p * s(t); c' = -w s, s' = w c
+    w = net.omega[net.kind == SRC][0]
+    Maug = np.zeros((N + nL + 2, N + nL + 2))
+    Maug[:N + nL, :N + nL] = M
+    src = net.kind[ind] == SRC
+    Eb, pb = net.E[ind], net.phase[ind]
+    Maug[N:N + nL, N + nL] = np.where(src, -Eb * np.cos(pb) / net.L[ind], 0)
+    Maug[N:N + nL, N + nL + 1] = np.where(src, Eb * np.sin(pb) / net.L[ind], 0)
+    Maug[N + nL, N + nL + 1] = -w
+    Maug[N + nL + 1, N + nL] = w
+    z0 = np.zeros(N + nL + 2)
+    z0[N + nL] = 1.0
+    # the grid's fastest line modes ring at ~1e4-1e5 rad/s: resolve them
+    t_end = 2e-3
+    errs = []
+    for dt in (2e-6, 1e-6, 0.5e-6):
+        T = int(round(t_end / dt))
+        rec = oracle_mod.run(net, dt, T)
+        stride = T // 40
+        idx = np.arange(stride, T + 1, stride)
+        exact = np.array([(scipy.linalg.expm(Maug * (n * dt)) @ z0)[:N] for n in idx])
+        errs.append(np.max(np.abs(rec[idx - 1] - exact)) / np.max(np.abs(exact)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+    assert errs[0] < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# P8: library special cases: the conductance matrix is SPD (Cholesky works)
+# and the oracle's LU solves agree with numpy's.
+# ---------------------------------------------------------------------------
+
+def test_conductance_spd_and_lu_vs_numpy(oracle_mod):
+    nets, sim = netgen.config0()
+    net = nets[0]
+    rng = np.random.default_rng(7)
+    for ins in (net.in_service0, np.ones(net.n_branches, np.uint8)):
+        G = oracle_mod.assemble(net, sim["dt"], ins)
+        assert np.allclose(G, G.T, rtol=0, atol=0)
+        np.linalg.cholesky(G)
+        b = rng.standard_normal(net.n_nodes)
+        x = oracle_mod.lu_solve(G, b)
+        assert rel_err(x, np.linalg.solve(G, b)) < 1e-14
+        xt = oracle_mod.lu_solve(G, b, transposed=True)
+        assert rel_err(xt, np.linalg.solve(G.T, b)) < 1e-14
+    # a nonsymmetric matrix exercises pivoting and the transposed solve
+    M = rng.standard_normal((9, 9))
+    b = rng.standard_normal(9)
+    assert rel_err(oracle_mod.lu_solve(M, b), np.linalg.solve(M, b)) < 1e-12
+    assert rel_err(oracle_mod.lu_solve(M, b, transposed=True), np.linalg.solve(M.T, b)) < 1e-12
+
+
+def test_singular_network_reported(oracle_mod):
+    # nodes 1 and 2 form an island with no conductive path to ground
+    net = netgen.circuit(3, [dict(k=0, m=-1, kind=CAP, C=1e-6),
+                             dict(k=1, m=2, kind=RL, R=1.0, L=1e-3)])
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle_mod.run(net, 50e-6, 10)
+
+
+# ---------------------------------------------------------------------------
+# P9: linearity, superposition and the balanced-three-phase invariant.
+# ---------------------------------------------------------------------------
+
+def test_linearity_and_superposition(oracle_mod):
+    nets, sim = netgen.config0()
+    net = nets[0]
+    dt, T = sim["dt"], 2500
+    base = oracle_mod.run(net, dt, T)
+    scaled = netgen.Network(**{**net.__dict__, "E": 2.5 * net.E})
+    assert rel_err(oracle_mod.run(scaled, dt, T), 2.5 * base) < 1e-13
+    src = np.where(net.kind == SRC)[0]
+    half = np.zeros_like(net.E)
+    half[src[:3]] = net.E[src[:3]]
+    rest = net.E - half
+    a = oracle_mod.run(netgen.Network(**{**net.__dict__, "E": half}), dt, T)
+    b = oracle_mod.run(netgen.Network(**{**net.__dict__, "E": rest}), dt, T)
+    assert rel_err(a + b, base) < 1e-13
+
+
+def test_zero_sequence_vanishes(oracle_mod):
+    # identical uncoupled phases fed by balanced sources: at every bus the
+    # three phase voltages sum to zero (the fault is symmetric too)
+    nets, sim = netgen.config0()
+    rec = oracle_mod.run(nets[0], sim["dt"], sim["n_steps"])
+    zs = rec.reshape(rec.shape[0], -1, 3).sum(axis=2)
+    assert np.max(np.abs(zs)) / np.max(np.abs(rec)) < 1e-12
+
+
+def test_batch_equals_single(oracle_mod):
+    nets, sim = netgen.config2(n_bus=10, n_scen=6, n_steps=300, event_step=120)
+    recs = oracle_mod.run_batch(nets, sim["dt"], sim["n_steps"], n_threads=3)
+    for net, r in zip(nets, recs):
+        assert np.array_equal(r, oracle_mod.run(net, sim["dt"], sim["n_steps"]))
+
+
+# ---------------------------------------------------------------------------
+# P10: the discrete adjoint against complex-step and central differences.
+# ---------------------------------------------------------------------------
+
+def _target(oracle_mod, net, dt, T, seed):
+    rng = np.random.default_rng(seed)
+    th_true = netgen.perturbed_theta(rng, net.theta0())
+    return oracle_mod.run(net, dt, T, theta=th_true)
+
+
+@pytest.mark.parametrize("events", [False, True])
+def test_adjoint_vs_complex_step(oracle_mod, events):
+    if events:
+        net = netgen.small_grid(31, 6, fault_step=120, remove_series=5, remove_step=180, n_mon=8)
+    else:
+        net = netgen.small_grid(32, 6, n_mon=8)
+    dt, T = 50e-6, 300
+    th0 = net.theta0()
+    target = _target(oracle_mod, net, dt, T, 5)
+    v = oracle_mod.run(net, dt, T, theta=th0)
+    grad = oracle_mod.adjoint(net, dt, T, 2.0 * (v - target), theta=th0)
+    h = 1e-30
+    cs = np.empty_like(grad)
+    for p in range(th0.size):
+        im = np.zeros_like(th0)
+        im[p] = h * th0[p]
+        J = oracle_mod.loss_complex(net, dt, T, th0, im, target)
+        cs[p] = J.imag / (h * th0[p])
+    floor = 1e-12 * np.max(np.abs(th0 * cs))
+    err = np.abs(th0 * (grad - cs)) / np.maximum(np.abs(th0 * cs), floor)
+    assert err.max() < 1e-10, err.max()
+
+
+def test_adjoint_vs_central_differences(oracle_mod):
+    net = netgen.small_grid(33, 8, fault_step=150, n_mon=10)
+    dt, T = 50e-6, 300
+    th0 = net.theta0()
+    target = _target(oracle_mod, net, dt, T, 6)
+
+    def J(th):
+        return float(np.sum((oracle_mod.run(net, dt, T, theta=th) - target) ** 2))
+
+    v = oracle_mod.run(net, dt, T, theta=th0)
+    grad = oracle_mod.adjoint(net, dt, T, 2.0 * (v - target), theta=th0)
+    rng = np.random.default_rng(9)
+    idx = rng.choice(th0.size, size=12, replace=False)
+    fd = np.empty(idx.size)
+    for q, p in enumerate(idx):
+        hp = 1e-6 * th0[p]
+        tp, tm = th0.copy(), th0.copy()
+        tp[p] += hp
+        tm[p] -= hp
+        fd[q] = (J(tp) - J(tm)) / (2 * hp)
+    scale = np.max(np.abs(th0[idx] * fd))
+    assert np.max(np.abs(th0[idx] * (grad[idx] - fd))) <= 1e-6 * scale
+
+
+def test_adjoint_vjp_linear_in_cotangent(oracle_mod):
+    net = netgen.small_grid(34, 5, fault_step=40, n_mon=6)
+    dt, T = 50e-6, 120
+    rng = np.random.default_rng(1)
+    d1 = rng.standard_normal((T, net.n_rec))
+    d2 = rng.standard_normal((T, net.n_rec))
+    g1 = oracle_mod.adjoint(net, dt, T, d1)
+    g2 = oracle_mod.adjoint(net, dt, T, d2)
+    g12 = oracle_mod.adjoint(net, dt, T, 3 * d1 - d2)
+    assert rel_err(g12, 3 * g1 - g2) < 1e-12
