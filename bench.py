@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the EMT nodal-analysis time loop on one MI355X.
+
+One bench step = one full simulation of the workload: emt_factor (every
+topology) + emt_step over the whole horizon, recording the outputs, with the
+inputs already resident on the device. Default workload: a 1000-bus
+three-phase grid (3000 nodes, 15,903 branches), 50,000 steps at 20 us, one
+three-phase fault at step 25,000, every node recorded.
+
+value = node-steps/s = nodes * steps * K / (timed seconds for K bench steps).
+
+Prints one JSON line. Secondary figures (batched N-1, adjoint/forward ratio,
+uneven batched gradients) ride along as extra keys unless --no-extras.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-steps/s (plain vs batched N-1) and adjoint/forward time ratio, FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_step(info, n_rec_total):
+    """Bytes one time step touches if nothing stayed on chip: branch
+    coefficients, terminals and state (g, beta, gamma, k, m, i, u read;
+    i, u written: 64 B per branch), the L factor read twice with its index
+    (24 B per strictly-lower nonzero), D^-1 (8 B per node) and the recorded
+    outputs (8 B each)."""
+    return (64 * info["total_branches"] + 24 * info["nnz_L"] + 8 * info["total_nodes"]
+            + 8 * n_rec_total)
+
+
+def time_simulation(torch, sim, rec, steps, warmup):
+    """Warmup, then `steps` full runs (reset + factor + all steps). Returns
+    (wall seconds, forward-kernel seconds per run from HIP events on the
+    launch stream)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        sim.reset()
+        sim.factor()
+        sim.step(sim.n_steps, rec=rec)
+        torch.cuda.synchronize()
+        log(f"  warmup run done")
+    evs = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.reset()
+        sim.factor()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(sim.n_steps, rec=rec)
+        b.record(stream)
+        evs.append((a, b))
+        if k == 0:
+            torch.cuda.synchronize()
+            log(f"  first timed run: {a.elapsed_time(b) / 1e3:.3f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    return wall, kern
+
+
+def cpu_baseline_config1(nets, cfg):
+    """The oracle (dense LU, one thread) on a bounded sample of the workload:
+    two short runs (50 and 250 steps) give the factorisation and per-step
+    costs, extrapolated to the full horizon with its two factorisations."""
+    from oracle import oracle as O
+    net = nets[0]
+    dt = cfg["dt"]
+    t0 = time.perf_counter()
+    O.run(net, dt, 50)
+    t50 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.run(net, dt, 250)
+    t250 = time.perf_counter() - t0
+    per_step = max((t250 - t50) / 200.0, 1e-12)
+    factor = max(t50 - 50 * per_step, 0.0)
+    T = cfg["n_steps"]
+    total = 2 * factor + T * per_step
+    return {"value": net.n_nodes * T / total, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle runs of 50 and 250 steps of the same 3000-node grid "
+                      f"({t50 + t250:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
+                      f"factorisation {factor:.2f} s extrapolated to 50,000 steps and 2 factorisations"}
+
+
+def extras(torch, args):
+    """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
+    uneven batched gradients; each measured once after a warmup."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator, theta_matrix
+    out = {}
+    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps.
+    nets, cfg = netgen.config2()
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    wall, kern = time_simulation(torch, sim, rec, 1, 1)
+    N = nets[0].n_nodes
+    batched = len(nets) * N * cfg["n_steps"] / wall
+    # plain per-scenario loop: a sample of scenarios run one at a time
+    n_plain = 8
+    plain_t = []
+    for s in range(n_plain):
+        one = Simulator([nets[s]], cfg["dt"], cfg["n_steps"])
+        r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
+        w1, _ = time_simulation(torch, one, r1, 1, 1 if s == 0 else 0)
+        plain_t.append(w1)
+        one.close()
+    plain = N * cfg["n_steps"] / float(np.mean(plain_t))
+    out["batched_n1"] = {"workload": "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us",
+                         "value": batched, "unit": "node-steps/s", "seconds": wall,
+                         "plain_loop_value": plain, "plain_loop_sample": f"{n_plain} scenarios run one at a time",
+                         "speedup_vs_plain_loop": batched / plain}
+    sim.close()
+    del rec
+    # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500.
+    nets, cfg = netgen.config3()
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    cot = torch.randn((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    for _ in range(2):
+        sim.reset()
+        sim.factor()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(sim.n_steps, rec=rec)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sim.adjoint(cot)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+    out["adjoint"] = {"workload": "grid100: 300 nodes, 10,000 steps at 50 us, 450 parameters, checkpoint every 500",
+                      "forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_over_forward": t_adj / t_fwd}
+    sim.close()
+    # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint.
+    nets, cfg = netgen.config4()
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+    theta = theta_matrix(nets, device=sim.device)
+    rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    cot = torch.randn_like(rec)
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.set_params(theta)
+        sim.factor()
+        sim.step(sim.n_steps, rec=rec)
+        sim.adjoint(cot)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+    n_loop = 8
+    loop_t = []
+    for j in range(n_loop):
+        one = Simulator([nets[j]], cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+        th1 = theta_matrix([nets[j]], device=one.device)
+        r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
+        c1 = torch.randn_like(r1)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one.set_params(th1)
+            one.factor()
+            one.step(one.n_steps, rec=r1)
+            one.adjoint(c1)
+            torch.cuda.synchronize()
+            tj = time.perf_counter() - t0
+        loop_t.append(tj)
+        one.close()
+    out["uneven_gradients"] = {"workload": "256 grids of 90-900 nodes, 5000 steps at 50 us, forward + adjoint",
+                               "gradients_per_s": len(nets) / t_b, "seconds": t_b,
+                               "per_instance_loop_gradients_per_s": 1.0 / float(np.mean(loop_t)),
+                               "loop_sample": f"{n_loop} instances run one at a time"}
+    sim.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the EMT time loop runs each scenario on one device "
+              "and this build has no multi-GPU path (scenarios would shard across GPUs with "
+              "no exchange during the loop). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator
+
+    nets, cfg = netgen.config1()
+    net = nets[0]
+    t0 = time.perf_counter()
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    build_s = time.perf_counter() - t0
+    info = sim.info()
+    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    log(f"built grid1000 in {build_s:.2f} s: {info}")
+    wall, kern = time_simulation(torch, sim, rec, args.steps, args.warmup)
+    N, T = net.n_nodes, cfg["n_steps"]
+    value = N * T * args.steps / wall
+    per_step_bytes = algorithmic_bytes_per_step(info, net.n_rec)
+    achieved = per_step_bytes * T / kern / 1e9
+    line = {
+        "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "grid1000: 1000-bus three-phase grid, 3000 nodes, 15903 branches, "
+                               "50000 steps at 20 us, three-phase fault at step 25000, all nodes recorded",
+                   "nodes": N, "branches": int(net.n_branches), "time_steps": T,
+                   "bench_step": "emt_factor + emt_step over the whole horizon"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_forward", "kernel_s": kern,
+                     "algorithmic_bytes_per_time_step": per_step_bytes},
+        "latency": {"us_per_time_step": kern / T * 1e6,
+                    "sweep_levels": info["max_levels"], "block_size": info["block_size"]},
+        "build_s": build_s,
+    }
+    sim.close()
+    del rec
+    if not args.no_extras:
+        line.update(extras(torch, args))
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_config1(nets, cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

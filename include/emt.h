@@ -1,0 +1,208 @@
+/*
+ * emt.h — C ABI of the MI355X EMT nodal-analysis time loop (FP64).
+ *
+ * The library runs the fixed-step nodal-analysis loop of an EMTP-type
+ * simulator: the paper (Sec. III-A) splits each step into four basic
+ * processes — update each component's Norton equivalent (history current and
+ * conductance), update the nodal injected currents, factorise the nodal
+ * conductance matrix, and forward/back substitute for the node voltages —
+ * and (Sec. III-B) runs many scenarios of one topology as one vectorised
+ * computation. The companion models are the trapezoidal-rule ones of the
+ * EMTP method (the paper's reference [2]):
+ *
+ *   series R-L (also a source's internal impedance):
+ *       g = 1/(R + 2L/dt), beta = (2L/dt - R) g, gamma = g
+ *   capacitor:                 g = 2C/dt, beta = -1, gamma = -g
+ *   resistor / closed switch:  g = 1/R,   beta = gamma = 0
+ *   out of service:            g = beta = gamma = 0 and u = i = 0
+ *
+ *   step n (t_n = n dt):  h = beta*i + gamma*u           (history, n-1 state)
+ *                         e = E cos(omega t_n + phase)    (source branches)
+ *                         rhs = A (g*e - h)               (nodal injection)
+ *                         v = G^{-1} rhs,  G = A diag(g) A^T
+ *                         u = A^T v - e,   i = g*u + h    (branch update)
+ *
+ * A is the node-by-branch incidence (+1 at k, -1 at m; ground = -1 is
+ * dropped), u is the voltage across a branch's passive part, i flows k -> m.
+ * The initial state is v = 0, i = 0, u = A^T v - e(0). Switching events
+ * apply at a step index: the new topology produces v at that step. The
+ * conductance matrix is factorised once per topology (LDL^T on a symbolic
+ * pattern shared by all topologies and by isomorphic scenarios); no
+ * factorisation happens inside the time loop.
+ *
+ * Conventions: FP64 values, int32 indices, node ids 0..n_nodes-1, ground -1,
+ * row-major arrays. Host arrays passed to a call are borrowed for that call
+ * only and copied. Device buffers (`*_dev`) belong to the caller, must be
+ * device memory of the current HIP device, and must stay valid until the
+ * work queued on `stream` has finished. `stream` is a hipStream_t (NULL =
+ * the default stream). Calls are stream-ordered; a context is not
+ * thread-safe. Every call returns a status; on a non-OK status nothing was
+ * queued and emt_last_error() describes the cause. No C++ exception crosses
+ * this interface.
+ */
+#ifndef EMT_H
+#define EMT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct emt_ctx emt_ctx;
+
+typedef enum {
+  EMT_OK = 0,
+  EMT_EINVAL = 1,     /* bad argument: sizes, indices, NaN or non-positive parameters */
+  EMT_ESINGULAR = 2,  /* a node has no conductive path to ground, or a non-positive pivot */
+  EMT_ENOMEM = 3,     /* host or device allocation failed */
+  EMT_EDEVICE = 4,    /* HIP runtime error or no device */
+  EMT_ESTATE = 5      /* call out of order (see each call) */
+} emt_status;
+
+typedef enum { EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4 } emt_kind;
+
+typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 } emt_solver;
+
+/* One network (scenario): a branch list, its switching events and outputs.
+ * Per-branch arrays have n_branches entries.
+ *   k, m       terminals (-1 = ground; not both -1), kind = emt_kind.
+ *   R, L, C    RL: R >= 0, L > 0 (source: internal R, L); C: C > 0;
+ *              R and SWITCH: R > 0 (SWITCH: closed resistance).
+ *   E, omega, phase  source EMF E cos(omega t + phase); read for EMT_SRC only.
+ *   line       pi-section line index l of the branch, or -1. Line parameters
+ *              theta[3l + {0,1,2}] = (R_l, L_l, C_l) are the series R and L
+ *              of each EMT_RL branch of line l and twice the capacitance of
+ *              each EMT_C branch of line l (C_l / 2 at each end).
+ *   n_params   3 * number of lines (0 if none).
+ *   in_service0  state at t = 0 (1 = in service / switch closed); NULL means
+ *              every branch in service except switches, which start open.
+ *   events     at step ev_step[j] (1 <= ev_step <= n_steps; later ones are
+ *              ignored) branch ev_branch[j] goes in service
+ *              (ev_in_service[j] = 1) or out (0).
+ *   rec_nodes  the n_rec recorded nodes (NULL = all nodes, n_rec = n_nodes).
+ */
+typedef struct {
+  int32_t n_nodes, n_branches;
+  const int32_t *k, *m, *kind;
+  const double *R, *L, *C;
+  const double *E, *omega, *phase;
+  const int32_t *line;
+  int32_t n_params;
+  const uint8_t *in_service0;
+  int32_t n_events;
+  const int64_t *ev_step;
+  const int32_t *ev_branch;
+  const uint8_t *ev_in_service;
+  int32_t n_rec;
+  const int32_t *rec_nodes;
+} emt_net;
+
+/* Simulation settings shared by all scenarios of a context.
+ *   dt > 0, n_steps >= 1 (the horizon T).
+ *   checkpoint_every K: 0 = no checkpoints (emt_adjoint unavailable); else
+ *     the forward run stores the branch state every K steps and the adjoint
+ *     recomputes each K-step segment from its checkpoint.
+ *   solver: EMT_SOLVER_* (AUTO picks per connected component). */
+typedef struct {
+  double dt;
+  int64_t n_steps;
+  int32_t checkpoint_every;
+  int32_t solver;
+} emt_sim;
+
+/* Sizes of a built context (emt_info) or of a host-only analysis. */
+typedef struct {
+  int32_t n_scen;
+  int32_t rec_stride;    /* R = max over scenarios of n_rec: rec is [S][n][R] */
+  int32_t param_stride;  /* P = max over scenarios of n_params: theta/grad [S][P] */
+  int32_t n_items;       /* scenario x connected-component work items */
+  int32_t n_symbolic;    /* distinct symbolic factorisations (shared by isomorphic items) */
+  int32_t max_item_nodes, max_item_branches;
+  int64_t total_nodes, total_branches;
+  int64_t nnz_L;         /* strictly-lower nonzeros of L summed over items */
+  int32_t max_levels;    /* deepest forward or backward sweep, in levels */
+  int32_t max_topologies;
+  int64_t step;          /* steps taken so far (built contexts only) */
+  int64_t device_bytes;  /* device memory owned by the context */
+  int32_t dense_items;   /* items solved entirely by their dense tail inverse */
+  int32_t block_size;    /* threads per work item in the step kernels */
+  int32_t sweep_levels;  /* barrier-separated solve phases per step (max over items) */
+  int32_t max_tail;      /* largest dense tail (nodes) */
+  int32_t lds_bytes;     /* LDS per workgroup of the forward step kernel */
+  int32_t lds_limit;     /* LDS per workgroup the device allows */
+  int32_t lds_staged;    /* 1 if index arrays and factors are staged in LDS */
+  int32_t lanes_per_block; /* branches per lane */
+} emt_info;
+
+/* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and
+ * upload n_scen networks; allocates the context on the current HIP device.
+ * Companion coefficients are computed from the branch values (no theta).
+ * Errors: EMT_EINVAL (any invalid field), EMT_ESINGULAR (a node without a
+ * conductive path to ground in some topology), EMT_ENOMEM, EMT_EDEVICE. */
+emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_ctx **out);
+
+/* Host-only: the validation and analysis of emt_build without any device
+ * work (same errors except EMT_ENOMEM/EMT_EDEVICE); fills *info. */
+emt_status emt_analyze(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_info *info);
+
+emt_status emt_info_get(const emt_ctx *ctx, emt_info *info);
+
+/* Replace the line parameters of every scenario: theta_dev is device memory
+ * [S][P] (P = info.param_stride; entries past a scenario's n_params are
+ * ignored). Recomputes the companion coefficients of all topologies on the
+ * device, rewinds to step 0 and marks the factors stale (emt_factor next).
+ * Values must be positive and finite: R_l >= 0, L_l > 0, C_l > 0 (not
+ * checked on the device; a bad value shows up as EMT_ESINGULAR or NaN). */
+emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream);
+
+/* Numerically factorise G of every topology of every scenario (LDL^T on the
+ * shared symbolic pattern). Synchronises `stream` to check the pivots:
+ * EMT_ESINGULAR if any pivot is non-positive or not finite. */
+emt_status emt_factor(emt_ctx *ctx, void *stream);
+
+/* Advance every scenario by n steps from the current step, writing the
+ * recorded node voltages to rec_dev [S][n][R] (row j = step current+1+j;
+ * columns past a scenario's n_rec are left untouched; rec_dev may be NULL to
+ * record nothing). Writes checkpoints when checkpoint_every > 0.
+ * Errors: EMT_ESTATE before emt_factor or past n_steps; EMT_EINVAL n < 0. */
+emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
+
+/* Return every scenario to step 0 with the zero initial state. */
+emt_status emt_reset(emt_ctx *ctx, void *stream);
+
+/* Reverse-time adjoint (vector-Jacobian product) of the whole recorded
+ * waveform: given dJ_drec_dev [S][T][R] returns grad_dev [S][P] = dJ/dtheta
+ * (entries past a scenario's n_params are set to 0). Recomputes each
+ * checkpoint segment, then runs transposed solves through the same factors
+ * backwards in time. Requires checkpoint_every > 0 and a forward run of all
+ * n_steps since the last emt_set_params/emt_factor/emt_reset (else
+ * EMT_ESTATE). Leaves the forward state at step n_steps. */
+emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream);
+
+/* Per-branch adjoints of the companion coefficients from the last
+ * emt_adjoint, in the scenario's original branch order (host arrays of
+ * n_branches, any may be NULL). Synchronises the device. */
+emt_status emt_branch_adjoints(emt_ctx *ctx, int32_t scen, double *gbar, double *betabar,
+                               double *gammabar);
+
+/* Copy one scenario's current state to host: v [n_nodes], i [n_branches]
+ * (original branch order; out-of-service branches read 0); either may be
+ * NULL. Synchronises the device. */
+emt_status emt_get_state(emt_ctx *ctx, int32_t scen, double *v_host, double *i_host);
+
+/* Overwrite one scenario's state at the current step from host v and i
+ * (u is recomputed as A^T v - e at the current step). Synchronises. */
+emt_status emt_set_state(emt_ctx *ctx, int32_t scen, const double *v_host, const double *i_host);
+
+/* Free everything the context owns (NULL-safe). Synchronises the device. */
+void emt_destroy(emt_ctx *ctx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *emt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMT_H */

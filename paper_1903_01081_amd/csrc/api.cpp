@@ -1,0 +1,725 @@
+// C ABI of the EMT library (include/emt.h): context management, device
+// layout, and the calls that queue the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "analysis.h"
+#include "device.h"
+#include "emt.h"
+#include "launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+emt_status set_error(emt_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  const emt_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? EMT_ENOMEM : EMT_EDEVICE;
+  throw emt::Error{st, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <class F>
+emt_status guarded(F &&f) {
+  try {
+    return f();
+  } catch (const emt::Error &e) {
+    return set_error(e.status, e.msg);
+  } catch (const std::bad_alloc &) {
+    return set_error(EMT_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(EMT_EDEVICE, "unexpected internal error");
+  }
+}
+
+}  // namespace
+
+struct emt_ctx {
+  emt::Analysis A;
+  emt_sim sim{};
+  int device = 0;
+  emt::KernelShape ks;
+  std::vector<void *> allocs;
+  int64_t device_bytes = 0;
+  emt::DevCtx dc{};
+  int n_items = 0;
+  int32_t *d_order = nullptr;
+  int32_t *d_pairs = nullptr;
+  int n_pairs = 0;
+  emt::CompanionArgs ca{};
+  int32_t *d_bscen = nullptr, *d_bitem = nullptr, *d_blocal = nullptr;
+  int64_t nbr_total = 0, nodes_total = 0;
+  int64_t *d_br_ids = nullptr;
+  std::vector<int64_t> scen_br_off;  // into d_br_ids
+  int32_t *d_lptr = nullptr, *d_line_scen = nullptr, *d_line_id = nullptr;
+  int64_t *d_lent = nullptr;
+  int n_lines_total = 0;
+  double *d_stage = nullptr;  // staging for set_state currents
+  std::vector<emt::ItemDesc> items;
+  bool sm_fwd = true, sm_adj = true, ks_adj_ok = true;
+  int max_tail = 0, dense_items = 0, sweep_levels = 0, lds_limit = 0;
+  int64_t step = 0;
+  bool factored = false;
+  bool clean = true;  // state evolved from the zero state with no set_state since
+
+  template <class T>
+  T *alloc(size_t count) {
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+    allocs.push_back(p);
+    device_bytes += (int64_t)(count * sizeof(T));
+    return static_cast<T *>(p);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v) {
+    T *p = alloc<T>(v.size());
+    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return p;
+  }
+  ~emt_ctx() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int env_int(const char *name, int dflt) {
+  const char *s = std::getenv(name);
+  return s ? std::atoi(s) : dflt;
+}
+
+// Largest dense tail whose inverse fits the lanes of one workgroup with at
+// most 16 entries per lane: d <= 4 sqrt(block size).
+int tail_max(int bs) { return bs >= 1024 ? 128 : (bs >= 256 ? 64 : 32); }
+
+int tpr_of(int d, int bs) {
+  int t = 64;
+  while (t > 1 && d * t > bs) t >>= 1;
+  return t;
+}
+
+}  // namespace
+
+// Fills the per-branch arrays that need the original networks.
+static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int32_t> &bkind,
+                               std::vector<int32_t> &bline, std::vector<double> &bE, std::vector<double> &bw,
+                               std::vector<double> &bph, std::vector<double> &bR, std::vector<double> &bL,
+                               std::vector<double> &bC, std::vector<uint32_t> &bpack, std::vector<uint8_t> &cins,
+                               std::vector<int64_t> &br_ids) {
+  const emt::Analysis &A = c.A;
+  for (size_t q = 0; q < A.items.size(); ++q) {
+    const emt::Item &it = A.items[q];
+    const emt_net &net = nets[it.scen];
+    for (int j = 0; j < it.n_br; ++j) {
+      const int b = it.br[j];
+      const int kind = net.kind[b];
+      bkind.push_back(kind);
+      bline.push_back(net.line ? net.line[b] : -1);
+      const bool src = kind == EMT_SRC;
+      bE.push_back(src ? net.E[b] : 0.0);
+      bw.push_back(src ? net.omega[b] : 0.0);
+      bph.push_back(src ? net.phase[b] : 0.0);
+      bR.push_back(net.R[b]);
+      bL.push_back(net.L[b]);
+      bC.push_back(net.C[b]);
+      const uint32_t k = it.bk[j] >= 0 ? (uint32_t)it.bk[j] : emt::kTermGround;
+      const uint32_t m = it.bm[j] >= 0 ? (uint32_t)it.bm[j] : emt::kTermGround;
+      const uint32_t cls = (kind == EMT_RL || kind == EMT_SRC) ? emt::GAMMA_PLUS_G
+                           : (kind == EMT_C ? emt::GAMMA_MINUS_G : emt::GAMMA_ZERO);
+      bpack.push_back(k | (m << 15) | (cls << 30));
+    }
+  }
+  for (size_t q = 0; q < A.items.size(); ++q) {
+    const emt::Item &it = A.items[q];
+    const emt::Scenario &sc = A.scens[it.scen];
+    for (int t = 0; t < sc.n_topo; ++t)
+      for (int j = 0; j < it.n_br; ++j) cins.push_back(sc.ins[t][it.br[j]]);
+  }
+  c.scen_br_off.clear();
+  for (size_t s = 0; s < A.scens.size(); ++s) {
+    c.scen_br_off.push_back((int64_t)br_ids.size());
+    const emt::Scenario &sc = A.scens[s];
+    for (int b = 0; b < sc.n_branches; ++b) {
+      if (sc.br_item[b] < 0) continue;
+      br_ids.push_back(c.items[sc.br_item[b]].br + sc.br_local[b]);
+    }
+  }
+  c.scen_br_off.push_back((int64_t)br_ids.size());
+}
+
+static emt::LdsShape shape_of(const emt::Item &it, const emt::Symbolic &S, const emt::SweepPlan &P) {
+  return emt::LdsShape{it.n, P.d, P.ns, it.n_br, it.n_src, P.nsv(), P.nlf(), P.nlb(), it.nptr[it.n],
+                       (int)it.rec_node.size()};
+  (void)S;
+}
+
+static void upload_all(emt_ctx &c, const emt_net *nets) {
+  using namespace emt;
+  Analysis &A = c.A;
+  const emt_sim &sim = c.sim;
+  const int K = sim.checkpoint_every;
+  const int64_t T = sim.n_steps;
+  const int64_t n_ck = K > 0 ? T / K + 1 : 0;
+  const int64_t seg_rows = K > 0 ? std::min<int64_t>(K, T) + 1 : 0;
+  const int NI = (int)A.items.size();
+
+  // Limits of the packed (15/16-bit) index formats.
+  if (A.rec_stride > 65535) throw Error{EMT_EINVAL, "at most 65535 recorded nodes per scenario"};
+  int max_nbr = 0;
+  for (const Item &it : A.items) {
+    if (it.n > kMaxItemNodes - 1)
+      throw Error{EMT_EINVAL, "a connected component has more than 32766 nodes"};
+    if (it.n_br > 32767) throw Error{EMT_EINVAL, "a connected component has more than 32767 branches"};
+    max_nbr = std::max(max_nbr, it.n_br);
+  }
+
+  // Workgroup size and branches per lane.
+  int max_lds = 65536;
+  (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
+  c.lds_limit = max_lds;
+  int bs = env_int("EMT_BLOCK", 0);
+  if (bs != 64 && bs != 256 && bs != 1024) {
+    bs = 1024;
+    for (int cand : {64, 256, 1024})
+      if ((max_nbr + cand - 1) / cand <= 8) {
+        bs = cand;
+        break;
+      }
+  }
+  int bpt = 1;
+  for (int cand : {1, 2, 4, 6, 8, 16}) {
+    bpt = cand;
+    if (cand * bs >= max_nbr) break;
+  }
+  if (bpt * bs < max_nbr) bpt = 32;
+  if (bpt > 16)
+    throw Error{EMT_EINVAL, "a connected component has " + std::to_string(max_nbr) +
+                                " branches; the step kernel holds at most 16 per lane"};
+  c.ks.bs = bs;
+  c.ks.bpt = bpt;
+  c.ks.dmax = tail_max(bs);
+
+  // Sweep plans: dense tail by cost, grown where the LDS would overflow.
+  std::vector<SweepPlan> plans(A.syms.size());
+  const int forced_tail = env_int("EMT_TAIL", -1);
+  for (size_t q = 0; q < A.syms.size(); ++q) {
+    const int d = forced_tail >= 0 ? std::min({forced_tail, A.syms[q].n, c.ks.dmax})
+                                   : choose_tail(A.syms[q], c.ks.dmax);
+    plans[q] = plan_sweeps(A.syms[q], d);
+  }
+  auto item_lds = [&](const Item &it, bool adj) {
+    return lds_bytes(shape_of(it, A.syms[it.sym], plans[it.sym]), true, adj);
+  };
+  for (const Item &it : A.items) {
+    SweepPlan &P = plans[it.sym];
+    if (item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
+      P = plan_sweeps(A.syms[it.sym], std::min(c.ks.dmax, it.n));
+  }
+  size_t f_sm = 0, a_sm = 0, f_gl = 0, a_gl = 0;
+  int wpt = 1;
+  for (const Item &it : A.items) {
+    const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym]);
+    f_sm = std::max(f_sm, lds_bytes(sh, true, false));
+    a_sm = std::max(a_sm, lds_bytes(sh, true, true));
+    f_gl = std::max(f_gl, lds_bytes(sh, false, false));
+    a_gl = std::max(a_gl, lds_bytes(sh, false, true));
+    const int d = plans[it.sym].d;
+    if (d > 0) wpt = std::max(wpt, (d + tpr_of(d, bs) - 1) / tpr_of(d, bs));
+    if (plans[it.sym].nsv() > 65535) throw Error{EMT_EINVAL, "a connected component's factor is too large"};
+  }
+  c.ks.wpt = wpt <= 4 ? 4 : 16;
+  if (wpt > 16) throw Error{EMT_EINVAL, "internal: dense tail too large for the block size"};
+  const int force_sm = env_int("EMT_LDS_STAGE", -1);
+  c.sm_fwd = f_sm <= (size_t)max_lds && force_sm != 0;
+  c.sm_adj = a_sm <= (size_t)max_lds && force_sm != 0;
+  c.ks.lds_fwd = c.sm_fwd ? f_sm : f_gl;
+  c.ks.lds_adj = c.sm_adj ? a_sm : a_gl;
+  if (f_gl > (size_t)max_lds) throw Error{EMT_EINVAL, "a connected component needs more LDS than a workgroup has"};
+  c.ks_adj_ok = a_gl <= (size_t)max_lds;
+
+  // Symbolic arrays.
+  std::vector<int32_t> symi;
+  std::vector<uint16_t> symh;
+  std::vector<SymDesc> sdesc;
+  auto put = [&symi](const std::vector<int> &v) {
+    const int64_t off = (int64_t)symi.size();
+    symi.insert(symi.end(), v.begin(), v.end());
+    return off;
+  };
+  auto puth = [&symh](const std::vector<int> &v) {
+    const int64_t off = (int64_t)symh.size();
+    for (int x : v) symh.push_back((uint16_t)x);
+    return off;
+  };
+  int max_tail = 0;
+  for (size_t q = 0; q < A.syms.size(); ++q) {
+    const Symbolic &S = A.syms[q];
+    const SweepPlan &P = plans[q];
+    SymDesc d{};
+    d.n = S.n;
+    d.d = P.d;
+    d.ns = P.ns;
+    d.nnz = (int32_t)S.nnz();
+    d.nsv = P.nsv();
+    d.nlf = P.nlf();
+    d.nlb = P.nlb();
+    d.nlev = S.levels_f();
+    d.rowptr = put(S.lrow_ptr);
+    d.rowcol = put(S.lrow_col);
+    d.colptr = put(S.lcol_ptr);
+    d.colrow = put(S.lcol_row);
+    d.colpos = put(S.lcol_pos);
+    d.flevptr = put(S.flev_ptr);
+    d.flevrows = put(S.flev_rows);
+    d.fentptr = put(S.fent_ptr);
+    d.fent = put(S.fent);
+    d.svmap = put(P.svmap);
+    d.frowptr = put(P.frow_ptr);
+    d.bptr = put(P.bptr);
+    d.sflevptr = put(P.flev_ptr);
+    d.sblevptr = put(P.blev_ptr);
+    d.fcol = puth(P.fcol);
+    d.brow = puth(P.brow);
+    d.bpos = puth(P.bpos);
+    d.sflevrows = puth(P.flev_rows);
+    d.sblevrows = puth(P.blev_rows);
+    sdesc.push_back(d);
+    max_tail = std::max(max_tail, P.d);
+  }
+  c.max_tail = max_tail;
+  std::vector<int64_t> topo, scen_topo_off;
+  for (const Scenario &sc : A.scens) {
+    scen_topo_off.push_back((int64_t)topo.size());
+    topo.insert(topo.end(), sc.topo_step.begin(), sc.topo_step.end());
+  }
+
+  c.items.assign(NI, ItemDesc{});
+  std::vector<int32_t> bk, bm, bgpos, bscen, bitem, blocal, nptr, rptr;
+  std::vector<uint16_t> nent, rnode, rcolumn;
+  int64_t coef_off = 0, fac_off = 0, dfac_off = 0, sv_off = 0, w_off = 0, ck_off = 0, seg_off = 0, node_off = 0;
+  std::vector<int64_t> ca_coef, ca_br;
+  std::vector<int32_t> ca_nbr, ca_prefix;
+  int64_t work = 0;
+  std::vector<int32_t> pairs;
+  c.dense_items = 0;
+  for (int q = 0; q < NI; ++q) {
+    const Item &it = A.items[q];
+    const Scenario &sc = A.scens[it.scen];
+    const Symbolic &S = A.syms[it.sym];
+    const SweepPlan &P = plans[it.sym];
+    if (P.d == it.n) c.dense_items++;
+    ItemDesc d{};
+    d.scen = it.scen;
+    d.sym = it.sym;
+    d.n = it.n;
+    d.n_br = it.n_br;
+    d.n_src = it.n_src;
+    d.n_topo = sc.n_topo;
+    d.n_rec = (int32_t)it.rec_node.size();
+    d.br = (int64_t)bk.size();
+    d.coef = coef_off;
+    d.nptr = (int64_t)nptr.size();
+    d.nent = (int64_t)nent.size();
+    d.node = node_off;
+    d.fac = fac_off;
+    d.dfac = dfac_off;
+    d.sv = sv_off;
+    d.w = w_off;
+    d.rec = (int64_t)rnode.size();
+    d.topo = scen_topo_off[it.scen];
+    d.ck = ck_off;
+    d.seg = seg_off;
+    c.items[q] = d;
+    coef_off += (int64_t)sc.n_topo * it.n_br;
+    fac_off += (int64_t)sc.n_topo * S.nnz();
+    dfac_off += (int64_t)sc.n_topo * it.n;
+    sv_off += (int64_t)sc.n_topo * P.nsv();
+    w_off += (int64_t)sc.n_topo * P.d * P.d;
+    ck_off += n_ck * it.n_br;
+    seg_off += seg_rows * it.n_br;
+    node_off += it.n;
+    for (int t = 0; t < sc.n_topo; ++t) {
+      pairs.push_back(q);
+      pairs.push_back(t);
+    }
+    ca_coef.push_back(d.coef);
+    ca_br.push_back(d.br);
+    ca_nbr.push_back(it.n_br);
+    ca_prefix.push_back((int32_t)work);
+    work += (int64_t)it.n_br * sc.n_topo;
+    for (int j = 0; j < it.n_br; ++j) {
+      bk.push_back(it.bk[j]);
+      bm.push_back(it.bm[j]);
+      bgpos.push_back(it.gpos[j]);
+      bscen.push_back(it.scen);
+      bitem.push_back(q);
+      blocal.push_back(j);
+    }
+    nptr.insert(nptr.end(), it.nptr.begin(), it.nptr.end());
+    for (int e : it.nent) nent.push_back((uint16_t)e);
+    std::vector<int> idx(it.rec_node.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return it.rec_node[a] < it.rec_node[b]; });
+    std::vector<int32_t> rp(it.n + 1, 0);
+    for (int e : idx) {
+      rnode.push_back((uint16_t)it.rec_node[e]);
+      rcolumn.push_back((uint16_t)it.rec_col[e]);
+      rp[it.rec_node[e] + 1]++;
+    }
+    for (int r = 0; r < it.n; ++r) rp[r + 1] += rp[r];
+    rptr.insert(rptr.end(), rp.begin(), rp.end());
+  }
+  if (work > INT32_MAX) throw Error{EMT_EINVAL, "too many branch-topology pairs"};
+  c.n_items = NI;
+  c.n_pairs = (int)pairs.size() / 2;
+  c.nbr_total = (int64_t)bk.size();
+  c.nodes_total = node_off;
+
+  std::vector<int32_t> bkind, bline;
+  std::vector<double> bE, bw, bph, bR, bL, bC;
+  std::vector<uint32_t> bpack;
+  std::vector<uint8_t> cins;
+  std::vector<int64_t> br_ids;
+  fill_branch_params(c, nets, bkind, bline, bE, bw, bph, bR, bL, bC, bpack, cins, br_ids);
+
+  // Line -> branches (global item-branch index), per scenario, fixed order.
+  std::vector<int32_t> lptr{0}, line_scen, line_id;
+  std::vector<int64_t> lent;
+  for (size_t s = 0; s < A.scens.size(); ++s) {
+    const Scenario &sc = A.scens[s];
+    const int nl = sc.n_params / 3;
+    std::vector<std::vector<int64_t>> per(nl);
+    for (int b = 0; b < sc.n_branches; ++b) {
+      const int l = nets[s].line ? nets[s].line[b] : -1;
+      if (l < 0 || sc.br_item[b] < 0) continue;
+      per[l].push_back(c.items[sc.br_item[b]].br + sc.br_local[b]);
+    }
+    for (int l = 0; l < nl; ++l) {
+      lent.insert(lent.end(), per[l].begin(), per[l].end());
+      lptr.push_back((int32_t)lent.size());
+      line_scen.push_back((int32_t)s);
+      line_id.push_back(l);
+    }
+  }
+  c.n_lines_total = (int)line_id.size();
+
+  // Largest items first so their workgroups start first.
+  std::vector<int32_t> order(NI);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)A.items[a].n + A.items[a].n_br > (int64_t)A.items[b].n + A.items[b].n_br;
+  });
+
+  DevCtx &dc = c.dc;
+  dc.items = c.upload(c.items);
+  dc.syms = c.upload(sdesc);
+  dc.symi = c.upload(symi);
+  dc.symh = c.upload(symh);
+  dc.bpack = c.upload(bpack);
+  dc.bk = c.upload(bk);
+  dc.bm = c.upload(bm);
+  dc.bkind = c.upload(bkind);
+  dc.bline = c.upload(bline);
+  dc.bgpos = c.upload(bgpos);
+  dc.bE = c.upload(bE);
+  dc.bw = c.upload(bw);
+  dc.bph = c.upload(bph);
+  dc.bR = c.upload(bR);
+  dc.bL = c.upload(bL);
+  dc.bC = c.upload(bC);
+  dc.si = c.alloc<double>(c.nbr_total);
+  dc.su = c.alloc<double>(c.nbr_total);
+  dc.gbar = c.alloc<double>(c.nbr_total);
+  dc.bbar = c.alloc<double>(c.nbr_total);
+  dc.cbar = c.alloc<double>(c.nbr_total);
+  dc.cg = c.alloc<double>(coef_off);
+  dc.cb = c.alloc<double>(coef_off);
+  dc.cins = c.upload(cins);
+  dc.nptr = c.upload(nptr);
+  dc.rptr = c.upload(rptr);
+  dc.nent = c.upload(nent);
+  dc.rnode = c.upload(rnode);
+  dc.rcolumn = c.upload(rcolumn);
+  dc.sv_state = c.alloc<double>(node_off);
+  dc.lfull = c.alloc<double>(fac_off);
+  dc.dpiv = c.alloc<double>(dfac_off);
+  dc.dinv = c.alloc<double>(dfac_off);
+  dc.svals = c.alloc<double>(sv_off);
+  dc.wtail = c.alloc<double>(w_off);
+  dc.topo = c.upload(topo);
+  dc.ck_i = K > 0 ? c.alloc<double>(ck_off) : nullptr;
+  dc.ck_u = K > 0 ? c.alloc<double>(ck_off) : nullptr;
+  dc.seg_i = K > 0 ? c.alloc<double>(seg_off) : nullptr;
+  dc.seg_u = K > 0 ? c.alloc<double>(seg_off) : nullptr;
+  dc.flags = c.alloc<int32_t>(4);
+  dc.dt = sim.dt;
+  dc.T = T;
+  dc.K = K;
+  dc.rec_stride = A.rec_stride;
+  c.d_order = c.upload(order);
+  c.d_pairs = c.upload(pairs);
+  c.ca.coef_base = c.upload(ca_coef);
+  c.ca.br_base = c.upload(ca_br);
+  c.ca.nbr_of = c.upload(ca_nbr);
+  c.ca.cnt_prefix = c.upload(ca_prefix);
+  c.ca.total = (int)work;
+  c.ca.n_items = NI;
+  c.d_bscen = c.upload(bscen);
+  c.d_bitem = c.upload(bitem);
+  c.d_blocal = c.upload(blocal);
+  c.d_br_ids = c.upload(br_ids);
+  c.d_lptr = c.upload(lptr);
+  c.d_lent = c.upload(lent);
+  c.d_line_scen = c.upload(line_scen);
+  c.d_line_id = c.upload(line_id);
+  int64_t max_scen_br = 0;
+  for (size_t s = 0; s + 1 < c.scen_br_off.size(); ++s)
+    max_scen_br = std::max(max_scen_br, c.scen_br_off[s + 1] - c.scen_br_off[s]);
+  c.d_stage = c.alloc<double>(max_scen_br);
+  // statistics
+  c.sweep_levels = 0;
+  for (const Item &it : A.items)
+    c.sweep_levels = std::max(c.sweep_levels, plans[it.sym].nlf() + plans[it.sym].nlb() + (plans[it.sym].d > 0 ? 2 : 0));
+}
+
+static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
+  emt::KernelShape ks = c.ks;
+  ks.sm = c.sm_fwd;
+  switch (ks.bs) {
+    case 64: return emt::launch_forward_bs64(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
+    case 256: return emt::launch_forward_bs256(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
+    default: return emt::launch_forward_bs1024(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
+  }
+}
+
+static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
+  emt::KernelShape ks = c.ks;
+  ks.sm = c.sm_adj;
+  switch (ks.bs) {
+    case 64: return emt::launch_adjoint_bs64(c.dc, ks, c.d_order, c.n_items, dJ, st);
+    case 256: return emt::launch_adjoint_bs256(c.dc, ks, c.d_order, c.n_items, dJ, st);
+    default: return emt::launch_adjoint_bs1024(c.dc, ks, c.d_order, c.n_items, dJ, st);
+  }
+}
+
+extern "C" {
+
+const char *emt_last_error(void) { return g_last_error.c_str(); }
+
+emt_status emt_analyze(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_info *info) {
+  return guarded([&]() -> emt_status {
+    if (!sim || !info) return set_error(EMT_EINVAL, "sim and info are required");
+    emt::Analysis A = emt::analyze(nets, n_scen, *sim);
+    emt::fill_info(A, info);
+    return EMT_OK;
+  });
+}
+
+emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_ctx **out) {
+  return guarded([&]() -> emt_status {
+    if (!out || !sim) return set_error(EMT_EINVAL, "sim and out are required");
+    *out = nullptr;
+    emt::Analysis A = emt::analyze(nets, n_scen, *sim);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return set_error(EMT_EDEVICE, "no HIP device");
+    std::unique_ptr<emt_ctx> c(new emt_ctx);
+    c->A = std::move(A);
+    c->sim = *sim;
+    hip_check(hipGetDevice(&c->device), "hipGetDevice");
+    upload_all(*c, nets);
+    hip_check(emt::launch_companions(c->dc, c->ca, nullptr), "companions");
+    hip_check(emt::launch_reset(c->dc, c->d_bitem, c->d_blocal, c->nbr_total, c->nodes_total, nullptr), "reset");
+    hip_check(hipDeviceSynchronize(), "build");
+    *out = c.release();
+    return EMT_OK;
+  });
+}
+
+emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || !info) return set_error(EMT_EINVAL, "ctx and info are required");
+    emt::fill_info(ctx->A, info);
+    info->step = ctx->step;
+    info->device_bytes = ctx->device_bytes;
+    info->block_size = ctx->ks.bs;
+    info->dense_items = ctx->dense_items;
+    info->sweep_levels = ctx->sweep_levels;
+    info->max_tail = ctx->max_tail;
+    info->lds_bytes = (int32_t)ctx->ks.lds_fwd;
+    info->lds_limit = ctx->lds_limit;
+    info->lds_staged = ctx->sm_fwd ? 1 : 0;
+    info->lanes_per_block = ctx->ks.bpt;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || !theta_dev) return set_error(EMT_EINVAL, "ctx and theta are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(emt::launch_set_params(ctx->dc, theta_dev, ctx->A.param_stride, ctx->d_bscen, ctx->nbr_total, st),
+              "set_params");
+    hip_check(emt::launch_companions(ctx->dc, ctx->ca, st), "companions");
+    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
+              "reset");
+    ctx->step = 0;
+    ctx->factored = false;
+    ctx->clean = true;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_factor(emt_ctx *ctx, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(emt::launch_fill_i32(ctx->dc.flags, 1, 0, st), "clear flags");
+    hip_check(emt::launch_factor(ctx->dc, ctx->d_pairs, ctx->n_pairs, ctx->max_tail, st), "factor");
+    int32_t bad = 0;
+    hip_check(hipMemcpyAsync(&bad, ctx->dc.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag");
+    hip_check(hipStreamSynchronize(st), "factor sync");
+    if (bad) {
+      ctx->factored = false;
+      return set_error(EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots");
+    }
+    ctx->factored = true;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    if (n < 0) return set_error(EMT_EINVAL, "n must be >= 0");
+    if (!ctx->factored) return set_error(EMT_ESTATE, "emt_factor has not succeeded since the last change");
+    if (ctx->step + n > ctx->sim.n_steps) return set_error(EMT_ESTATE, "stepping past n_steps");
+    if (n == 0) return EMT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    ctx->step += n;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_reset(emt_ctx *ctx, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
+              "reset");
+    ctx->step = 0;
+    ctx->clean = true;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || !dJ_drec_dev || !grad_dev) return set_error(EMT_EINVAL, "ctx, dJ_drec and grad are required");
+    if (ctx->sim.checkpoint_every <= 0) return set_error(EMT_ESTATE, "built without checkpoints");
+    if (!ctx->factored || !ctx->clean || ctx->step != ctx->sim.n_steps)
+      return set_error(EMT_ESTATE, "needs a complete forward run from step 0 since the last change");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!ctx->ks_adj_ok) return set_error(EMT_EINVAL, "a connected component is too large for the adjoint kernel");
+    hip_check(launch_adjoint(*ctx, dJ_drec_dev, st), "adjoint");
+    const int P = ctx->A.param_stride;
+    hip_check(emt::launch_grad(ctx->dc, ctx->d_lptr, ctx->d_lent, ctx->d_line_scen, ctx->d_line_id,
+                               ctx->n_lines_total, grad_dev, P, (int64_t)ctx->A.scens.size() * P, st),
+              "grad");
+    return EMT_OK;
+  });
+}
+
+emt_status emt_branch_adjoints(emt_ctx *ctx, int32_t scen, double *gbar, double *betabar, double *gammabar) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size()) return set_error(EMT_EINVAL, "bad scenario");
+    hip_check(hipDeviceSynchronize(), "sync");
+    const emt::Scenario &sc = ctx->A.scens[scen];
+    double *outs[3] = {gbar, betabar, gammabar};
+    double *srcs[3] = {ctx->dc.gbar, ctx->dc.bbar, ctx->dc.cbar};
+    std::vector<double> buf(ctx->nbr_total);
+    for (int w = 0; w < 3; ++w) {
+      if (!outs[w]) continue;
+      hip_check(hipMemcpy(buf.data(), srcs[w], buf.size() * sizeof(double), hipMemcpyDeviceToHost), "copy");
+      for (int b = 0; b < sc.n_branches; ++b)
+        outs[w][b] = sc.br_item[b] < 0 ? 0.0 : buf[ctx->items[sc.br_item[b]].br + sc.br_local[b]];
+    }
+    return EMT_OK;
+  });
+}
+
+emt_status emt_get_state(emt_ctx *ctx, int32_t scen, double *v_host, double *i_host) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size()) return set_error(EMT_EINVAL, "bad scenario");
+    hip_check(hipDeviceSynchronize(), "sync");
+    const emt::Scenario &sc = ctx->A.scens[scen];
+    if (v_host) {
+      std::vector<double> sv(ctx->nodes_total);
+      hip_check(hipMemcpy(sv.data(), ctx->dc.sv_state, sv.size() * sizeof(double), hipMemcpyDeviceToHost), "copy v");
+      for (int a = 0; a < sc.n_nodes; ++a)
+        v_host[a] = sv[ctx->items[sc.node_item[a]].node + sc.node_local[a]];
+    }
+    if (i_host) {
+      std::vector<double> si(ctx->nbr_total);
+      hip_check(hipMemcpy(si.data(), ctx->dc.si, si.size() * sizeof(double), hipMemcpyDeviceToHost), "copy i");
+      for (int b = 0; b < sc.n_branches; ++b)
+        i_host[b] = sc.br_item[b] < 0 ? 0.0 : si[ctx->items[sc.br_item[b]].br + sc.br_local[b]];
+    }
+    return EMT_OK;
+  });
+}
+
+emt_status emt_set_state(emt_ctx *ctx, int32_t scen, const double *v_host, const double *i_host) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size() || !v_host || !i_host)
+      return set_error(EMT_EINVAL, "bad arguments");
+    const emt::Scenario &sc = ctx->A.scens[scen];
+    for (int a = 0; a < sc.n_nodes; ++a)
+      if (!std::isfinite(v_host[a])) return set_error(EMT_EINVAL, "non-finite voltage");
+    for (int b = 0; b < sc.n_branches; ++b)
+      if (!std::isfinite(i_host[b])) return set_error(EMT_EINVAL, "non-finite current");
+    hip_check(hipDeviceSynchronize(), "sync");
+    for (int q : sc.items) {
+      const emt::Item &it = ctx->A.items[q];
+      std::vector<double> v(it.n);
+      for (int a = 0; a < it.n; ++a) v[a] = v_host[it.gnode[a]];
+      hip_check(hipMemcpy(ctx->dc.sv_state + ctx->items[q].node, v.data(), v.size() * sizeof(double),
+                          hipMemcpyHostToDevice),
+                "copy v");
+    }
+    std::vector<double> iv;
+    for (int b = 0; b < sc.n_branches; ++b)
+      if (sc.br_item[b] >= 0) iv.push_back(i_host[b]);
+    const int64_t b0 = ctx->scen_br_off[scen], nb = ctx->scen_br_off[scen + 1] - b0;
+    if (nb > 0) {
+      hip_check(hipMemcpy(ctx->d_stage, iv.data(), nb * sizeof(double), hipMemcpyHostToDevice), "copy i");
+      hip_check(emt::launch_set_state(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->d_br_ids, b0, nb, ctx->d_stage,
+                                      ctx->step, nullptr),
+                "set_state");
+    }
+    hip_check(hipDeviceSynchronize(), "sync");
+    ctx->clean = false;
+    return EMT_OK;
+  });
+}
+
+void emt_destroy(emt_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+}  // extern "C"

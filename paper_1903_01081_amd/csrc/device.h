@@ -1,0 +1,82 @@
+// Device-side data layout shared by the kernels and the host code that
+// uploads it. Everything is flattened into a few big arrays addressed by
+// per-item offsets (structure of arrays; one work item = one connected
+// component of one scenario).
+#pragma once
+
+#include <cstdint>
+
+namespace emt {
+
+enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4 };
+
+// Packed branch descriptor for the step kernels: local terminals in 15 bits
+// each (kTermGround = ground) and the history-coefficient class in 2 bits:
+// gamma = g (R-L and sources), -g (capacitors) or 0 (resistors, switches).
+constexpr uint32_t kTermGround = 0x7FFF;
+constexpr int kMaxItemNodes = 0x7FFF;
+enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2 };
+
+// Symbolic factor and sweep plan (shared by isomorphic items). Offsets index
+// DevCtx::symi (int32) or DevCtx::symh (uint16).
+struct SymDesc {
+  int32_t n, d, ns, nnz;      // nodes, dense-tail size, leading size, nonzeros of L
+  int32_t nsv, nlf, nlb, nlev;  // sweep entries, sweep levels, factor levels
+  // int32 (symi): full factor structure for the numeric factorisation
+  int64_t rowptr, rowcol, colptr, colrow, colpos, flevptr, flevrows, fentptr, fent;
+  // int32 (symi): sweep plan
+  int64_t svmap, frowptr, bptr, sflevptr, sblevptr;
+  // uint16 (symh): sweep plan
+  int64_t fcol, brow, bpos, sflevrows, sblevrows;
+};
+
+struct ItemDesc {
+  int32_t scen, sym, n, n_br, n_src, n_topo, n_rec, pad0;
+  int64_t br;    // per-branch arrays
+  int64_t coef;  // coefficient arrays [n_topo][n_br] (g, beta, in-service)
+  int64_t nptr;  // node CSR pointers [n+1] (int32); also recorded-node pointers rptr
+  int64_t nent;  // node CSR entries (uint16: local branch << 1 | end-is-m)
+  int64_t node;  // per-node state [n]
+  int64_t fac;   // full L values [n_topo][nnz] (factorisation work)
+  int64_t dfac;  // pivots D and 1/D [n_topo][n]
+  int64_t sv;    // sweep values [n_topo][nsv]
+  int64_t w;     // tail inverse [n_topo][d*d]
+  int64_t rec;   // recorded pairs (uint16 local node, uint16 column) [n_rec]
+  int64_t topo;  // scenario topology start steps [n_topo]
+  int64_t ck;    // checkpoints (i, u) [n_ck][n_br]
+  int64_t seg;   // adjoint segment buffer (i, u) [K+1][n_br]
+};
+
+// Everything a kernel needs, passed by value.
+struct DevCtx {
+  const ItemDesc *items;
+  const SymDesc *syms;
+  const int32_t *symi;
+  const uint16_t *symh;
+  // per item-branch arrays (ItemDesc::br + local branch)
+  const uint32_t *bpack;
+  const int32_t *bk, *bm, *bkind, *bline, *bgpos;
+  const double *bE, *bw, *bph;
+  double *bR, *bL, *bC;
+  double *si, *su;             // branch state i, u
+  double *gbar, *bbar, *cbar;  // adjoint accumulators
+  // coefficients (ItemDesc::coef + t * n_br + b)
+  double *cg, *cb;
+  const uint8_t *cins;
+  // node data
+  const int32_t *nptr, *rptr;  // node CSR and recorded-column pointers (ItemDesc::nptr)
+  const uint16_t *nent;        // (ItemDesc::nent)
+  const uint16_t *rnode, *rcolumn;  // (ItemDesc::rec)
+  double *sv_state;            // node voltages (ItemDesc::node)
+  // numeric factors
+  double *lfull, *dpiv, *dinv, *svals, *wtail;
+  const int64_t *topo;
+  double *ck_i, *ck_u, *seg_i, *seg_u;
+  int32_t *flags;  // [0] = bad pivots
+  double dt;
+  int64_t T;
+  int32_t K;
+  int32_t rec_stride;
+};
+
+}  // namespace emt

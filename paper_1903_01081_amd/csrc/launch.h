@@ -1,0 +1,63 @@
+// Host-callable launchers of the HIP kernels (step.hip, aux.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "device.h"
+
+namespace emt {
+
+// Sizes that decide an item's LDS footprint in the step kernels.
+struct LdsShape {
+  int n, d, ns, nbr, nsrc, nsv, nlf, nlb, nent, nrec;
+};
+
+// Launch shape of the step kernels, chosen once per context.
+struct KernelShape {
+  int bs = 256;    // threads per workgroup (64, 256 or 1024)
+  int bpt = 1;     // branches per lane (1, 2, 4, 6, 8, 16)
+  int wpt = 4;     // tail-inverse entries per lane (4 or 16)
+  bool sm = true;  // index arrays and factors staged in LDS
+  size_t lds_fwd = 0, lds_adj = 0;
+  int dmax = 0;    // largest dense tail this block size supports
+};
+
+struct CompanionArgs {
+  const int64_t *coef_base, *br_base;
+  const int32_t *nbr_of, *cnt_prefix;
+  int total, n_items;
+};
+
+size_t lds_bytes(const LdsShape &s, bool sm, bool adjoint);
+
+hipError_t launch_forward_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
+                               double *, hipStream_t);
+hipError_t launch_forward_bs256(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
+                                double *, hipStream_t);
+hipError_t launch_forward_bs1024(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
+                                 double *, hipStream_t);
+hipError_t launch_adjoint_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                               hipStream_t);
+hipError_t launch_adjoint_bs256(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                hipStream_t);
+hipError_t launch_adjoint_bs1024(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                 hipStream_t);
+
+hipError_t launch_factor(const DevCtx &c, const int32_t *pairs, int n_pairs, int max_tail, hipStream_t st);
+hipError_t launch_companions(const DevCtx &c, const CompanionArgs &a, hipStream_t st);
+hipError_t launch_set_params(const DevCtx &c, const double *theta, int P, const int32_t *bscen,
+                             int64_t nbr_total, hipStream_t st);
+hipError_t launch_reset(const DevCtx &c, const int32_t *bitem, const int32_t *blocal, int64_t nbr_total,
+                        int64_t n_nodes_total, hipStream_t st);
+hipError_t launch_set_state(const DevCtx &c, const int32_t *bitem, const int32_t *blocal,
+                            const int64_t *br_ids, int64_t b0, int64_t nb, const double *i_in, int64_t n,
+                            hipStream_t st);
+hipError_t launch_grad(const DevCtx &c, const int32_t *lptr, const int64_t *lent, const int32_t *line_scen,
+                       const int32_t *line_id, int n_lines_total, double *grad, int P, int64_t grad_len,
+                       hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+
+}  // namespace emt

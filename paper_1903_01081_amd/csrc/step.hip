@@ -1,0 +1,67 @@
+// Instantiations of the step kernels for one workgroup size (EMT_BS, set by
+// the build: 64, 256 or 1024), so the three sizes compile in parallel.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "step.h"
+
+#ifndef EMT_BS
+#error "EMT_BS must be defined"
+#endif
+
+namespace emt {
+
+namespace {
+
+template <int BPT, int WPT, bool SM>
+hipError_t fwd(const DevCtx &c, const int32_t *order, int n_items, int64_t n0, int64_t ns, double *rec,
+               size_t lds, hipStream_t st) {
+  auto k = step::k_forward<EMT_BS, BPT, WPT, SM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(EMT_BS), lds, st, c, order, n0, ns, rec);
+  return hipGetLastError();
+}
+
+template <int BPT, int WPT, bool SM>
+hipError_t adj(const DevCtx &c, const int32_t *order, int n_items, const double *dJ, size_t lds,
+               hipStream_t st) {
+  auto k = step::k_adjoint<EMT_BS, BPT, WPT, SM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_items), dim3(EMT_BS), lds, st, c, order, dJ);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define EMT_CAT2(a, b) a##b
+#define EMT_CAT(a, b) EMT_CAT2(a, b)
+
+#define EMT_SHAPES_SM(X, SM) \
+  X(1, 4, SM) X(2, 4, SM) X(4, 4, SM) X(6, 4, SM) X(8, 4, SM) X(16, 4, SM) \
+  X(1, 16, SM) X(2, 16, SM) X(4, 16, SM) X(6, 16, SM) X(8, 16, SM) X(16, 16, SM)
+#define EMT_SHAPES(X) EMT_SHAPES_SM(X, true) EMT_SHAPES_SM(X, false)
+
+hipError_t EMT_CAT(launch_forward_bs, EMT_BS)(const DevCtx &c, const KernelShape &ks, const int32_t *order,
+                                              int n_items, int64_t n0, int64_t ns, double *rec,
+                                              hipStream_t st) {
+#define EMT_CASE(BPT, WPT, SM) \
+  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return fwd<BPT, WPT, SM>(c, order, n_items, n0, ns, rec, ks.lds_fwd, st);
+  EMT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t EMT_CAT(launch_adjoint_bs, EMT_BS)(const DevCtx &c, const KernelShape &ks, const int32_t *order,
+                                              int n_items, const double *dJ, hipStream_t st) {
+#define EMT_CASE(BPT, WPT, SM) \
+  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return adj<BPT, WPT, SM>(c, order, n_items, dJ, ks.lds_adj, st);
+  EMT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace emt

@@ -341,7 +341,8 @@ def small_grid(seed: int, n_bus: int, *, n_lines=None, n_gen=None, n_load=None,
                remove_series: Optional[int] = None, remove_step: Optional[int] = None):
     """A grid of the same recipe at an arbitrary size, for tests."""
     rng = np.random.default_rng(seed)
-    n_lines = int(round(1.5 * n_bus)) if n_lines is None else n_lines
+    if n_lines is None:
+        n_lines = min(int(round(1.5 * n_bus)), n_bus * (n_bus - 1) // 2)
     n_gen = max(1, int(round(0.2 * n_bus))) if n_gen is None else n_gen
     n_load = int(round(0.6 * n_bus)) if n_load is None else n_load
     bld, info = three_phase_grid(rng, n_bus, n_lines, n_gen, n_load,

@@ -1,0 +1,149 @@
+"""Python front end of the EMT library: a Simulator over libemt.so.
+
+Torch tensors only carry device memory and the current stream; every step of
+the time loop runs in the HIP kernels behind include/emt.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import EMTError, check
+
+SOLVERS = {"auto": 0, "dense": 1, "sparse": 2}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, shape, name: str):
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Simulator:
+    """A batch of networks (scenarios) stepped together on the current HIP device.
+
+    rec layout: [S, n, R] with R = max n_rec; theta / grad layout: [S, P] with
+    P = max n_params (3 per line: R_l, L_l, C_l).
+    """
+
+    def __init__(self, nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0,
+                 solver: str = "auto", device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the EMT library needs a HIP device")
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.nets = list(nets)
+        self.dt = float(dt)
+        self.n_steps = int(n_steps)
+        self.checkpoint_every = int(checkpoint_every)
+        packed = _lib.PackedNets(self.nets)
+        sim = _lib.make_sim(dt, n_steps, checkpoint_every, SOLVERS[solver])
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.emt_build(packed.ref, packed.n, C.addressof(sim), C.byref(self._ctx)))
+        info = self.info()
+        self.S = info["n_scen"]
+        self.R = info["rec_stride"]
+        self.P = info["param_stride"]
+        self.n_nodes = [int(n.n_nodes) for n in self.nets]
+        self.n_branches = [int(n.n_branches) for n in self.nets]
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.emt_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = _lib.EmtInfo()
+        check(self.lib.emt_info_get(self._ctx, C.addressof(inf)))
+        return inf.as_dict()
+
+    @property
+    def step_index(self) -> int:
+        return int(self.info()["step"])
+
+    # -- the loop ---------------------------------------------------------
+    def set_params(self, theta: torch.Tensor):
+        """theta: [S, P] float64 device tensor of line parameters."""
+        check(self.lib.emt_set_params(self._ctx, _dev_ptr(theta, (self.S, self.P), "theta"), _stream()))
+
+    def factor(self):
+        check(self.lib.emt_factor(self._ctx, _stream()))
+
+    def reset(self):
+        check(self.lib.emt_reset(self._ctx, _stream()))
+
+    def step(self, n: int, rec: Optional[torch.Tensor] = None, record: bool = True):
+        """Advance n steps; returns rec [S, n, R] (allocated if not given)."""
+        if record and rec is None:
+            rec = torch.zeros((self.S, n, self.R), dtype=torch.float64, device=self.device)
+        ptr = _dev_ptr(rec, (self.S, n, self.R), "rec") if record else None
+        check(self.lib.emt_step(self._ctx, int(n), ptr, _stream()))
+        return rec
+
+    def run(self, record: bool = True):
+        """factor (if needed by the caller) then all n_steps from step 0."""
+        return self.step(self.n_steps, record=record)
+
+    def adjoint(self, dJ_drec: torch.Tensor, grad: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dJ/dtheta [S, P] for a cotangent dJ/drec [S, T, R]."""
+        if grad is None:
+            grad = torch.empty((self.S, self.P), dtype=torch.float64, device=self.device)
+        d = _dev_ptr(dJ_drec, (self.S, self.n_steps, self.R), "dJ_drec")
+        g = _dev_ptr(grad, (self.S, self.P), "grad")
+        check(self.lib.emt_adjoint(self._ctx, d, g, _stream()))
+        return grad
+
+    def branch_adjoints(self, scen: int):
+        nb = self.n_branches[scen]
+        out = [np.empty(nb) for _ in range(3)]
+        check(self.lib.emt_branch_adjoints(self._ctx, int(scen), *[o.ctypes.data for o in out]))
+        return tuple(out)
+
+    # -- state ------------------------------------------------------------
+    def get_state(self, scen: int):
+        v = np.empty(self.n_nodes[scen])
+        i = np.empty(self.n_branches[scen])
+        check(self.lib.emt_get_state(self._ctx, int(scen), v.ctypes.data, i.ctypes.data))
+        return v, i
+
+    def set_state(self, scen: int, v, i):
+        v = np.ascontiguousarray(v, np.float64)
+        i = np.ascontiguousarray(i, np.float64)
+        if v.shape != (self.n_nodes[scen],) or i.shape != (self.n_branches[scen],):
+            raise ValueError("state shapes do not match the scenario")
+        check(self.lib.emt_set_state(self._ctx, int(scen), v.ctypes.data, i.ctypes.data))
+
+
+def theta_matrix(nets, thetas=None, device=None) -> torch.Tensor:
+    """Stacks per-scenario parameter vectors (default: nominal) into [S, P]."""
+    P = max(3 * int(n.n_lines) for n in nets)
+    out = np.zeros((len(nets), P))
+    for s, n in enumerate(nets):
+        th = n.theta0() if thetas is None else np.asarray(thetas[s], np.float64)
+        out[s, :th.shape[0]] = th
+    return torch.tensor(out, dtype=torch.float64, device=device)
+
+
+__all__ = ["Simulator", "EMTError", "theta_matrix", "SOLVERS"]
