@@ -76,7 +76,7 @@ def time_simulation(torch, sim, rec, steps, warmup):
 
 def cpu_baseline_config1(nets, cfg):
     """The oracle (dense LU, one thread) on a bounded sample of the workload:
-    two short runs (50 and 250 steps) give the factorisation and per-step
+    two short runs (50 and 1050 steps) give the factorisation and per-step
     costs, extrapolated to the full horizon with its two factorisations."""
     from oracle import oracle as O
     net = nets[0]
@@ -85,15 +85,15 @@ def cpu_baseline_config1(nets, cfg):
     O.run(net, dt, 50)
     t50 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    O.run(net, dt, 250)
-    t250 = time.perf_counter() - t0
-    per_step = max((t250 - t50) / 200.0, 1e-12)
+    O.run(net, dt, 1050)
+    t1050 = time.perf_counter() - t0
+    per_step = max((t1050 - t50) / 1000.0, 1e-12)
     factor = max(t50 - 50 * per_step, 0.0)
     T = cfg["n_steps"]
     total = 2 * factor + T * per_step
     return {"value": net.n_nodes * T / total, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle runs of 50 and 250 steps of the same 3000-node grid "
-                      f"({t50 + t250:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
+            "sample": f"oracle runs of 50 and 1050 steps of the same 3000-node grid "
+                      f"({t50 + t1050:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
                       f"factorisation {factor:.2f} s extrapolated to 50,000 steps and 2 factorisations"}
 
 

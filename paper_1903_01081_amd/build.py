@@ -24,7 +24,7 @@ SOURCES = [
     ("aux.hip", "aux", []),
     ("step.hip", "step64", ["-DEMT_BS=64"]),
     ("step.hip", "step256", ["-DEMT_BS=256"]),
-    ("step.hip", "step1024", ["-DEMT_BS=1024"]),
+    ("step.hip", "step512", ["-DEMT_BS=512"]),
 ]
 
 COMMON = [

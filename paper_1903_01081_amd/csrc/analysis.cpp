@@ -268,6 +268,43 @@ SweepPlan plan_sweeps(const Symbolic &S, int d) {
   };
   group(lev, nlf, P.flev_ptr, P.flev_rows);
   group(blev, nlb, P.blev_ptr, P.blev_rows);
+  auto desc = [](int row, int q0, int cnt) {
+    return (uint64_t)(uint32_t)row | ((uint64_t)(uint32_t)q0 << 16) | ((uint64_t)(uint32_t)cnt << 32);
+  };
+  P.fpass_ptr.assign(1, 0);
+  for (int l = 1; l < nlf; ++l) {
+    int mx = 0;
+    for (int p = P.flev_ptr[l]; p < P.flev_ptr[l + 1]; ++p) {
+      const int r = P.flev_rows[p];
+      const int cnt = P.frow_ptr[r + 1] - P.frow_ptr[r];
+      P.fdesc.push_back(desc(r, P.frow_ptr[r], cnt));
+      mx = std::max(mx, cnt);
+    }
+    P.fpass_ptr.push_back((int)P.fdesc.size());
+    P.fpass_maxcnt.push_back(mx);
+  }
+  if (d > 0) {
+    int mx = 0;
+    for (int r = ns; r < n; ++r) {
+      const int cnt = P.frow_ptr[r + 1] - P.frow_ptr[r];
+      P.fdesc.push_back(desc(r, P.frow_ptr[r], cnt));
+      mx = std::max(mx, cnt);
+    }
+    P.fpass_ptr.push_back((int)P.fdesc.size());
+    P.fpass_maxcnt.push_back(mx);
+  }
+  P.bpass_ptr.assign(1, 0);
+  for (int l = 0; l < nlb; ++l) {
+    int mx = 0;
+    for (int p = P.blev_ptr[l]; p < P.blev_ptr[l + 1]; ++p) {
+      const int r = P.blev_rows[p];
+      const int cnt = P.bptr[r + 1] - P.bptr[r];
+      P.bdesc.push_back(desc(r, P.bptr[r], cnt));
+      mx = std::max(mx, cnt);
+    }
+    P.bpass_ptr.push_back((int)P.bdesc.size());
+    P.bpass_maxcnt.push_back(mx);
+  }
   return P;
 }
 

@@ -47,7 +47,15 @@ struct SweepPlan {
   std::vector<int> brow, bpos;           // [nsv] row and sv index of each
   std::vector<int> flev_ptr, flev_rows;  // forward levels over rows < ns
   std::vector<int> blev_ptr, blev_rows;  // backward levels over rows < ns
+  // Row descriptors for the device sweeps: row | first entry << 16 | count
+  // << 32. Forward passes: levels 1.. of the leading rows (level 0 rows have
+  // no entries), then one pass over the tail rows; backward passes: the
+  // backward levels. Per pass: start, row count, largest count.
+  std::vector<uint64_t> fdesc, bdesc;
+  std::vector<int> fpass_ptr, fpass_maxcnt, bpass_ptr, bpass_maxcnt;
   int nsv() const { return (int)fcol.size(); }
+  int nfpass() const { return (int)fpass_ptr.size() - 1; }
+  int nbpass() const { return (int)bpass_ptr.size() - 1; }
   int nlf() const { return (int)flev_ptr.size() - 1; }
   int nlb() const { return (int)blev_ptr.size() - 1; }
 };

@@ -69,6 +69,7 @@ struct emt_ctx {
   double *d_stage = nullptr;  // staging for set_state currents
   std::vector<emt::ItemDesc> items;
   bool sm_fwd = true, sm_adj = true, ks_adj_ok = true;
+  int bpt_global = 0;
   int max_tail = 0, dense_items = 0, sweep_levels = 0, lds_limit = 0;
   int64_t step = 0;
   bool factored = false;
@@ -101,9 +102,9 @@ int env_int(const char *name, int dflt) {
   return s ? std::atoi(s) : dflt;
 }
 
-// Largest dense tail whose inverse fits the lanes of one workgroup with at
-// most 16 entries per lane: d <= 4 sqrt(block size).
-int tail_max(int bs) { return bs >= 1024 ? 128 : (bs >= 256 ? 64 : 32); }
+// Largest dense tail whose inverse fits the lanes of one workgroup: 16
+// entries per lane up to 256 lanes (d <= 4 sqrt(lanes)), 32 with 512 lanes.
+int tail_max(int bs) { return bs >= 512 ? 128 : (bs >= 256 ? 64 : 32); }
 
 int tpr_of(int d, int bs) {
   int t = 64;
@@ -161,9 +162,17 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
 }
 
 static emt::LdsShape shape_of(const emt::Item &it, const emt::Symbolic &S, const emt::SweepPlan &P) {
-  return emt::LdsShape{it.n, P.d, P.ns, it.n_br, it.n_src, P.nsv(), P.nlf(), P.nlb(), it.nptr[it.n],
-                       (int)it.rec_node.size()};
   (void)S;
+  return emt::LdsShape{it.n, P.d, P.ns, it.n_br, it.n_src, P.nsv(), (int)P.fdesc.size(), (int)P.bdesc.size(),
+                       it.nptr[it.n], (int)it.rec_node.size()};
+}
+
+// log2 of the lanes that share one row in a sweep pass: enough lanes that
+// the pass's rows fill the workgroup, but no more than its longest row needs.
+static int pass_lanes_log2(int rows, int maxcnt, int bs) {
+  int lg = 0;
+  while (lg < 6 && (rows << (lg + 1)) <= bs && (1 << lg) < maxcnt) ++lg;
+  return lg;
 }
 
 static void upload_all(emt_ctx &c, const emt_net *nets) {
@@ -190,24 +199,27 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   int max_lds = 65536;
   (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
   c.lds_limit = max_lds;
+  // The smallest workgroup that holds the largest component's branches with
+  // at most 8 per lane (12 with 512 lanes); 512 lanes run 2 waves per SIMD,
+  // which leaves 256 VGPRs per lane for the branch state and tail inverse.
   int bs = env_int("EMT_BLOCK", 0);
-  if (bs != 64 && bs != 256 && bs != 1024) {
-    bs = 1024;
-    for (int cand : {64, 256, 1024})
+  if (bs != 64 && bs != 256 && bs != 512) {
+    bs = 512;
+    for (int cand : {64, 256})
       if ((max_nbr + cand - 1) / cand <= 8) {
         bs = cand;
         break;
       }
   }
-  int bpt = 1;
-  for (int cand : {1, 2, 4, 6, 8, 16}) {
-    bpt = cand;
-    if (cand * bs >= max_nbr) break;
-  }
-  if (bpt * bs < max_nbr) bpt = 32;
-  if (bpt > 16)
+  int bpt = 0;
+  for (int cand : {1, 2, 4, 6, 8, 12, 16})
+    if (cand * bs >= max_nbr) {
+      bpt = cand;
+      break;
+    }
+  if (bpt == 0)
     throw Error{EMT_EINVAL, "a connected component has " + std::to_string(max_nbr) +
-                                " branches; the step kernel holds at most 16 per lane"};
+                                " branches; the step kernel holds at most " + std::to_string(16 * bs)};
   c.ks.bs = bs;
   c.ks.bpt = bpt;
   c.ks.dmax = tail_max(bs);
@@ -240,11 +252,15 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     if (d > 0) wpt = std::max(wpt, (d + tpr_of(d, bs) - 1) / tpr_of(d, bs));
     if (plans[it.sym].nsv() > 65535) throw Error{EMT_EINVAL, "a connected component's factor is too large"};
   }
-  c.ks.wpt = wpt <= 4 ? 4 : 16;
-  if (wpt > 16) throw Error{EMT_EINVAL, "internal: dense tail too large for the block size"};
+  c.ks.wpt = wpt <= 4 ? 4 : (wpt <= 16 ? 16 : 32);
+  if (wpt > 32 || (wpt > 16 && bs < 512)) throw Error{EMT_EINVAL, "internal: dense tail too large for the block size"};
   const int force_sm = env_int("EMT_LDS_STAGE", -1);
   c.sm_fwd = f_sm <= (size_t)max_lds && force_sm != 0;
   c.sm_adj = a_sm <= (size_t)max_lds && force_sm != 0;
+  if (!c.sm_fwd || !c.sm_adj) {
+    // the global-memory variants exist for 4, 8 and 16 branches per lane
+    c.bpt_global = bpt <= 4 ? 4 : (bpt <= 8 ? 8 : 16);
+  }
   c.ks.lds_fwd = c.sm_fwd ? f_sm : f_gl;
   c.ks.lds_adj = c.sm_adj ? a_sm : a_gl;
   if (f_gl > (size_t)max_lds) throw Error{EMT_EINVAL, "a connected component needs more LDS than a workgroup has"};
@@ -253,6 +269,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // Symbolic arrays.
   std::vector<int32_t> symi;
   std::vector<uint16_t> symh;
+  std::vector<uint64_t> symd;
   std::vector<SymDesc> sdesc;
   auto put = [&symi](const std::vector<int> &v) {
     const int64_t off = (int64_t)symi.size();
@@ -265,6 +282,16 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     return off;
   };
   int max_tail = 0;
+  auto passes = [&](const std::vector<int> &ptr, const std::vector<int> &maxcnt) {
+    std::vector<int> v;
+    for (size_t k = 0; k + 1 < ptr.size(); ++k) {
+      v.push_back(ptr[k]);
+      v.push_back(pass_lanes_log2(ptr[k + 1] - ptr[k], maxcnt[k], bs));
+    }
+    v.push_back(ptr.back());
+    v.push_back(0);
+    return v;
+  };
   for (size_t q = 0; q < A.syms.size(); ++q) {
     const Symbolic &S = A.syms[q];
     const SweepPlan &P = plans[q];
@@ -274,9 +301,11 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.ns = P.ns;
     d.nnz = (int32_t)S.nnz();
     d.nsv = P.nsv();
-    d.nlf = P.nlf();
-    d.nlb = P.nlb();
+    d.nfpass = P.nfpass();
+    d.nbpass = P.nbpass();
     d.nlev = S.levels_f();
+    d.nfdesc = (int32_t)P.fdesc.size();
+    d.nbdesc = (int32_t)P.bdesc.size();
     d.rowptr = put(S.lrow_ptr);
     d.rowcol = put(S.lrow_col);
     d.colptr = put(S.lcol_ptr);
@@ -287,15 +316,15 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.fentptr = put(S.fent_ptr);
     d.fent = put(S.fent);
     d.svmap = put(P.svmap);
-    d.frowptr = put(P.frow_ptr);
-    d.bptr = put(P.bptr);
-    d.sflevptr = put(P.flev_ptr);
-    d.sblevptr = put(P.blev_ptr);
+    d.fpass = put(passes(P.fpass_ptr, P.fpass_maxcnt));
+    d.bpass = put(passes(P.bpass_ptr, P.bpass_maxcnt));
     d.fcol = puth(P.fcol);
     d.brow = puth(P.brow);
     d.bpos = puth(P.bpos);
-    d.sflevrows = puth(P.flev_rows);
-    d.sblevrows = puth(P.blev_rows);
+    d.fdesc = (int64_t)symd.size();
+    symd.insert(symd.end(), P.fdesc.begin(), P.fdesc.end());
+    d.bdesc = (int64_t)symd.size();
+    symd.insert(symd.end(), P.bdesc.begin(), P.bdesc.end());
     sdesc.push_back(d);
     max_tail = std::max(max_tail, P.d);
   }
@@ -428,6 +457,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.syms = c.upload(sdesc);
   dc.symi = c.upload(symi);
   dc.symh = c.upload(symh);
+  dc.symd = c.upload(symd);
   dc.bpack = c.upload(bpack);
   dc.bk = c.upload(bk);
   dc.bm = c.upload(bm);
@@ -492,26 +522,28 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // statistics
   c.sweep_levels = 0;
   for (const Item &it : A.items)
-    c.sweep_levels = std::max(c.sweep_levels, plans[it.sym].nlf() + plans[it.sym].nlb() + (plans[it.sym].d > 0 ? 2 : 0));
+    c.sweep_levels = std::max(c.sweep_levels, plans[it.sym].nfpass() + plans[it.sym].nbpass() + (plans[it.sym].d > 0 ? 1 : 0));
 }
 
 static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
   emt::KernelShape ks = c.ks;
   ks.sm = c.sm_fwd;
+  if (!ks.sm) ks.bpt = c.bpt_global;
   switch (ks.bs) {
     case 64: return emt::launch_forward_bs64(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
     case 256: return emt::launch_forward_bs256(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
-    default: return emt::launch_forward_bs1024(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
+    default: return emt::launch_forward_bs512(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
   }
 }
 
 static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
   emt::KernelShape ks = c.ks;
   ks.sm = c.sm_adj;
+  if (!ks.sm) ks.bpt = c.bpt_global;
   switch (ks.bs) {
     case 64: return emt::launch_adjoint_bs64(c.dc, ks, c.d_order, c.n_items, dJ, st);
     case 256: return emt::launch_adjoint_bs256(c.dc, ks, c.d_order, c.n_items, dJ, st);
-    default: return emt::launch_adjoint_bs1024(c.dc, ks, c.d_order, c.n_items, dJ, st);
+    default: return emt::launch_adjoint_bs512(c.dc, ks, c.d_order, c.n_items, dJ, st);
   }
 }
 

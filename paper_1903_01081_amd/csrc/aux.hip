@@ -291,14 +291,13 @@ __global__ void k_grad(DevCtx c, const int32_t *lptr, const int64_t *lent, const
 // ---------------------------------------------------------------------------
 
 size_t lds_bytes(const LdsShape &s, bool sm, bool adjoint) {
-  size_t dbl = (size_t)s.n + s.nbr + s.d + s.nsrc + (adjoint ? s.n : 0);
-  size_t i32 = 0, u16 = 0;
+  auto arr = [](size_t cnt, size_t size) { return (cnt * size + 15) & ~(size_t)15; };
+  size_t b = arr(s.d + 1, 8) + arr(s.n, 8) + arr(s.nbr, 8) + arr(s.nsrc, 8) + arr(adjoint ? s.n : 0, 8);
   if (sm) {
-    dbl += (size_t)s.nsv + s.ns;
-    i32 = (size_t)(s.n + 1) + (s.ns + 1) + (s.nlf + 1) + (s.nlb + 1) + (s.n + 1) + (adjoint ? s.n + 1 : 0);
-    u16 = 3 * (size_t)s.nsv + 2 * (size_t)s.ns + s.nent + 2 * (size_t)s.nrec;
+    b += arr(s.nsv, 8) + arr(s.ns, 8) + arr(s.nfdesc, 8) + arr(s.nbdesc, 8) + arr(s.n + 1, 4) +
+         arr(adjoint ? s.n + 1 : 0, 4) + 3 * arr(s.nsv, 2) + arr(s.nent, 2) + 2 * arr(s.nrec, 2);
   }
-  return 8 * dbl + 4 * i32 + 2 * u16 + 16;
+  return b;
 }
 
 static unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

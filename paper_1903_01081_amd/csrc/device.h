@@ -20,14 +20,18 @@ enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2 };
 // Symbolic factor and sweep plan (shared by isomorphic items). Offsets index
 // DevCtx::symi (int32) or DevCtx::symh (uint16).
 struct SymDesc {
-  int32_t n, d, ns, nnz;      // nodes, dense-tail size, leading size, nonzeros of L
-  int32_t nsv, nlf, nlb, nlev;  // sweep entries, sweep levels, factor levels
+  int32_t n, d, ns, nnz;        // nodes, dense-tail size, leading size, nonzeros of L
+  int32_t nsv, nfpass, nbpass, nlev;  // sweep entries, sweep passes, factor levels
+  int32_t nfdesc, nbdesc, pad0, pad1;  // row descriptors of the passes
   // int32 (symi): full factor structure for the numeric factorisation
   int64_t rowptr, rowcol, colptr, colrow, colpos, flevptr, flevrows, fentptr, fent;
-  // int32 (symi): sweep plan
-  int64_t svmap, frowptr, bptr, sflevptr, sblevptr;
+  // int32 (symi): sweep plan: sv entry -> L entry; per pass (first row
+  // descriptor, log2 lanes per row) pairs, nfpass+1 / nbpass+1 of them
+  int64_t svmap, fpass, bpass;
   // uint16 (symh): sweep plan
-  int64_t fcol, brow, bpos, sflevrows, sblevrows;
+  int64_t fcol, brow, bpos;
+  // uint64 (symd): row descriptors (row | first << 16 | count << 32)
+  int64_t fdesc, bdesc;
 };
 
 struct ItemDesc {
@@ -53,6 +57,7 @@ struct DevCtx {
   const SymDesc *syms;
   const int32_t *symi;
   const uint16_t *symh;
+  const uint64_t *symd;
   // per item-branch arrays (ItemDesc::br + local branch)
   const uint32_t *bpack;
   const int32_t *bk, *bm, *bkind, *bline, *bgpos;

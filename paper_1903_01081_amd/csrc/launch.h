@@ -12,14 +12,14 @@ namespace emt {
 
 // Sizes that decide an item's LDS footprint in the step kernels.
 struct LdsShape {
-  int n, d, ns, nbr, nsrc, nsv, nlf, nlb, nent, nrec;
+  int n, d, ns, nbr, nsrc, nsv, nfdesc, nbdesc, nent, nrec;
 };
 
 // Launch shape of the step kernels, chosen once per context.
 struct KernelShape {
-  int bs = 256;    // threads per workgroup (64, 256 or 1024)
-  int bpt = 1;     // branches per lane (1, 2, 4, 6, 8, 16)
-  int wpt = 4;     // tail-inverse entries per lane (4 or 16)
+  int bs = 256;    // threads per workgroup (64, 256 or 512)
+  int bpt = 1;     // branches per lane (1, 2, 4, 6, 8, 12, 16)
+  int wpt = 4;     // tail-inverse entries per lane (4, 16 or 32)
   bool sm = true;  // index arrays and factors staged in LDS
   size_t lds_fwd = 0, lds_adj = 0;
   int dmax = 0;    // largest dense tail this block size supports
@@ -37,14 +37,14 @@ hipError_t launch_forward_bs64(const DevCtx &, const KernelShape &, const int32_
                                double *, hipStream_t);
 hipError_t launch_forward_bs256(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
                                 double *, hipStream_t);
-hipError_t launch_forward_bs1024(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
-                                 double *, hipStream_t);
+hipError_t launch_forward_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, int64_t, int64_t,
+                                double *, hipStream_t);
 hipError_t launch_adjoint_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                hipStream_t);
 hipError_t launch_adjoint_bs256(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                 hipStream_t);
-hipError_t launch_adjoint_bs1024(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
-                                 hipStream_t);
+hipError_t launch_adjoint_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                hipStream_t);
 
 hipError_t launch_factor(const DevCtx &c, const int32_t *pairs, int n_pairs, int max_tail, hipStream_t st);
 hipError_t launch_companions(const DevCtx &c, const CompanionArgs &a, hipStream_t st);

@@ -5,21 +5,24 @@
 // for many time steps; scenarios and components are more workgroups of the
 // same launch. This is the paper's pair of parallel strategies (Sec. III-B):
 // the processes of one layer run together and the layers are replayed in
-// order every step; isomorphic scenarios run the same processes side by side.
-// Each step runs the four basic processes of an EMTP-type solver that the
-// paper lists (Sec. III-A), separated by workgroup barriers:
-//   1. branch phase (one branch per lane, coefficients and history in VGPRs):
-//        source EMF e, branch injection J = g*e - h into LDS;
-//   2. forward sweep: each row gathers its nodal injection from its incident
-//        branch ends in a fixed (CSR) order — a deterministic segmented sum,
-//        no atomics — and solves L y = rhs level by level over the leading
-//        part of the elimination order; the dense tail rows gather
-//        c = rhs_D - L_DS y_S;
-//   3. tail: x_D = W c with W = (L_DD D_D L_DD^T)^{-1} held in VGPRs (a
-//        dense matrix-vector product reduced across lanes with shuffles);
-//      backward sweep: x = D^{-1} y - L^T x level by level;
-//   4. branch phase: u = A^T v - e, i = g*u + h, next history
-//        h = beta*i + gamma*u; record and checkpoint.
+// order every step; isomorphic scenarios run the same processes side by
+// side. A step runs the four basic processes of an EMTP-type solver that the
+// paper lists (Sec. III-A) as barrier-separated phases:
+//   branch phase  (one branch per lane slot; coefficients and history in
+//                 VGPRs): u = A^T v - e and i = g u + h of the previous step,
+//                 the next history h = beta i + gamma u, the source EMF e and
+//                 the branch injection J = g e - h into LDS;
+//   gather        every node sums its incident branch ends' J in a fixed
+//                 (CSR) order — a deterministic segmented sum, no atomics;
+//   forward       L y = rhs over the leading part of the elimination order,
+//                 one pass per level (level 0 needs none), then the dense
+//                 tail's reduced right-hand side c = rhs_D - L_DS y_S;
+//   tail          x_D = W c, W = (L_DD D_D L_DD^T)^{-1} held in VGPRs;
+//   backward      x = D^{-1} y - L^T x, one pass per level.
+// In a sweep pass each row is shared by 2^k adjacent lanes (k per pass, so
+// that a few long rows at the top of the tree use many lanes and many short
+// rows one lane each); the lanes' partial sums meet in a fixed butterfly of
+// shuffles, so every run rounds identically.
 // All factors of every topology are computed before the loop (k_factor,
 // k_tail); a switching event swaps coefficients and factor pointers.
 //
@@ -55,14 +58,23 @@ __device__ __forceinline__ int topo_of(const int64_t *topo, int ntopo, int64_t n
   return t;
 }
 
-// The lane index, hidden from the optimiser once per time step so that the
-// per-branch index and address arithmetic is recomputed inside the loop
-// (a few integer operations) instead of being hoisted out of it and held in
-// VGPRs for every branch of the lane.
+// The lane index, hidden from the optimiser at each use so that per-slot
+// index and address arithmetic is recomputed inside the time loop (a few
+// integer operations) instead of being hoisted out of it and held in VGPRs.
 __device__ __forceinline__ int lane_id() {
   int t = (int)threadIdx.x;
   asm volatile("" : "+v"(t));
   return t;
+}
+
+// Workgroup barrier that orders LDS only. Lanes of a workgroup exchange
+// data only through LDS here; global stores (recorded outputs, checkpoints,
+// state) are read by later kernels or by the same lane, so a barrier need
+// not wait for them to complete as __syncthreads() would.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Dynamic LDS of the step kernels (addressed with 32-bit offsets so that
@@ -90,49 +102,37 @@ struct Lds {
   __device__ __forceinline__ T &operator[](int i) const { return reinterpret_cast<T *>(emt_lds + off)[i]; }
 };
 
-// Per-workgroup view of an item. Index arrays and factor values live in LDS
-// (SM = true) or are read from global memory.
+// Per-workgroup view of an item: sizes, LDS arrays, and the sweep data in
+// LDS (SM = true) or global memory.
 template <bool SM>
 struct View {
-  int n, d, ns, nbr, nsrc, nsv, nlf, nlb, nrec, tpr;
-  Ref<int32_t, SM> frowptr, bptr, flevptr, blevptr, nptr, rptr;
-  Ref<uint16_t, SM> fcol, brow, bpos, flevrows, blevrows, nent, rnode, rcolumn;
+  int n, d, ns, nbr, nsrc, nsv, nrec, tpr, wlen;
+  int nfpass, nbpass;
+  const int32_t *fpass, *bpass;  // (first descriptor, log2 lanes) pairs, global
+  Ref<uint64_t, SM> fdesc, bdesc;
+  Ref<uint16_t, SM> fcol, brow, bpos, nent, rnode, rcolumn;
+  Ref<int32_t, SM> nptr, rptr;
   Lds<double> x, J, cD, eS, dv, sv_s, dinv_s;
   Ref<double, SM> sv, dinv;
 };
 
-// Threads per tail row: the largest power of two (<= 64, one wave) with
-// d * tpr <= block size.
+// Tail rows are split into tpr lanes of contiguous columns: tpr = the
+// largest power of two (<= 64, within one wave) with d * tpr <= block size.
 __device__ __forceinline__ int tail_tpr(int d, int bs) {
   int t = 64;
   while (t > 1 && d * t > bs) t >>= 1;
   return t;
 }
 
-template <int BS>
-__device__ __forceinline__ void copy_i32(int32_t *dst, const int32_t *src, int cnt) {
-  for (int q = threadIdx.x; q < cnt; q += BS) dst[q] = src[q];
-}
-template <int BS>
-__device__ __forceinline__ void copy_u16(uint16_t *dst, const uint16_t *src, int cnt) {
-  for (int q = threadIdx.x; q < cnt; q += BS) dst[q] = src[q];
-}
-template <int BS>
-__device__ __forceinline__ void copy_f64(double *dst, const double *src, int cnt) {
+template <int BS, class T>
+__device__ __forceinline__ void copy_to(uint32_t off, const T *src, int cnt) {
+  T *dst = reinterpret_cast<T *>(emt_lds + off);
   for (int q = threadIdx.x; q < cnt; q += BS) dst[q] = src[q];
 }
 
-// LDS layout: doubles (x, J, cD, eS, [dv], [sv, dinv]), then int32, then
-// uint16. Must match lds_bytes() on the host.
-template <int BS>
-__device__ __forceinline__ void copy_to(uint32_t off, const int32_t *src, int cnt) {
-  copy_i32<BS>(reinterpret_cast<int32_t *>(emt_lds + off), src, cnt);
-}
-template <int BS>
-__device__ __forceinline__ void copy_to(uint32_t off, const uint16_t *src, int cnt) {
-  copy_u16<BS>(reinterpret_cast<uint16_t *>(emt_lds + off), src, cnt);
-}
-
+// LDS layout (byte offsets from emt_lds, each array 16-byte aligned):
+// cD, x, J, eS, [dv], then under SM sv, dinv, fdesc, bdesc, nptr, [rptr],
+// fcol, brow, bpos, nent, rnode, rcolumn. Must match lds_bytes() on the host.
 template <int BS, bool SM>
 __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint) {
   const SymDesc sd = c.syms[it.sym];
@@ -143,175 +143,233 @@ __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint)
   v.nbr = it.n_br;
   v.nsrc = it.n_src;
   v.nsv = sd.nsv;
-  v.nlf = sd.nlf;
-  v.nlb = sd.nlb;
   v.nrec = it.n_rec;
   v.tpr = tail_tpr(sd.d, BS);
-  const int32_t *g_frowptr = c.symi + sd.frowptr, *g_bptr = c.symi + sd.bptr;
-  const int32_t *g_flevptr = c.symi + sd.sflevptr, *g_blevptr = c.symi + sd.sblevptr;
-  const int32_t *g_nptr = c.nptr + it.nptr, *g_rptr = c.rptr + it.nptr;
+  v.wlen = (sd.d + v.tpr - 1) / v.tpr;
+  v.nfpass = sd.nfpass;
+  v.nbpass = sd.nbpass;
+  v.fpass = c.symi + sd.fpass;
+  v.bpass = c.symi + sd.bpass;
+  const uint64_t *g_fdesc = c.symd + sd.fdesc, *g_bdesc = c.symd + sd.bdesc;
   const uint16_t *g_fcol = c.symh + sd.fcol, *g_brow = c.symh + sd.brow, *g_bpos = c.symh + sd.bpos;
-  const uint16_t *g_flevrows = c.symh + sd.sflevrows, *g_blevrows = c.symh + sd.sblevrows;
+  const int32_t *g_nptr = c.nptr + it.nptr, *g_rptr = c.rptr + it.nptr;
   const uint16_t *g_nent = c.nent + it.nent, *g_rnode = c.rnode + it.rec, *g_rcolumn = c.rcolumn + it.rec;
   const int nent_cnt = g_nptr[v.n];
 
   uint32_t off = 0;
   auto take = [&off](int cnt, int size) {
     const uint32_t o = off;
-    off += (uint32_t)cnt * (uint32_t)size;
+    off += ((uint32_t)cnt * (uint32_t)size + 15u) & ~15u;
     return o;
   };
+  v.cD.off = take(v.d + 1, 8);
   v.x.off = take(v.n, 8);
   v.J.off = take(v.nbr, 8);
-  v.cD.off = take(v.d, 8);
   v.eS.off = take(v.nsrc, 8);
   v.dv.off = take(adjoint ? v.n : 0, 8);
+  if (threadIdx.x == 0) v.cD[v.d] = 0.0;  // spare slot read by the last pair of the tail product
   if constexpr (SM) {
     v.sv_s.off = take(v.nsv, 8);
     v.dinv_s.off = take(v.ns, 8);
-    v.frowptr.off = take(v.n + 1, 4);
-    v.bptr.off = take(v.ns + 1, 4);
-    v.flevptr.off = take(v.nlf + 1, 4);
-    v.blevptr.off = take(v.nlb + 1, 4);
+    v.fdesc.off = take(sd.nfdesc, 8);
+    v.bdesc.off = take(sd.nbdesc, 8);
     v.nptr.off = take(v.n + 1, 4);
     v.rptr.off = take(adjoint ? v.n + 1 : 0, 4);
     v.fcol.off = take(v.nsv, 2);
     v.brow.off = take(v.nsv, 2);
     v.bpos.off = take(v.nsv, 2);
-    v.flevrows.off = take(v.ns, 2);
-    v.blevrows.off = take(v.ns, 2);
     v.nent.off = take(nent_cnt, 2);
     v.rnode.off = take(v.nrec, 2);
     v.rcolumn.off = take(v.nrec, 2);
-    copy_to<BS>(v.frowptr.off, g_frowptr, v.n + 1);
-    copy_to<BS>(v.bptr.off, g_bptr, v.ns + 1);
-    copy_to<BS>(v.flevptr.off, g_flevptr, v.nlf + 1);
-    copy_to<BS>(v.blevptr.off, g_blevptr, v.nlb + 1);
+    copy_to<BS>(v.fdesc.off, g_fdesc, sd.nfdesc);
+    copy_to<BS>(v.bdesc.off, g_bdesc, sd.nbdesc);
     copy_to<BS>(v.nptr.off, g_nptr, v.n + 1);
     if (adjoint) copy_to<BS>(v.rptr.off, g_rptr, v.n + 1);
     copy_to<BS>(v.fcol.off, g_fcol, v.nsv);
     copy_to<BS>(v.brow.off, g_brow, v.nsv);
     copy_to<BS>(v.bpos.off, g_bpos, v.nsv);
-    copy_to<BS>(v.flevrows.off, g_flevrows, v.ns);
-    copy_to<BS>(v.blevrows.off, g_blevrows, v.ns);
     copy_to<BS>(v.nent.off, g_nent, nent_cnt);
     copy_to<BS>(v.rnode.off, g_rnode, v.nrec);
     copy_to<BS>(v.rcolumn.off, g_rcolumn, v.nrec);
     v.sv.off = v.sv_s.off;
     v.dinv.off = v.dinv_s.off;
   } else {
-    v.frowptr.p = g_frowptr; v.bptr.p = g_bptr; v.flevptr.p = g_flevptr; v.blevptr.p = g_blevptr;
-    v.nptr.p = g_nptr; v.rptr.p = g_rptr;
-    v.fcol.p = g_fcol; v.brow.p = g_brow; v.bpos.p = g_bpos; v.flevrows.p = g_flevrows;
-    v.blevrows.p = g_blevrows; v.nent.p = g_nent; v.rnode.p = g_rnode; v.rcolumn.p = g_rcolumn;
+    v.fdesc.p = g_fdesc;
+    v.bdesc.p = g_bdesc;
+    v.fcol.p = g_fcol;
+    v.brow.p = g_brow;
+    v.bpos.p = g_bpos;
+    v.nptr.p = g_nptr;
+    v.rptr.p = g_rptr;
+    v.nent.p = g_nent;
+    v.rnode.p = g_rnode;
+    v.rcolumn.p = g_rcolumn;
   }
   return v;
 }
 
 // Factor values and the tail inverse of topology t (sweep values and 1/D in
-// LDS under SM; the lane's share of W in VGPRs).
+// LDS under SM; the lane's contiguous share of its tail row of W in VGPRs).
 template <int BS, int WPT, bool SM>
 __device__ __forceinline__ void select_factor(const DevCtx &c, const ItemDesc &it, View<SM> &v, int t,
                                               double (&w)[WPT]) {
   const double *sv = c.svals + it.sv + (int64_t)t * v.nsv;
   const double *di = c.dinv + it.dfac + (int64_t)t * v.n;
   if constexpr (SM) {
-    copy_f64<BS>(reinterpret_cast<double *>(emt_lds + v.sv_s.off), sv, v.nsv);
-    copy_f64<BS>(reinterpret_cast<double *>(emt_lds + v.dinv_s.off), di, v.ns);
+    copy_to<BS>(v.sv_s.off, sv, v.nsv);
+    copy_to<BS>(v.dinv_s.off, di, v.ns);
   } else {
     v.sv.p = sv;
     v.dinv.p = di;
   }
   const double *W = c.wtail + it.w + (int64_t)t * v.d * v.d;
-  const int row = threadIdx.x / v.tpr, lane = threadIdx.x % v.tpr;
+  const int tid = lane_id();
+  const int row = tid / v.tpr, col0 = (tid % v.tpr) * v.wlen;
 #pragma unroll
   for (int q = 0; q < WPT; ++q) {
-    const int col = lane + q * v.tpr;
-    w[q] = (row < v.d && col < v.d) ? W[row * v.d + col] : 0.0;
+    const int col = col0 + q;
+    w[q] = (row < v.d && q < v.wlen && col < v.d) ? W[row * v.d + col] : 0.0;
   }
 }
 
-template <bool ADJ, bool SM>
-__device__ __forceinline__ double gather(const View<SM> &v, int r) {
-  double acc = 0.0;
-  const int e1 = v.nptr[r + 1];
-  for (int e = v.nptr[r]; e < e1; ++e) {
-    const int ent = v.nent[e];
-    const double jv = v.J[ent >> 1];
-    acc = (ent & 1) ? acc - jv : acc + jv;
-  }
-  if (ADJ) acc = acc + v.dv[r];
-  return acc;
-}
-
-// Forward sweep over the leading rows, then the tail rows' reduced
-// right-hand side c = rhs_D - L_DS y_S (into cD).
+// Gather: x_r = sum of the signed branch injections at node r (+ dv_r in the
+// adjoint), for every node; loads run four entries ahead of the in-order sum.
 template <int BS, bool ADJ, bool SM>
-__device__ __forceinline__ void sweep_forward(const View<SM> &v) {
-  for (int l = 0; l < v.nlf; ++l) {
-    const int p1 = v.flevptr[l + 1];
-    for (int p = v.flevptr[l] + (int)threadIdx.x; p < p1; p += BS) {
-      const int r = v.flevrows[p];
-      double acc = gather<ADJ, SM>(v, r);
-      const int q1 = v.frowptr[r + 1];
-      for (int q = v.frowptr[r]; q < q1; ++q) acc = acc - v.sv[q] * v.x[v.fcol[q]];
-      v.x[r] = acc;
+__device__ __forceinline__ void gather_all(const View<SM> &v) {
+  for (int r = lane_id(); r < v.n; r += BS) {
+    double acc = 0.0;
+    int e = v.nptr[r];
+    const int e1 = v.nptr[r + 1];
+    for (; e + 4 <= e1; e += 4) {
+      const int n0 = v.nent[e], n1 = v.nent[e + 1], n2 = v.nent[e + 2], n3 = v.nent[e + 3];
+      const double j0 = v.J[n0 >> 1], j1 = v.J[n1 >> 1], j2 = v.J[n2 >> 1], j3 = v.J[n3 >> 1];
+      acc = (n0 & 1) ? acc - j0 : acc + j0;
+      acc = (n1 & 1) ? acc - j1 : acc + j1;
+      acc = (n2 & 1) ? acc - j2 : acc + j2;
+      acc = (n3 & 1) ? acc - j3 : acc + j3;
     }
-    __syncthreads();
-  }
-  if (v.d > 0) {
-    for (int a = threadIdx.x; a < v.d; a += BS) {
-      const int r = v.ns + a;
-      double acc = gather<ADJ, SM>(v, r);
-      const int q1 = v.frowptr[r + 1];
-      for (int q = v.frowptr[r]; q < q1; ++q) acc = acc - v.sv[q] * v.x[v.fcol[q]];
-      v.cD[a] = acc;
+    for (; e < e1; ++e) {
+      const int ent = v.nent[e];
+      const double jv = v.J[ent >> 1];
+      acc = (ent & 1) ? acc - jv : acc + jv;
     }
-    __syncthreads();
+    if (ADJ) acc = acc + v.dv[r];
+    v.x[r] = acc;
   }
+  lds_barrier();
 }
 
-// x_D = W c: each tail row is shared by tpr adjacent lanes of one wave; the
-// partial dot products are combined by a fixed butterfly of shuffles.
+// Butterfly sum over the 2^lg lanes of a row group (fixed order).
+__device__ __forceinline__ double group_sum(double s, int lg) {
+  for (int k = 0; k < lg; ++k) s = s + __shfl_xor(s, 1 << k);
+  return s;
+}
+
+// One forward pass: for each row descriptor (r, q0, cnt) the row's lanes
+// sum sv[q] x[fcol[q]] over their strided entries; out[r - shift] =
+// x[r] - sum (out = x for the leading levels, cD with shift ns for the tail
+// rows).
+template <int BS, bool SM>
+__device__ __forceinline__ void forward_pass(const View<SM> &v, int p0, int p1, int lg, uint32_t out_off,
+                                             int shift) {
+  const int tid = lane_id();
+  const int G = 1 << lg, sub = tid & (G - 1);
+  for (int p = p0 + (tid >> lg); p < p1; p += (BS >> lg)) {
+    const uint64_t dsc = v.fdesc[p];
+    const int r = (int)(dsc & 0xFFFF), q0 = (int)((dsc >> 16) & 0xFFFF), cnt = (int)(dsc >> 32);
+    const double xr = v.x[r];
+    double s = 0.0;
+    int q = q0 + sub;
+    const int q1 = q0 + cnt;
+    for (; q + G < q1; q += 2 * G) {
+      const int c0 = v.fcol[q], c1 = v.fcol[q + G];
+      const double a0 = v.sv[q], a1 = v.sv[q + G];
+      const double x0 = v.x[c0], x1 = v.x[c1];
+      s = s + a0 * x0;
+      s = s + a1 * x1;
+    }
+    if (q < q1) s = s + v.sv[q] * v.x[v.fcol[q]];
+    s = group_sum(s, lg);
+    if (sub == 0) reinterpret_cast<double *>(emt_lds + out_off)[r - shift] = xr - s;
+  }
+  lds_barrier();
+}
+
+// One backward pass: x_r = x_r / D_r - sum over the row's column entries of
+// sv[bpos[q]] x[brow[q]].
+template <int BS, bool SM>
+__device__ __forceinline__ void backward_pass(const View<SM> &v, int p0, int p1, int lg) {
+  const int tid = lane_id();
+  const int G = 1 << lg, sub = tid & (G - 1);
+  for (int p = p0 + (tid >> lg); p < p1; p += (BS >> lg)) {
+    const uint64_t dsc = v.bdesc[p];
+    const int r = (int)(dsc & 0xFFFF), q0 = (int)((dsc >> 16) & 0xFFFF), cnt = (int)(dsc >> 32);
+    const double xr = v.x[r] * v.dinv[r];
+    double s = 0.0;
+    int q = q0 + sub;
+    const int q1 = q0 + cnt;
+    for (; q + G < q1; q += 2 * G) {
+      const int i0 = v.bpos[q], i1 = v.bpos[q + G];
+      const int r0 = v.brow[q], r1 = v.brow[q + G];
+      const double a0 = v.sv[i0], a1 = v.sv[i1];
+      const double x0 = v.x[r0], x1 = v.x[r1];
+      s = s + a0 * x0;
+      s = s + a1 * x1;
+    }
+    if (q < q1) s = s + v.sv[v.bpos[q]] * v.x[v.brow[q]];
+    s = group_sum(s, lg);
+    if (sub == 0) v.x[r] = xr - s;
+  }
+  lds_barrier();
+}
+
+// x_D = W c: each tail row is shared by tpr adjacent lanes of one wave, lane
+// k owning the contiguous columns [k*wlen, (k+1)*wlen).
 template <int BS, int WPT, bool SM>
 __device__ __forceinline__ void tail_solve(const View<SM> &v, const double (&w)[WPT]) {
-  if (v.d == 0) return;
   const int tid = lane_id();
-  const int row = tid / v.tpr, lane = tid % v.tpr;
+  const int row = tid / v.tpr, col0 = (tid % v.tpr) * v.wlen;
+  const double *cD = reinterpret_cast<const double *>(emt_lds + v.cD.off);
   double s = 0.0;
   if (row < v.d) {
+    if ((v.wlen & 1) == 0) {
+      // pairs: both columns of a pair are < d or both >= d up to the spare
+      // slot of cD, whose product with a zero W entry is zero
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-      const int col = lane + q * v.tpr;
-      if (col < v.d) s = s + w[q] * v.cD[col];
+      for (int q = 0; q < WPT; q += 2) {
+        if (q < v.wlen && col0 + q < v.d) {
+          const double2 cc = *reinterpret_cast<const double2 *>(cD + col0 + q);
+          s = s + w[q] * cc.x;
+          s = s + w[q + 1] * cc.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < WPT; ++q)
+        if (q < v.wlen && col0 + q < v.d) s = s + w[q] * cD[col0 + q];
     }
   }
-  for (int off = 1; off < v.tpr; off <<= 1) s = s + __shfl_xor(s, off);
-  if (row < v.d && lane == 0) v.x[v.ns + row] = s;
-  __syncthreads();
+  int lg = 0;
+  while ((1 << lg) < v.tpr) ++lg;
+  s = group_sum(s, lg);
+  if (row < v.d && (tid % v.tpr) == 0) v.x[v.ns + row] = s;
+  lds_barrier();
 }
 
-// Backward sweep over the leading rows: x_r = y_r / D_r - sum_c L_cr x_c.
-template <int BS, bool SM>
-__device__ __forceinline__ void sweep_backward(const View<SM> &v) {
-  for (int l = 0; l < v.nlb; ++l) {
-    const int p1 = v.blevptr[l + 1];
-    for (int p = v.blevptr[l] + (int)threadIdx.x; p < p1; p += BS) {
-      const int r = v.blevrows[p];
-      double acc = v.x[r] * v.dinv[r];
-      const int q1 = v.bptr[r + 1];
-      for (int q = v.bptr[r]; q < q1; ++q) acc = acc - v.sv[v.bpos[q]] * v.x[v.brow[q]];
-      v.x[r] = acc;
-    }
-    __syncthreads();
+// The solve after the gather: forward passes, tail, backward passes.
+template <int BS, int WPT, bool SM>
+__device__ __forceinline__ void solve_after_gather(const View<SM> &v, const double (&w)[WPT]) {
+  for (int k = 0; k < v.nfpass; ++k) {
+    const int p0 = v.fpass[2 * k], lg = v.fpass[2 * k + 1], p1 = v.fpass[2 * k + 2];
+    // the last forward pass of an item with a dense tail is the tail rows'
+    const bool tail_rows = v.d > 0 && k == v.nfpass - 1;
+    forward_pass<BS, SM>(v, p0, p1, lg, tail_rows ? v.cD.off : v.x.off, tail_rows ? v.ns : 0);
   }
-}
-
-template <int BS, int WPT, bool ADJ, bool SM>
-__device__ __forceinline__ void solve(const View<SM> &v, const double (&w)[WPT]) {
-  sweep_forward<BS, ADJ, SM>(v);
-  tail_solve<BS, WPT, SM>(v, w);
-  sweep_backward<BS, SM>(v);
+  if (v.d > 0) tail_solve<BS, WPT, SM>(v, w);
+  for (int k = 0; k < v.nbpass; ++k) {
+    const int p0 = v.bpass[2 * k], lg = v.bpass[2 * k + 1], p1 = v.bpass[2 * k + 2];
+    backward_pass<BS, SM>(v, p0, p1, lg);
+  }
 }
 
 // Lane state of the forward loop: coefficients of the current topology and
@@ -363,10 +421,18 @@ __device__ __forceinline__ void history_from_state(const double *si, const doubl
   }
 }
 
+// EMF of step n for branch b of slot j (sources only).
+template <int BPT>
+__device__ __forceinline__ double emf_of(const DevCtx &c, const ItemDesc &it, const Lane<BPT> &L, int j, int b,
+                                         int64_t n) {
+  if (j == 0) return L.sE * emf_cos(L.sw * ((double)n * c.dt) + L.sph);
+  return source_emf(c, it.br + b, n);
+}
+
+// Branch injections of step n: J = g e - h (and e of sources into eS).
 template <int BS, int BPT, bool SM>
 __device__ __forceinline__ void inject(const DevCtx &c, const ItemDesc &it, const View<SM> &v, const Lane<BPT> &L,
                                        int64_t n) {
-  const double tn = (double)n * c.dt;
   const int tid = lane_id();
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
@@ -374,7 +440,7 @@ __device__ __forceinline__ void inject(const DevCtx &c, const ItemDesc &it, cons
     if (b < v.nbr) {
       double e = 0.0;
       if (b < v.nsrc) {
-        e = (j == 0) ? L.sE * emf_cos(L.sw * tn + L.sph) : source_emf(c, it.br + b, n);
+        e = emf_of<BPT>(c, it, L, j, b, n);
         v.eS[b] = e;
       }
       v.J[b] = L.g[j] * e - L.h[j];
@@ -382,13 +448,15 @@ __device__ __forceinline__ void inject(const DevCtx &c, const ItemDesc &it, cons
   }
 }
 
-// Branch update of step n with the current coefficients; optional stores of
-// (i, u) to up to two places (null = none); then, if the next step starts a
-// new topology, its coefficients are loaded before the next history current
-// is formed.
+// Branch phase after the solve of step n: u, i of step n with the current
+// coefficients; optional stores of (i, u) to up to two places (null = none);
+// if step n+1 starts a new topology its coefficients are loaded; the history
+// of step n+1; and, when inj is set, the injections of step n+1.
 template <int BS, int BPT, bool SM>
-__device__ __forceinline__ void update(const DevCtx &c, const View<SM> &v, Lane<BPT> &L, double *st_i, double *st_u,
-                                       double *st2_i, double *st2_u, bool switch_next, int64_t next_coef) {
+__device__ __forceinline__ void update_inject(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
+                                              Lane<BPT> &L, double *st_i, double *st_u, double *st2_i,
+                                              double *st2_u, bool switch_next, int64_t next_coef, bool inj,
+                                              int64_t n) {
   const int tid = lane_id();
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
@@ -414,12 +482,20 @@ __device__ __forceinline__ void update(const DevCtx &c, const View<SM> &v, Lane<
         L.be[j] = c.cb[next_coef + b];
       }
       L.h[j] = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
+      if (inj) {
+        double e1 = 0.0;
+        if (b < v.nsrc) {
+          e1 = emf_of<BPT>(c, it, L, j, b, n + 1);
+          v.eS[b] = e1;
+        }
+        v.J[b] = L.g[j] * e1 - L.h[j];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Forward loop: steps n0+1 .. n0+ns for every item.
+// Forward loop: steps n0+1 .. n0+nsteps for every item.
 // ---------------------------------------------------------------------------
 template <int BS, int BPT, int WPT, bool SM>
 __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, int64_t n0, int64_t nsteps,
@@ -435,16 +511,16 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
   history_from_state<BS, BPT>(c.si + it.br, c.su + it.br, v.nbr, L);
   select_factor<BS, WPT, SM>(c, it, v, t, w);
-  __syncthreads();
+  inject<BS, BPT, SM>(c, it, v, L, n0 + 1);
+  lds_barrier();
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
   for (int64_t n = n0 + 1; n <= n_end; ++n) {
-    inject<BS, BPT, SM>(c, it, v, L, n);
-    __syncthreads();
-    solve<BS, WPT, false, SM>(v, w);
+    gather_all<BS, false, SM>(v);
+    solve_after_gather<BS, WPT, SM>(v, w);
     if (rec) {
       double *row = rec + ((int64_t)it.scen * nsteps + (n - n0 - 1)) * R;
-      for (int q = threadIdx.x; q < v.nrec; q += BS) row[v.rcolumn[q]] = v.x[v.rnode[q]];
+      for (int q = lane_id(); q < v.nrec; q += BS) row[v.rcolumn[q]] = v.x[v.rnode[q]];
     }
     const bool sw = (n + 1 == next);
     double *ck_i = nullptr, *ck_u = nullptr, *st_i = nullptr, *st_u = nullptr;
@@ -457,12 +533,14 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       st_i = c.si + it.br;
       st_u = c.su + it.br;
     }
-    update<BS, BPT, SM>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr);
+    update_inject<BS, BPT, SM>(c, it, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
+                               n < n_end, n);
     if (sw) {
       ++t;
       next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
       select_factor<BS, WPT, SM>(c, it, v, t, w);
     }
+    lds_barrier();
   }
   for (int q = threadIdx.x; q < v.n; q += BS) c.sv_state[it.node + q] = v.x[q];
 }
@@ -477,6 +555,31 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
 //   hbar_n = ibar - A^T w
 //   gbar += hbar_n u_n, betabar += hbar_n i_{n-1}, gammabar += hbar_n u_{n-1}
 // ---------------------------------------------------------------------------
+template <int BS, int BPT, bool SM>
+__device__ __forceinline__ void adjoint_seed(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
+                                             const Lane<BPT> &L, const double (&g_nx)[BPT],
+                                             const double (&be_nx)[BPT], const double (&hb_nx)[BPT],
+                                             double (&ib)[BPT], const double *dJ, int64_t n) {
+  const int tid = lane_id();
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int b = tid + j * BS;
+    if (b < v.nbr) {
+      const double ibar = be_nx[j] * hb_nx[j];
+      ib[j] = ibar;
+      const double ga_nx = gamma_of(L.pk[j], g_nx[j]);
+      v.J[b] = (L.g[j] != 0.0) ? ga_nx * hb_nx[j] + L.g[j] * ibar : 0.0;
+    }
+  }
+  const double *drow = dJ + ((int64_t)it.scen * c.T + (n - 1)) * c.rec_stride;
+  for (int r = tid; r < v.n; r += BS) {
+    double acc = 0.0;
+    const int e1 = v.rptr[r + 1];
+    for (int e = v.rptr[r]; e < e1; ++e) acc = acc + drow[v.rcolumn[e]];
+    v.dv[r] = acc;
+  }
+}
+
 template <int BS, int BPT, int WPT, bool SM>
 __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, const double *dJ) {
   const ItemDesc it = c.items[order[blockIdx.x]];
@@ -484,7 +587,6 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
   const int64_t *topo = c.topo + it.topo;
   const int K = c.K;
   const int64_t T = c.T;
-  const int R = c.rec_stride;
   const int64_t nseg = (T + K - 1) / K;
   double *seg_i = c.seg_i + it.seg, *seg_u = c.seg_u + it.seg;
   const int nbr = v.nbr;
@@ -495,7 +597,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
   double g_nx[BPT], be_nx[BPT], hb_nx[BPT], ib[BPT];
   double gb[BPT], bb[BPT], cb[BPT];
 #pragma unroll
-  for (int j = 0; j < BPT; ++j) g_nx[j] = be_nx[j] = hb_nx[j] = gb[j] = bb[j] = cb[j] = 0.0;
+  for (int j = 0; j < BPT; ++j) g_nx[j] = be_nx[j] = hb_nx[j] = gb[j] = bb[j] = cb[j] = ib[j] = 0.0;
 
   for (int64_t s = nseg - 1; s >= 0; --s) {
     const int64_t lo = s * K, hi = (lo + K < T) ? lo + K : T;
@@ -514,47 +616,33 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
     load_coefs<BS, BPT>(c, it, t, L.g, L.be);
     history_from_state<BS, BPT>(c.ck_i + cko, c.ck_u + cko, nbr, L);
     select_factor<BS, WPT, SM>(c, it, v, t, w);
-    __syncthreads();
+    inject<BS, BPT, SM>(c, it, v, L, lo + 1);
+    lds_barrier();
     for (int64_t n = lo + 1; n <= hi; ++n) {
-      inject<BS, BPT, SM>(c, it, v, L, n);
-      __syncthreads();
-      solve<BS, WPT, false, SM>(v, w);
+      gather_all<BS, false, SM>(v);
+      solve_after_gather<BS, WPT, SM>(v, w);
       const int64_t o = (n - lo) * (int64_t)nbr;
       const bool sw = (n + 1 == next) && n < hi;
-      update<BS, BPT, SM>(c, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw, it.coef + (int64_t)(t + 1) * nbr);
+      update_inject<BS, BPT, SM>(c, it, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw,
+                                 it.coef + (int64_t)(t + 1) * nbr, n < hi, n);
       if (sw) {
         ++t;
         next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
         select_factor<BS, WPT, SM>(c, it, v, t, w);
       }
+      lds_barrier();
     }
     // L.g, L.be and the factors now belong to step hi.
+    adjoint_seed<BS, BPT, SM>(c, it, v, L, g_nx, be_nx, hb_nx, ib, dJ, hi);
+    lds_barrier();
     for (int64_t n = hi; n >= lo + 1; --n) {
+      gather_all<BS, true, SM>(v);
+      solve_after_gather<BS, WPT, SM>(v, w);
+      const int64_t on = (n - lo) * (int64_t)nbr, op = (n - 1 - lo) * (int64_t)nbr;
       const int tid = lane_id();
 #pragma unroll
       for (int j = 0; j < BPT; ++j) {
         const int b = tid + j * BS;
-        if (b < nbr) {
-          const double ibar = be_nx[j] * hb_nx[j];
-          ib[j] = ibar;
-          const double ga_nx = gamma_of(L.pk[j], g_nx[j]);
-          v.J[b] = (L.g[j] != 0.0) ? ga_nx * hb_nx[j] + L.g[j] * ibar : 0.0;
-        }
-      }
-      const double *drow = dJ + ((int64_t)it.scen * T + (n - 1)) * R;
-      for (int r = threadIdx.x; r < v.n; r += BS) {
-        double acc = 0.0;
-        const int e1 = v.rptr[r + 1];
-        for (int e = v.rptr[r]; e < e1; ++e) acc = acc + drow[v.rcolumn[e]];
-        v.dv[r] = acc;
-      }
-      __syncthreads();
-      solve<BS, WPT, true, SM>(v, w);
-      const int64_t on = (n - lo) * (int64_t)nbr, op = (n - 1 - lo) * (int64_t)nbr;
-      const int tid2 = lane_id();
-#pragma unroll
-      for (int j = 0; j < BPT; ++j) {
-        const int b = tid2 + j * BS;
         if (b < nbr) {
           const uint32_t pk = L.pk[j];
           const uint32_t k = pk & kTermGround, m = (pk >> 15) & kTermGround;
@@ -576,9 +664,10 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
           load_coefs<BS, BPT>(c, it, t, L.g, L.be);
           select_factor<BS, WPT, SM>(c, it, v, t, w);
         }
+        adjoint_seed<BS, BPT, SM>(c, it, v, L, g_nx, be_nx, hb_nx, ib, dJ, n - 1);
       }
+      lds_barrier();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {

@@ -40,10 +40,16 @@ hipError_t adj(const DevCtx &c, const int32_t *order, int n_items, const double 
 #define EMT_CAT2(a, b) a##b
 #define EMT_CAT(a, b) EMT_CAT2(a, b)
 
-#define EMT_SHAPES_SM(X, SM) \
-  X(1, 4, SM) X(2, 4, SM) X(4, 4, SM) X(6, 4, SM) X(8, 4, SM) X(16, 4, SM) \
-  X(1, 16, SM) X(2, 16, SM) X(4, 16, SM) X(6, 16, SM) X(8, 16, SM) X(16, 16, SM)
-#define EMT_SHAPES(X) EMT_SHAPES_SM(X, true) EMT_SHAPES_SM(X, false)
+// Branches per lane x tail-inverse entries per lane: LDS-staged variants for
+// every size, global-memory fallbacks for the larger ones.
+#define EMT_SHAPES_W(X, W) \
+  X(1, W, true) X(2, W, true) X(4, W, true) X(6, W, true) X(8, W, true) X(12, W, true) X(16, W, true) \
+  X(4, W, false) X(8, W, false) X(16, W, false)
+#if EMT_BS >= 512
+#define EMT_SHAPES(X) EMT_SHAPES_W(X, 4) EMT_SHAPES_W(X, 16) EMT_SHAPES_W(X, 32)
+#else
+#define EMT_SHAPES(X) EMT_SHAPES_W(X, 4) EMT_SHAPES_W(X, 16)
+#endif
 
 hipError_t EMT_CAT(launch_forward_bs, EMT_BS)(const DevCtx &c, const KernelShape &ks, const int32_t *order,
                                               int n_items, int64_t n0, int64_t ns, double *rec,
