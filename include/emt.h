@@ -103,7 +103,13 @@ typedef struct {
  *   checkpoint_every K: 0 = no checkpoints (emt_adjoint unavailable); else
  *     the forward run stores the branch state every K steps and the adjoint
  *     recomputes each K-step segment from its checkpoint.
- *   solver: EMT_SOLVER_* (AUTO picks per connected component). */
+ *   solver: how each connected component's G v = rhs is solved (Sec. III-A,
+ *     fourth basic process). SPARSE: level-scheduled forward/backward sweeps
+ *     over the LDL^T factor. DENSE: v = G^{-1} rhs with the component's whole
+ *     inverse held by its workgroup; EMT_EINVAL from emt_build when a
+ *     component exceeds the dense limit (128 nodes). AUTO: sweeps over the
+ *     leading rows of the elimination order and the dense inverse of its
+ *     trailing block, cut where a cost model finds fewest dependent phases. */
 typedef struct {
   double dt;
   int64_t n_steps;

@@ -478,6 +478,7 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       it_.br = srcs;
       it_.br.insert(it_.br.end(), rest.begin(), rest.end());
       it_.n_br = (int)it_.br.size();
+      it_.n_br_real = it_.n_br;
       it_.bk.resize(it_.n_br);
       it_.bm.resize(it_.n_br);
       it_.gpos.assign(it_.n_br, -1);
@@ -535,9 +536,9 @@ void fill_info(const Analysis &a, emt_info *info) {
   z.max_topologies = a.max_topo;
   for (const auto &it : a.items) {
     z.max_item_nodes = std::max(z.max_item_nodes, it.n);
-    z.max_item_branches = std::max(z.max_item_branches, it.n_br);
+    z.max_item_branches = std::max(z.max_item_branches, it.n_br_real);
     z.total_nodes += it.n;
-    z.total_branches += it.n_br;
+    z.total_branches += it.n_br_real;
     const Symbolic &S = a.syms[it.sym];
     z.nnz_L += S.nnz();
     z.max_levels = std::max(z.max_levels, std::max(S.levels_f(), S.levels_b()));

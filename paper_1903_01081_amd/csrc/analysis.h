@@ -70,8 +70,9 @@ int choose_tail(const Symbolic &S, int dmax);
 // One work item: one connected component of one scenario.
 struct Item {
   int scen = 0, sym = 0, n = 0, n_br = 0, n_src = 0;
+  int n_br_real = 0;        // branches before padding to whole lane slots
   std::vector<int> gnode;   // local node -> scenario node id
-  std::vector<int> br;      // local branch -> scenario branch id (sources first)
+  std::vector<int> br;      // local branch -> scenario branch id (sources first; -1 = padding)
   std::vector<int> bk, bm;  // local terminals (-1 = ground)
   std::vector<int> nptr, nent;  // node CSR of incident branch ends: (local branch << 1) | (end is m)
   std::vector<int> gpos;    // per local branch: CSR entry of L for its off-diagonal, -1 if none

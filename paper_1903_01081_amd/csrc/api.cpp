@@ -107,7 +107,7 @@ int env_int(const char *name, int dflt) {
 int tail_max(int bs) { return bs >= 512 ? 128 : (bs >= 256 ? 64 : 32); }
 
 int tpr_of(int d, int bs) {
-  int t = 64;
+  int t = 16;
   while (t > 1 && d * t > bs) t >>= 1;
   return t;
 }
@@ -126,6 +126,20 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
     const emt_net &net = nets[it.scen];
     for (int j = 0; j < it.n_br; ++j) {
       const int b = it.br[j];
+      if (b < 0) {
+        // padding: a resistor between the always-zero node slot and itself,
+        // never in service
+        bkind.push_back(EMT_R);
+        bline.push_back(-1);
+        bE.push_back(0.0);
+        bw.push_back(0.0);
+        bph.push_back(0.0);
+        bR.push_back(1.0);
+        bL.push_back(0.0);
+        bC.push_back(0.0);
+        bpack.push_back((uint32_t)it.n | ((uint32_t)it.n << 15) | ((uint32_t)emt::GAMMA_ZERO << 30));
+        continue;
+      }
       const int kind = net.kind[b];
       bkind.push_back(kind);
       bline.push_back(net.line ? net.line[b] : -1);
@@ -136,8 +150,9 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
       bR.push_back(net.R[b]);
       bL.push_back(net.L[b]);
       bC.push_back(net.C[b]);
-      const uint32_t k = it.bk[j] >= 0 ? (uint32_t)it.bk[j] : emt::kTermGround;
-      const uint32_t m = it.bm[j] >= 0 ? (uint32_t)it.bm[j] : emt::kTermGround;
+      // ground terminals point at the node slot n, which holds 0
+      const uint32_t k = it.bk[j] >= 0 ? (uint32_t)it.bk[j] : (uint32_t)it.n;
+      const uint32_t m = it.bm[j] >= 0 ? (uint32_t)it.bm[j] : (uint32_t)it.n;
       const uint32_t cls = (kind == EMT_RL || kind == EMT_SRC) ? emt::GAMMA_PLUS_G
                            : (kind == EMT_C ? emt::GAMMA_MINUS_G : emt::GAMMA_ZERO);
       bpack.push_back(k | (m << 15) | (cls << 30));
@@ -147,7 +162,7 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
     const emt::Item &it = A.items[q];
     const emt::Scenario &sc = A.scens[it.scen];
     for (int t = 0; t < sc.n_topo; ++t)
-      for (int j = 0; j < it.n_br; ++j) cins.push_back(sc.ins[t][it.br[j]]);
+      for (int j = 0; j < it.n_br; ++j) cins.push_back(it.br[j] < 0 ? 0 : sc.ins[t][it.br[j]]);
   }
   c.scen_br_off.clear();
   for (size_t s = 0; s < A.scens.size(); ++s) {
@@ -168,10 +183,11 @@ static emt::LdsShape shape_of(const emt::Item &it, const emt::Symbolic &S, const
 }
 
 // log2 of the lanes that share one row in a sweep pass: enough lanes that
-// the pass's rows fill the workgroup, but no more than its longest row needs.
+// the pass's rows fill the workgroup, but no more than its longest row needs
+// and at most 16 (one DPP row).
 static int pass_lanes_log2(int rows, int maxcnt, int bs) {
   int lg = 0;
-  while (lg < 6 && (rows << (lg + 1)) <= bs && (1 << lg) < maxcnt) ++lg;
+  while (lg < 4 && (rows << (lg + 1)) <= bs && (1 << lg) < maxcnt) ++lg;
   return lg;
 }
 
@@ -187,8 +203,9 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
 
   // Limits of the packed (15/16-bit) index formats.
   if (A.rec_stride > 65535) throw Error{EMT_EINVAL, "at most 65535 recorded nodes per scenario"};
-  int max_nbr = 0;
+  int max_nbr = 0, max_n = 0;
   for (const Item &it : A.items) {
+    max_n = std::max(max_n, it.n);
     if (it.n > kMaxItemNodes - 1)
       throw Error{EMT_EINVAL, "a connected component has more than 32766 nodes"};
     if (it.n_br > 32767) throw Error{EMT_EINVAL, "a connected component has more than 32767 branches"};
@@ -206,7 +223,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   if (bs != 64 && bs != 256 && bs != 512) {
     bs = 512;
     for (int cand : {64, 256})
-      if ((max_nbr + cand - 1) / cand <= 8) {
+      if ((max_nbr + cand - 1) / cand <= 8 && (c.sim.solver != EMT_SOLVER_DENSE || tail_max(cand) >= max_n)) {
         bs = cand;
         break;
       }
@@ -223,22 +240,50 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   c.ks.bs = bs;
   c.ks.bpt = bpt;
   c.ks.dmax = tail_max(bs);
+  // Pad every item's branch list to whole lane slots with inert branches, so
+  // the step kernels need no per-slot bounds; sources must fit slot 0.
+  for (Item &it : A.items) {
+    if (it.n_src > bs)
+      throw Error{EMT_EINVAL, "a connected component has more sources (" + std::to_string(it.n_src) +
+                                  ") than lanes (" + std::to_string(bs) + ")"};
+    const int pad = bs * bpt;
+    it.br.resize(pad, -1);
+    it.bk.resize(pad, -1);
+    it.bm.resize(pad, -1);
+    it.gpos.resize(pad, -1);
+    it.n_br = pad;
+  }
 
-  // Sweep plans: dense tail by cost, grown where the LDS would overflow.
+  // Sweep plans. SPARSE: level-scheduled sweeps only; DENSE: the whole
+  // component is the dense tail (it must fit one workgroup's tail); AUTO:
+  // dense tail chosen by cost and grown where the LDS would overflow.
   std::vector<SweepPlan> plans(A.syms.size());
   const int forced_tail = env_int("EMT_TAIL", -1);
+  const int solver = c.sim.solver;
   for (size_t q = 0; q < A.syms.size(); ++q) {
-    const int d = forced_tail >= 0 ? std::min({forced_tail, A.syms[q].n, c.ks.dmax})
-                                   : choose_tail(A.syms[q], c.ks.dmax);
+    const int n = A.syms[q].n;
+    int d;
+    if (solver == EMT_SOLVER_SPARSE) {
+      d = 0;
+    } else if (solver == EMT_SOLVER_DENSE) {
+      if (n > c.ks.dmax)
+        throw Error{EMT_EINVAL, "the dense solver holds components of at most " + std::to_string(c.ks.dmax) +
+                                    " nodes at this block size; a component has " + std::to_string(n)};
+      d = n;
+    } else {
+      d = forced_tail >= 0 ? std::min({forced_tail, n, c.ks.dmax}) : choose_tail(A.syms[q], c.ks.dmax);
+    }
     plans[q] = plan_sweeps(A.syms[q], d);
   }
   auto item_lds = [&](const Item &it, bool adj) {
     return lds_bytes(shape_of(it, A.syms[it.sym], plans[it.sym]), true, adj);
   };
-  for (const Item &it : A.items) {
-    SweepPlan &P = plans[it.sym];
-    if (item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
-      P = plan_sweeps(A.syms[it.sym], std::min(c.ks.dmax, it.n));
+  if (solver == EMT_SOLVER_AUTO) {
+    for (const Item &it : A.items) {
+      SweepPlan &P = plans[it.sym];
+      if (item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
+        P = plan_sweeps(A.syms[it.sym], std::min(c.ks.dmax, it.n));
+    }
   }
   size_t f_sm = 0, a_sm = 0, f_gl = 0, a_gl = 0;
   int wpt = 1;
@@ -449,7 +494,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<int32_t> order(NI);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return (int64_t)A.items[a].n + A.items[a].n_br > (int64_t)A.items[b].n + A.items[b].n_br;
+    return (int64_t)A.items[a].n + A.items[a].n_br_real > (int64_t)A.items[b].n + A.items[b].n_br_real;
   });
 
   DevCtx &dc = c.dc;

@@ -11,9 +11,10 @@ namespace emt {
 enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4 };
 
 // Packed branch descriptor for the step kernels: local terminals in 15 bits
-// each (kTermGround = ground) and the history-coefficient class in 2 bits:
-// gamma = g (R-L and sources), -g (capacitors) or 0 (resistors, switches).
-constexpr uint32_t kTermGround = 0x7FFF;
+// each (a grounded terminal holds the node count n: the step kernels keep a
+// zero at x[n]) and the history-coefficient class in 2 bits: gamma = g (R-L
+// and sources), -g (capacitors) or 0 (resistors, switches).
+constexpr uint32_t kTermGround = 0x7FFF;  // mask of one packed terminal
 constexpr int kMaxItemNodes = 0x7FFF;
 enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2 };
 

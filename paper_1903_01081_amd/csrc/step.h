@@ -19,10 +19,10 @@
 //                 tail's reduced right-hand side c = rhs_D - L_DS y_S;
 //   tail          x_D = W c, W = (L_DD D_D L_DD^T)^{-1} held in VGPRs;
 //   backward      x = D^{-1} y - L^T x, one pass per level.
-// In a sweep pass each row is shared by 2^k adjacent lanes (k per pass, so
-// that a few long rows at the top of the tree use many lanes and many short
-// rows one lane each); the lanes' partial sums meet in a fixed butterfly of
-// shuffles, so every run rounds identically.
+// In a sweep pass each row is shared by 2^k <= 16 adjacent lanes (k per
+// pass, so that a few long rows at the top of the tree use many lanes and
+// many short rows one lane each); the lanes' partial sums meet in a fixed
+// scan of DPP row shifts, so every run rounds identically.
 // All factors of every topology are computed before the loop (k_factor,
 // k_tail); a switching event swaps coefficients and factor pointers.
 //
@@ -106,20 +106,20 @@ struct Lds {
 // LDS (SM = true) or global memory.
 template <bool SM>
 struct View {
-  int n, d, ns, nbr, nsrc, nsv, nrec, tpr, wlen;
+  int n, d, ns, nbr, nsrc, nsv, nrec, tpr, wlen;  // nbr: padded to whole lane slots
   int nfpass, nbpass;
   const int32_t *fpass, *bpass;  // (first descriptor, log2 lanes) pairs, global
   Ref<uint64_t, SM> fdesc, bdesc;
   Ref<uint16_t, SM> fcol, brow, bpos, nent, rnode, rcolumn;
   Ref<int32_t, SM> nptr, rptr;
-  Lds<double> x, J, cD, eS, dv, sv_s, dinv_s;
+  Lds<double> x, J, cD, dv, sv_s, dinv_s;  // x has n+1 entries, x[n] = 0
   Ref<double, SM> sv, dinv;
 };
 
 // Tail rows are split into tpr lanes of contiguous columns: tpr = the
-// largest power of two (<= 64, within one wave) with d * tpr <= block size.
+// largest power of two (<= 16, within one DPP row) with d * tpr <= block size.
 __device__ __forceinline__ int tail_tpr(int d, int bs) {
-  int t = 64;
+  int t = 16;
   while (t > 1 && d * t > bs) t >>= 1;
   return t;
 }
@@ -131,7 +131,7 @@ __device__ __forceinline__ void copy_to(uint32_t off, const T *src, int cnt) {
 }
 
 // LDS layout (byte offsets from emt_lds, each array 16-byte aligned):
-// cD, x, J, eS, [dv], then under SM sv, dinv, fdesc, bdesc, nptr, [rptr],
+// cD, x, J, [dv], then under SM sv, dinv, fdesc, bdesc, nptr, [rptr],
 // fcol, brow, bpos, nent, rnode, rcolumn. Must match lds_bytes() on the host.
 template <int BS, bool SM>
 __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint) {
@@ -163,11 +163,13 @@ __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint)
     return o;
   };
   v.cD.off = take(v.d + 1, 8);
-  v.x.off = take(v.n, 8);
+  v.x.off = take(v.n + 1, 8);
   v.J.off = take(v.nbr, 8);
-  v.eS.off = take(v.nsrc, 8);
   v.dv.off = take(adjoint ? v.n : 0, 8);
-  if (threadIdx.x == 0) v.cD[v.d] = 0.0;  // spare slot read by the last pair of the tail product
+  if (threadIdx.x == 0) {
+    v.cD[v.d] = 0.0;  // spare slot read by the last pair of the tail product
+    v.x[v.n] = 0.0;   // the ground: every grounded terminal points here
+  }
   if constexpr (SM) {
     v.sv_s.off = take(v.nsv, 8);
     v.dinv_s.off = take(v.ns, 8);
@@ -259,9 +261,36 @@ __device__ __forceinline__ void gather_all(const View<SM> &v) {
   lds_barrier();
 }
 
-// Butterfly sum over the 2^lg lanes of a row group (fixed order).
-__device__ __forceinline__ double group_sum(double s, int lg) {
-  for (int k = 0; k < lg; ++k) s = s + __shfl_xor(s, 1 << k);
+// DPP row_shr:K of a double: lane i receives lane i-K of its 16-lane row
+// (0 where that lane is outside the row).
+template <int K>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffu), 0x110 + K, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x110 + K, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over an aligned group of 2^lg <= 16 lanes (sub = lane index in the
+// group) by an inclusive scan of row shifts: the group's last lane ends
+// with the sum, always added in the same order.
+__device__ __forceinline__ double group_sum(double s, int lg, int sub) {
+  if (lg >= 1) {
+    const double t = dpp_row_shr<1>(s);
+    if (sub >= 1) s = s + t;
+  }
+  if (lg >= 2) {
+    const double t = dpp_row_shr<2>(s);
+    if (sub >= 2) s = s + t;
+  }
+  if (lg >= 3) {
+    const double t = dpp_row_shr<4>(s);
+    if (sub >= 4) s = s + t;
+  }
+  if (lg >= 4) {
+    const double t = dpp_row_shr<8>(s);
+    if (sub >= 8) s = s + t;
+  }
   return s;
 }
 
@@ -289,8 +318,8 @@ __device__ __forceinline__ void forward_pass(const View<SM> &v, int p0, int p1, 
       s = s + a1 * x1;
     }
     if (q < q1) s = s + v.sv[q] * v.x[v.fcol[q]];
-    s = group_sum(s, lg);
-    if (sub == 0) reinterpret_cast<double *>(emt_lds + out_off)[r - shift] = xr - s;
+    s = group_sum(s, lg, sub);
+    if (sub == G - 1) reinterpret_cast<double *>(emt_lds + out_off)[r - shift] = xr - s;
   }
   lds_barrier();
 }
@@ -317,8 +346,8 @@ __device__ __forceinline__ void backward_pass(const View<SM> &v, int p0, int p1,
       s = s + a1 * x1;
     }
     if (q < q1) s = s + v.sv[v.bpos[q]] * v.x[v.brow[q]];
-    s = group_sum(s, lg);
-    if (sub == 0) v.x[r] = xr - s;
+    s = group_sum(s, lg, sub);
+    if (sub == G - 1) v.x[r] = xr - s;
   }
   lds_barrier();
 }
@@ -351,8 +380,9 @@ __device__ __forceinline__ void tail_solve(const View<SM> &v, const double (&w)[
   }
   int lg = 0;
   while ((1 << lg) < v.tpr) ++lg;
-  s = group_sum(s, lg);
-  if (row < v.d && (tid % v.tpr) == 0) v.x[v.ns + row] = s;
+  const int sub = tid % v.tpr;
+  s = group_sum(s, lg, sub);
+  if (row < v.d && sub == v.tpr - 1) v.x[v.ns + row] = s;
   lds_barrier();
 }
 
@@ -373,28 +403,27 @@ __device__ __forceinline__ void solve_after_gather(const View<SM> &v, const doub
 }
 
 // Lane state of the forward loop: coefficients of the current topology and
-// the history current of the next step.
+// the history current of the next step for each slot (branches padded to
+// whole slots with inert ones, so every slot is valid).
 template <int BPT>
 struct Lane {
   double g[BPT], be[BPT], h[BPT];
   uint32_t pk[BPT];
-  // EMF parameters of the lane's first branch (sources are numbered first,
-  // so only slot 0 can hold one while n_src <= block size)
-  double sE, sw, sph;
+  // the source of slot 0 (sources are numbered first and fit in one slot):
+  // EMF parameters and the EMF of the current step
+  double sE, sw, sph, e0;
 };
 
 template <int BS, int BPT>
 __device__ __forceinline__ void load_lane(const DevCtx &c, const ItemDesc &it, Lane<BPT> &L) {
 #pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-    const int b = threadIdx.x + j * BS;
-    L.pk[j] = b < it.n_br ? c.bpack[it.br + b] : (kTermGround | (kTermGround << 15));
-  }
+  for (int j = 0; j < BPT; ++j) L.pk[j] = c.bpack[it.br + threadIdx.x + j * BS];
   const int b0 = threadIdx.x;
   const bool src = b0 < it.n_src;
   L.sE = src ? c.bE[it.br + b0] : 0.0;
   L.sw = src ? c.bw[it.br + b0] : 0.0;
   L.sph = src ? c.bph[it.br + b0] : 0.0;
+  L.e0 = 0.0;
 }
 
 template <int BS, int BPT>
@@ -403,48 +432,36 @@ __device__ __forceinline__ void load_coefs(const DevCtx &c, const ItemDesc &it, 
   const int64_t base = it.coef + (int64_t)t * it.n_br;
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
-    const int b = threadIdx.x + j * BS;
-    g[j] = b < it.n_br ? c.cg[base + b] : 0.0;
-    be[j] = b < it.n_br ? c.cb[base + b] : 0.0;
+    g[j] = c.cg[base + threadIdx.x + j * BS];
+    be[j] = c.cb[base + threadIdx.x + j * BS];
   }
 }
 
 // History current h = beta*i + gamma*u from a stored state (i, u).
 template <int BS, int BPT>
-__device__ __forceinline__ void history_from_state(const double *si, const double *su, int nbr, Lane<BPT> &L) {
+__device__ __forceinline__ void history_from_state(const double *si, const double *su, Lane<BPT> &L) {
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = threadIdx.x + j * BS;
-    const double i = b < nbr ? si[b] : 0.0;
-    const double u = b < nbr ? su[b] : 0.0;
-    L.h[j] = L.be[j] * i + gamma_of(L.pk[j], L.g[j]) * u;
+    L.h[j] = L.be[j] * si[b] + gamma_of(L.pk[j], L.g[j]) * su[b];
   }
 }
 
-// EMF of step n for branch b of slot j (sources only).
+// EMF of step n for the lane's slot-0 branch (0 if it is not a source).
 template <int BPT>
-__device__ __forceinline__ double emf_of(const DevCtx &c, const ItemDesc &it, const Lane<BPT> &L, int j, int b,
-                                         int64_t n) {
-  if (j == 0) return L.sE * emf_cos(L.sw * ((double)n * c.dt) + L.sph);
-  return source_emf(c, it.br + b, n);
+__device__ __forceinline__ double slot0_emf(const DevCtx &c, const Lane<BPT> &L, int tid, int nsrc, int64_t n) {
+  return tid < nsrc ? L.sE * emf_cos(L.sw * ((double)n * c.dt) + L.sph) : 0.0;
 }
 
-// Branch injections of step n: J = g e - h (and e of sources into eS).
+// Branch injections of step n: J = g e - h.
 template <int BS, int BPT, bool SM>
-__device__ __forceinline__ void inject(const DevCtx &c, const ItemDesc &it, const View<SM> &v, const Lane<BPT> &L,
-                                       int64_t n) {
+__device__ __forceinline__ void inject(const DevCtx &c, const View<SM> &v, Lane<BPT> &L, int64_t n) {
   const int tid = lane_id();
+  L.e0 = slot0_emf<BPT>(c, L, tid, v.nsrc, n);
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
-    const int b = tid + j * BS;
-    if (b < v.nbr) {
-      double e = 0.0;
-      if (b < v.nsrc) {
-        e = emf_of<BPT>(c, it, L, j, b, n);
-        v.eS[b] = e;
-      }
-      v.J[b] = L.g[j] * e - L.h[j];
-    }
+    const double e = j == 0 ? L.e0 : 0.0;
+    v.J[tid + j * BS] = L.g[j] * e - L.h[j];
   }
 }
 
@@ -453,45 +470,35 @@ __device__ __forceinline__ void inject(const DevCtx &c, const ItemDesc &it, cons
 // if step n+1 starts a new topology its coefficients are loaded; the history
 // of step n+1; and, when inj is set, the injections of step n+1.
 template <int BS, int BPT, bool SM>
-__device__ __forceinline__ void update_inject(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
-                                              Lane<BPT> &L, double *st_i, double *st_u, double *st2_i,
-                                              double *st2_u, bool switch_next, int64_t next_coef, bool inj,
-                                              int64_t n) {
+__device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v, Lane<BPT> &L, double *st_i,
+                                              double *st_u, double *st2_i, double *st2_u, bool switch_next,
+                                              int64_t next_coef, bool inj, int64_t n) {
   const int tid = lane_id();
+  const double e_next = inj ? slot0_emf<BPT>(c, L, tid, v.nsrc, n + 1) : 0.0;
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = tid + j * BS;
-    if (b < v.nbr) {
-      const uint32_t pk = L.pk[j];
-      const uint32_t k = pk & kTermGround, m = (pk >> 15) & kTermGround;
-      const double vk = k != kTermGround ? v.x[k] : 0.0;
-      const double vm = m != kTermGround ? v.x[m] : 0.0;
-      const double e = b < v.nsrc ? v.eS[b] : 0.0;
-      const double u = (L.g[j] != 0.0) ? (vk - vm) - e : 0.0;
-      const double i = L.g[j] * u + L.h[j];
-      if (st_i) {
-        st_i[b] = i;
-        st_u[b] = u;
-      }
-      if (st2_i) {
-        st2_i[b] = i;
-        st2_u[b] = u;
-      }
-      if (switch_next) {
-        L.g[j] = c.cg[next_coef + b];
-        L.be[j] = c.cb[next_coef + b];
-      }
-      L.h[j] = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
-      if (inj) {
-        double e1 = 0.0;
-        if (b < v.nsrc) {
-          e1 = emf_of<BPT>(c, it, L, j, b, n + 1);
-          v.eS[b] = e1;
-        }
-        v.J[b] = L.g[j] * e1 - L.h[j];
-      }
+    const uint32_t pk = L.pk[j];
+    const double vk = v.x[pk & kTermGround], vm = v.x[(pk >> 15) & kTermGround];
+    const double e = j == 0 ? L.e0 : 0.0;
+    const double u = (L.g[j] != 0.0) ? (vk - vm) - e : 0.0;
+    const double i = L.g[j] * u + L.h[j];
+    if (st_i) {
+      st_i[b] = i;
+      st_u[b] = u;
     }
+    if (st2_i) {
+      st2_i[b] = i;
+      st2_u[b] = u;
+    }
+    if (switch_next) {
+      L.g[j] = c.cg[next_coef + b];
+      L.be[j] = c.cb[next_coef + b];
+    }
+    L.h[j] = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
+    if (inj) v.J[b] = L.g[j] * (j == 0 ? e_next : 0.0) - L.h[j];
   }
+  L.e0 = e_next;
 }
 
 // ---------------------------------------------------------------------------
@@ -509,9 +516,9 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-  history_from_state<BS, BPT>(c.si + it.br, c.su + it.br, v.nbr, L);
+  history_from_state<BS, BPT>(c.si + it.br, c.su + it.br, L);
   select_factor<BS, WPT, SM>(c, it, v, t, w);
-  inject<BS, BPT, SM>(c, it, v, L, n0 + 1);
+  inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
@@ -533,7 +540,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       st_i = c.si + it.br;
       st_u = c.su + it.br;
     }
-    update_inject<BS, BPT, SM>(c, it, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
+    update_inject<BS, BPT, SM>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
                                n < n_end, n);
     if (sw) {
       ++t;
@@ -564,12 +571,10 @@ __device__ __forceinline__ void adjoint_seed(const DevCtx &c, const ItemDesc &it
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = tid + j * BS;
-    if (b < v.nbr) {
-      const double ibar = be_nx[j] * hb_nx[j];
-      ib[j] = ibar;
-      const double ga_nx = gamma_of(L.pk[j], g_nx[j]);
-      v.J[b] = (L.g[j] != 0.0) ? ga_nx * hb_nx[j] + L.g[j] * ibar : 0.0;
-    }
+    const double ibar = be_nx[j] * hb_nx[j];
+    ib[j] = ibar;
+    const double ga_nx = gamma_of(L.pk[j], g_nx[j]);
+    v.J[b] = (L.g[j] != 0.0) ? ga_nx * hb_nx[j] + L.g[j] * ibar : 0.0;
   }
   const double *drow = dJ + ((int64_t)it.scen * c.T + (n - 1)) * c.rec_stride;
   for (int r = tid; r < v.n; r += BS) {
@@ -606,24 +611,22 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
       const int b = threadIdx.x + j * BS;
-      if (b < nbr) {
-        seg_i[b] = c.ck_i[cko + b];
-        seg_u[b] = c.ck_u[cko + b];
-      }
+      seg_i[b] = c.ck_i[cko + b];
+      seg_u[b] = c.ck_u[cko + b];
     }
     int t = topo_of(topo, it.n_topo, lo + 1);
     int64_t next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
     load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-    history_from_state<BS, BPT>(c.ck_i + cko, c.ck_u + cko, nbr, L);
+    history_from_state<BS, BPT>(c.ck_i + cko, c.ck_u + cko, L);
     select_factor<BS, WPT, SM>(c, it, v, t, w);
-    inject<BS, BPT, SM>(c, it, v, L, lo + 1);
+    inject<BS, BPT, SM>(c, v, L, lo + 1);
     lds_barrier();
     for (int64_t n = lo + 1; n <= hi; ++n) {
       gather_all<BS, false, SM>(v);
       solve_after_gather<BS, WPT, SM>(v, w);
       const int64_t o = (n - lo) * (int64_t)nbr;
       const bool sw = (n + 1 == next) && n < hi;
-      update_inject<BS, BPT, SM>(c, it, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw,
+      update_inject<BS, BPT, SM>(c, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw,
                                  it.coef + (int64_t)(t + 1) * nbr, n < hi, n);
       if (sw) {
         ++t;
@@ -643,19 +646,15 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
 #pragma unroll
       for (int j = 0; j < BPT; ++j) {
         const int b = tid + j * BS;
-        if (b < nbr) {
-          const uint32_t pk = L.pk[j];
-          const uint32_t k = pk & kTermGround, m = (pk >> 15) & kTermGround;
-          const double wk = k != kTermGround ? v.x[k] : 0.0;
-          const double wm = m != kTermGround ? v.x[m] : 0.0;
-          const double hb = (L.g[j] != 0.0) ? ib[j] - (wk - wm) : 0.0;
-          gb[j] = gb[j] + hb * seg_u[on + b];
-          bb[j] = bb[j] + hb * seg_i[op + b];
-          cb[j] = cb[j] + hb * seg_u[op + b];
-          hb_nx[j] = hb;
-          g_nx[j] = L.g[j];
-          be_nx[j] = L.be[j];
-        }
+        const uint32_t pk = L.pk[j];
+        const double wk = v.x[pk & kTermGround], wm = v.x[(pk >> 15) & kTermGround];
+        const double hb = (L.g[j] != 0.0) ? ib[j] - (wk - wm) : 0.0;
+        gb[j] = gb[j] + hb * seg_u[on + b];
+        bb[j] = bb[j] + hb * seg_i[op + b];
+        cb[j] = cb[j] + hb * seg_u[op + b];
+        hb_nx[j] = hb;
+        g_nx[j] = L.g[j];
+        be_nx[j] = L.be[j];
       }
       if (n - 1 >= lo + 1) {
         const int tp = topo_of(topo, it.n_topo, n - 1);
@@ -672,11 +671,9 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = threadIdx.x + j * BS;
-    if (b < nbr) {
-      c.gbar[it.br + b] = gb[j];
-      c.bbar[it.br + b] = bb[j];
-      c.cbar[it.br + b] = cb[j];
-    }
+    c.gbar[it.br + b] = gb[j];
+    c.bbar[it.br + b] = bb[j];
+    c.cbar[it.br + b] = cb[j];
   }
 }
 

@@ -1,0 +1,153 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+bench.py times (one emt_step over the whole horizon after emt_factor):
+outputs the oracle can reach in seconds (a prefix of the horizon, sampled
+scenarios) are compared element by element; the rest is checked through
+properties that hold at any size (the balanced three-phase invariant, KCL and
+the trapezoidal branch relations of the device state)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1903_01081_amd import netgen
+from paper_1903_01081_amd.netgen import CAP, RL, SRC
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def rel(a, b):
+    s = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (s if s > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def grid1000_run(torch_cuda):
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config1()
+    say("grid1000 full horizon: 3000 nodes, 50000 steps")
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    sim.factor()
+    rec = sim.step(cfg["n_steps"])
+    torch_cuda.cuda.synchronize()
+    return nets, cfg, sim, rec
+
+
+def test_grid1000_prefix_vs_oracle(grid1000_run, oracle_mod):
+    nets, cfg, sim, rec = grid1000_run
+    T0 = 300
+    ref = oracle_mod.run(nets[0], cfg["dt"], T0)
+    got = rec[0, :T0].cpu().numpy()
+    err = rel(got, ref)
+    say("grid1000 prefix rel err", err)
+    assert err < TOL
+
+
+def test_grid1000_zero_sequence_whole_horizon(grid1000_run):
+    # identical uncoupled phases, balanced sources, symmetric fault: the three
+    # phase voltages of every bus sum to zero at every one of the 50,000 steps
+    nets, cfg, sim, rec = grid1000_run
+    r = rec[0]
+    zs = r.view(r.shape[0], -1, 3).sum(dim=2).abs().max().item()
+    assert zs / r.abs().max().item() < 1e-11
+
+
+def test_grid1000_final_state_kcl_and_branch_relations(grid1000_run, torch_cuda):
+    # the last step checked from the device state alone: KCL at every node and
+    # the trapezoidal relation of every in-service branch between steps T-1, T
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg, _, _ = grid1000_run
+    net = nets[0]
+    T, dt = cfg["n_steps"], cfg["dt"]
+    sim = Simulator(nets, dt, T)
+    sim.factor()
+    sim.step(T - 1, record=False)
+    v0, i0 = sim.get_state(0)
+    sim.step(1, record=False)
+    v1, i1 = sim.get_state(0)
+    inj = np.zeros(net.n_nodes)
+    mag = np.zeros(net.n_nodes)
+    for arr, sgn in ((net.k, 1.0), (net.m, -1.0)):
+        ok = arr >= 0
+        np.add.at(inj, arr[ok], sgn * i1[ok])
+        np.add.at(mag, arr[ok], np.abs(i1[ok]))
+    assert np.max(np.abs(inj)) <= 1e-10 * np.max(mag)
+    # every branch is in service at the end (the fault closed at mid-horizon)
+    e = np.where(net.kind == SRC, net.E * np.cos(net.omega * (np.arange(2)[:, None] + T - 1) * dt + net.phase), 0.0)
+
+    def branch_v(v, ee):
+        vk = np.where(net.k >= 0, v[np.maximum(net.k, 0)], 0.0)
+        vm = np.where(net.m >= 0, v[np.maximum(net.m, 0)], 0.0)
+        return vk - vm - ee
+    u0, u1 = branch_v(v0, e[0]), branch_v(v1, e[1])
+    ind = (net.kind == RL) | (net.kind == SRC)
+    lhs = net.L[ind] * (i1[ind] - i0[ind]) / dt
+    rhs = 0.5 * (u1[ind] + u0[ind]) - net.R[ind] * 0.5 * (i1[ind] + i0[ind])
+    scale = np.max(np.abs(u1[ind]) + np.abs(u0[ind]) + net.R[ind] * (np.abs(i1[ind]) + np.abs(i0[ind])))
+    assert np.max(np.abs(lhs - rhs)) <= 1e-9 * scale
+    cap = net.kind == CAP
+    lhs = net.C[cap] * (u1[cap] - u0[cap]) / dt
+    rhs = 0.5 * (i1[cap] + i0[cap])
+    assert np.max(np.abs(lhs - rhs)) <= 1e-9 * np.max(np.abs(i1[cap]) + np.abs(i0[cap]))
+
+
+def test_grid1000_fault_factors_vs_oracle(torch_cuda, oracle_mod):
+    # the full-size grid with its fault moved early, so the oracle reaches
+    # the post-fault topology in seconds
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config1(n_steps=320, fault_step=150)
+    say("grid1000 with fault at 150, 320 steps")
+    sim = Simulator(nets, cfg["dt"], 320)
+    sim.factor()
+    got = sim.step(320).cpu().numpy()[0]
+    ref = oracle_mod.run(nets[0], cfg["dt"], 320)
+    err = rel(got, ref)
+    say("grid1000 fault rel err", err)
+    assert err < TOL
+
+
+def test_n1_full_size_sampled_scenarios(torch_cuda, oracle_mod):
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config2()
+    say("grid200 N-1 full: 400 scenarios x 600 nodes, 15000 steps")
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    sim.factor()
+    rec = sim.step(cfg["n_steps"])
+    pick = [0, 137, 399]
+    got = rec[pick].cpu().numpy()
+    del rec
+    refs = oracle_mod.run_batch([nets[s] for s in pick], cfg["dt"], cfg["n_steps"], n_threads=3)
+    errs = [rel(got[q], refs[q]) for q in range(len(pick))]
+    say("grid200 N-1 sampled rel errs", errs)
+    assert max(errs) < TOL
+
+
+def test_uneven_full_size_sampled_instances(torch_cuda, oracle_mod):
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config4()
+    say("uneven full: 256 grids of 90-900 nodes, 5000 steps")
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    sim.factor()
+    rec = sim.step(cfg["n_steps"])
+    sizes = np.array([n.n_nodes for n in nets])
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes)), 100]
+    got = rec[pick].cpu().numpy()
+    del rec
+    refs = oracle_mod.run_batch([nets[s] for s in pick], cfg["dt"], cfg["n_steps"], n_threads=3)
+    errs = [rel(got[q][:, :nets[s].n_rec], refs[q]) for q, s in enumerate(pick)]
+    say("uneven sampled rel errs", errs, "sizes", sizes[pick])
+    assert max(errs) < TOL

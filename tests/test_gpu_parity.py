@@ -178,3 +178,33 @@ def test_error_paths(torch_cuda):
     with pytest.raises(EMTError) as e:
         sim.adjoint(torch.zeros((1, 50, 27), dtype=torch.float64, device=sim.device))
     assert e.value.status == EMT_ESTATE
+
+
+@pytest.mark.parametrize("solver", ["sparse", "dense"])
+@pytest.mark.parametrize("n_bus,seed", [(9, 21), (40, 22)])
+def test_solver_modes_vs_oracle(torch_cuda, oracle_mod, solver, n_bus, seed):
+    # sparse: level-scheduled sweeps over the whole factor, no dense tail;
+    # dense: the whole component solved by its inverse (no sweeps)
+    T = 500
+    net = netgen.small_grid(seed, n_bus, fault_step=150, remove_series=2, remove_step=300,
+                            n_mon=min(25, 3 * n_bus))
+    say(f"solver={solver} n_bus={n_bus} seed={seed}")
+    sim, rec = gpu_run([net], 20e-6, T, solver=solver)
+    info = sim.info()
+    if solver == "sparse":
+        assert info["max_tail"] == 0
+    else:
+        assert info["max_tail"] == n_bus
+    ref = oracle_mod.run(net, 20e-6, T)
+    err = rel(rec[0], ref)
+    say("rel err", err)
+    assert err < TOL
+
+
+def test_dense_solver_rejects_large_component(torch_cuda):
+    from paper_1903_01081_amd._lib import EMTError, EMT_EINVAL
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(31, 400, n_mon=20)
+    with pytest.raises(EMTError) as e:
+        Simulator([net], 20e-6, 10, solver="dense")
+    assert e.value.status == EMT_EINVAL and "dense solver" in str(e.value)
