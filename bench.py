@@ -15,6 +15,7 @@ uneven batched gradients) ride along as extra keys unless --no-extras.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +42,35 @@ def algorithmic_bytes_per_step(info, n_rec_total):
     outputs (8 B each)."""
     return (64 * info["total_branches"] + 24 * info["nnz_L"] + 8 * info["total_nodes"]
             + 8 * n_rec_total)
+
+
+KERNEL_SOURCES = ("paper_1903_01081_amd/csrc/step.h", "paper_1903_01081_amd/csrc/step.hip",
+                  "paper_1903_01081_amd/csrc/device.h")
+TRAFFIC_PROFILE = "profiles/k_forward_grid1000.md"
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_forward launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or
+    None when the kernel sources have changed since it was taken."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("source_digest") == kernel_source_digest():
+                        return float(rec["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def time_simulation(torch, sim, rec, steps, warmup):
@@ -76,7 +106,7 @@ def time_simulation(torch, sim, rec, steps, warmup):
 
 def cpu_baseline_config1(nets, cfg):
     """The oracle (dense LU, one thread) on a bounded sample of the workload:
-    two short runs (50 and 1050 steps) give the factorisation and per-step
+    two short runs (50 and 2550 steps) give the factorisation and per-step
     costs, extrapolated to the full horizon with its two factorisations."""
     from oracle import oracle as O
     net = nets[0]
@@ -85,15 +115,15 @@ def cpu_baseline_config1(nets, cfg):
     O.run(net, dt, 50)
     t50 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    O.run(net, dt, 1050)
-    t1050 = time.perf_counter() - t0
-    per_step = max((t1050 - t50) / 1000.0, 1e-12)
+    O.run(net, dt, 2550)
+    t_long = time.perf_counter() - t0
+    per_step = max((t_long - t50) / 2500.0, 1e-12)
     factor = max(t50 - 50 * per_step, 0.0)
     T = cfg["n_steps"]
     total = 2 * factor + T * per_step
     return {"value": net.n_nodes * T / total, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle runs of 50 and 1050 steps of the same 3000-node grid "
-                      f"({t50 + t1050:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
+            "sample": f"oracle runs of 50 and 2550 steps of the same 3000-node grid "
+                      f"({t50 + t_long:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
                       f"factorisation {factor:.2f} s extrapolated to 50,000 steps and 2 factorisations"}
 
 
@@ -187,6 +217,19 @@ def extras(torch, args):
     return out
 
 
+def calibrate_copy(torch, gib=1):
+    """A plain device-to-device copy of a known size, run under the same
+    rocprofv3 --pmc counters as the step kernel: FETCH_SIZE and WRITE_SIZE
+    of this copy, against its true bytes, give the counters' scale."""
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +237,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the EMT time loop runs each scenario on one device "
@@ -202,6 +247,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
 
@@ -228,7 +276,8 @@ def main():
                    "nodes": N, "branches": int(net.n_branches), "time_steps": T,
                    "bench_step": "emt_factor + emt_step over the whole horizon"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_forward", "kernel_s": kern,
                      "algorithmic_bytes_per_time_step": per_step_bytes},
         "latency": {"us_per_time_step": kern / T * 1e6,
