@@ -106,8 +106,12 @@ typedef struct {
  *   solver: how each connected component's G v = rhs is solved (Sec. III-A,
  *     fourth basic process). SPARSE: level-scheduled forward/backward sweeps
  *     over the LDL^T factor. DENSE: v = G^{-1} rhs with the component's whole
- *     inverse held by its workgroup; EMT_EINVAL from emt_build when a
- *     component exceeds the dense limit (128 nodes). AUTO: sweeps over the
+ *     inverse, formed by emt_factor for every topology; a component of up to
+ *     128 nodes keeps it in one workgroup, a larger one (up to 2048 nodes) is
+ *     split by columns over ceil(n/16) workgroups that exchange partial
+ *     voltages every step (all must be resident at once: EMT_EINVAL from
+ *     emt_build otherwise; forward only: EMT_EINVAL with checkpoint_every
+ *     > 0). AUTO: sweeps over the
  *     leading rows of the elimination order and the dense inverse of its
  *     trailing block, cut where a cost model finds fewest dependent phases. */
 typedef struct {
@@ -139,6 +143,7 @@ typedef struct {
   int32_t lds_limit;     /* LDS per workgroup the device allows */
   int32_t lds_staged;    /* 1 if index arrays and factors are staged in LDS */
   int32_t lanes_per_block; /* branches per lane */
+  int32_t split_tiles;   /* workgroups of the split dense components (0 if none) */
 } emt_info;
 
 /* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and

@@ -25,6 +25,7 @@ SOURCES = [
     ("step.hip", "step64", ["-DEMT_BS=64"]),
     ("step.hip", "step256", ["-DEMT_BS=256"]),
     ("step.hip", "step512", ["-DEMT_BS=512"]),
+    ("split.hip", "split", []),
 ]
 
 COMMON = [

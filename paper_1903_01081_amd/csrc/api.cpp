@@ -71,6 +71,16 @@ struct emt_ctx {
   bool sm_fwd = true, sm_adj = true, ks_adj_ok = true;
   int bpt_global = 0;
   int max_tail = 0, dense_items = 0, sweep_levels = 0, lds_limit = 0;
+  // items solved in one workgroup (k_forward launches the first n_fwd of
+  // d_order) and split dense components (k_split, one workgroup per tile)
+  int n_fwd = 0;
+  std::vector<char> is_split;
+  emt::SplitCtx sc{};
+  int n_tiles = 0, split_bpt = 1, split_rpl = 1;
+  size_t split_lds = 0, inverse_lds = 0;
+  int32_t *d_inv_jobs = nullptr;
+  int n_inv_jobs = 0;
+  std::vector<std::pair<int64_t, int32_t>> split_flags;  // (offset, count) per split item
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -191,6 +201,210 @@ static int pass_lanes_log2(int rows, int maxcnt, int bs) {
   return lg;
 }
 
+// Tiles of the split dense components: a breadth-first order of each
+// component's nodes cut into blocks of kSplitCols columns; a tile takes every
+// branch incident to its block (a branch between two blocks belongs to both,
+// and the block of its k terminal writes its state), the nodes those
+// branches touch, the CSR of its own nodes' branch ends and its recorded
+// nodes. Then the device arrays, the inverse jobs and the launch shape.
+static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
+  using namespace emt;
+  const Analysis &A = c.A;
+  const int NI = (int)A.items.size();
+  constexpr int RT = kSplitCols;
+  std::vector<SplitItem> sitems;
+  std::vector<SplitTile> tiles;
+  std::vector<int32_t> i32;
+  std::vector<uint32_t> u32;
+  std::vector<uint16_t> u16;
+  std::vector<int32_t> jobs;
+  int64_t gt_off = 0, xb_off = 0, fl_off = 0;
+  int max_slots = 0, max_n = 0;
+  size_t inv_lds = 0;
+  struct TileLists {
+    std::vector<int> br, need, nptr, nent;
+    std::vector<uint32_t> pack, rec;
+    int cnt = 0, nsrc = 0;
+  };
+  std::vector<std::vector<TileLists>> all;
+  for (int q = 0; q < NI; ++q) {
+    if (!c.is_split[q]) continue;
+    const Item &it = A.items[q];
+    const Scenario &sc = A.scens[it.scen];
+    const int n = it.n;
+    max_n = std::max(max_n, n);
+    // adjacency over real branches, breadth-first order from node 0
+    std::vector<std::vector<int>> adj(n);
+    for (int b = 0; b < it.n_br; ++b) {
+      if (it.br[b] < 0 || it.bk[b] < 0 || it.bm[b] < 0) continue;
+      adj[it.bk[b]].push_back(it.bm[b]);
+      adj[it.bm[b]].push_back(it.bk[b]);
+    }
+    std::vector<int> bfs, pos(n, -1);
+    for (int root = 0; root < n; ++root) {
+      if (pos[root] >= 0) continue;
+      pos[root] = (int)bfs.size();
+      bfs.push_back(root);
+      for (size_t h = bfs.size() - 1; h < bfs.size(); ++h) {
+        std::vector<int> nb = adj[bfs[h]];
+        std::sort(nb.begin(), nb.end());
+        for (int v : nb)
+          if (pos[v] < 0) {
+            pos[v] = (int)bfs.size();
+            bfs.push_back(v);
+          }
+      }
+    }
+    const int P = (n + RT - 1) / RT;
+    SplitItem si{};
+    si.item = q;
+    si.P = P;
+    si.cb = std::max(1, std::min(16, 20000 / n));
+    si.pos = (int64_t)i32.size();
+    i32.insert(i32.end(), pos.begin(), pos.end());
+    si.gt = gt_off;
+    si.xbuf = xb_off;
+    si.flag = fl_off;
+    gt_off += (int64_t)sc.n_topo * P * RT * n;
+    xb_off += 2 * (int64_t)n * ((P + 7) & ~7);
+    fl_off += P;
+    c.split_flags.emplace_back(si.flag, P);
+    inv_lds = std::max(inv_lds, (size_t)si.cb * n * sizeof(double));
+    for (int t = 0; t < sc.n_topo; ++t)
+      for (int j0 = 0; j0 < n; j0 += si.cb) {
+        jobs.push_back((int32_t)sitems.size());
+        jobs.push_back(t);
+        jobs.push_back(j0);
+      }
+    std::vector<TileLists> tl(P);
+    auto tile_of = [&](int node) { return pos[node] / RT; };
+    for (int p = 0; p < P; ++p) {
+      TileLists &T = tl[p];
+      const int a0 = p * RT, a1 = std::min(n, a0 + RT);
+      T.cnt = a1 - a0;
+      std::vector<int> slot(n, -1);
+      for (int a = a0; a < a1; ++a) {
+        slot[bfs[a]] = (int)T.need.size();
+        T.need.push_back(bfs[a]);
+      }
+      auto in_tile = [&](int node) { return node >= 0 && tile_of(node) == p; };
+      std::vector<int> srcs, rest;
+      for (int b = 0; b < it.n_br; ++b) {
+        if (it.br[b] < 0) continue;
+        if (!in_tile(it.bk[b]) && !in_tile(it.bm[b])) continue;
+        (b < it.n_src ? srcs : rest).push_back(b);
+      }
+      T.nsrc = (int)srcs.size();
+      std::vector<int> brs = srcs;
+      brs.insert(brs.end(), rest.begin(), rest.end());
+      std::vector<int> halo;
+      for (int b : brs)
+        for (int v : {it.bk[b], it.bm[b]})
+          if (v >= 0 && slot[v] < 0) {
+            slot[v] = -2;
+            halo.push_back(v);
+          }
+      std::sort(halo.begin(), halo.end());
+      for (int v : halo) {
+        slot[v] = (int)T.need.size();
+        T.need.push_back(v);
+      }
+      const uint32_t gnd = (uint32_t)T.need.size();
+      for (int b : brs) {
+        const int writer = it.bk[b] >= 0 ? tile_of(it.bk[b]) : tile_of(it.bm[b]);
+        T.br.push_back(b | ((writer == p ? 1 : 0) << 30));
+        const uint32_t k = it.bk[b] >= 0 ? (uint32_t)slot[it.bk[b]] : gnd;
+        const uint32_t m = it.bm[b] >= 0 ? (uint32_t)slot[it.bm[b]] : gnd;
+        T.pack.push_back(k | (m << 15) | (bpack[c.items[q].br + b] & 0xC0000000u));
+      }
+      T.nptr.push_back(0);
+      for (int a = 0; a < T.cnt; ++a) {
+        const int node = T.need[a];
+        for (int j = 0; j < (int)brs.size(); ++j) {
+          if (it.bk[brs[j]] == node) T.nent.push_back(j << 1);
+          if (it.bm[brs[j]] == node) T.nent.push_back((j << 1) | 1);
+        }
+        T.nptr.push_back((int)T.nent.size());
+      }
+      for (size_t r = 0; r < it.rec_node.size(); ++r)
+        if (in_tile(it.rec_node[r]))
+          T.rec.push_back((uint32_t)slot[it.rec_node[r]] | ((uint32_t)it.rec_col[r] << 16));
+      if ((int)T.need.size() > kMaxItemNodes - 1 || T.nent.size() > 65535)
+        throw Error{EMT_EINVAL, "a split tile touches too many nodes"};
+      if (2 * (int)brs.size() > 65535) throw Error{EMT_EINVAL, "a split tile has too many branches"};
+      max_slots = std::max(max_slots, (int)brs.size());
+    }
+    sitems.push_back(si);
+    all.push_back(std::move(tl));
+  }
+  if (sitems.empty()) return;
+  int bpt = 0;
+  for (int cand : {1, 2, 4})
+    if (cand * kSplitBS >= max_slots) {
+      bpt = cand;
+      break;
+    }
+  if (bpt == 0) throw Error{EMT_EINVAL, "a split tile has more than " + std::to_string(4 * kSplitBS) + " branches"};
+  const int rpl = (max_n + kSplitBS - 1) / kSplitBS;
+  if (rpl > 4) throw Error{EMT_EINVAL, "the dense solver splits components of at most " +
+                                           std::to_string(4 * kSplitBS) + " nodes"};
+  c.split_rpl = rpl <= 1 ? 1 : (rpl <= 2 ? 2 : 4);
+  c.split_bpt = bpt;
+  const int slots = bpt * kSplitBS;
+  size_t lds = 0;
+  for (size_t k = 0; k < sitems.size(); ++k) {
+    for (int p = 0; p < sitems[k].P; ++p) {
+      TileLists &T = all[k][p];
+      SplitTile d{};
+      d.sitem = (int32_t)k;
+      d.p = p;
+      d.cnt = T.cnt;
+      d.nn = (int32_t)T.need.size();
+      d.nsrc = T.nsrc;
+      d.nrec = (int32_t)T.rec.size();
+      d.ne = (int32_t)T.nent.size();
+      d.need = (int64_t)i32.size();
+      i32.insert(i32.end(), T.need.begin(), T.need.end());
+      d.br = (int64_t)i32.size();
+      for (int j = 0; j < slots; ++j) i32.push_back(j < (int)T.br.size() ? T.br[j] : -1);
+      d.bpack = (int64_t)u32.size();
+      for (int j = 0; j < slots; ++j)
+        u32.push_back(j < (int)T.pack.size() ? T.pack[j]
+                                             : ((uint32_t)d.nn | ((uint32_t)d.nn << 15) | (GAMMA_ZERO << 30)));
+      d.nptr = (int64_t)i32.size();
+      i32.insert(i32.end(), T.nptr.begin(), T.nptr.end());
+      d.nent = (int64_t)u16.size();
+      for (int e : T.nent) u16.push_back((uint16_t)e);
+      d.rec = (int64_t)u32.size();
+      u32.insert(u32.end(), T.rec.begin(), T.rec.end());
+      lds = std::max(lds, split_lds_bytes(d.nn, bpt, d.ne, d.nrec));
+      tiles.push_back(d);
+    }
+  }
+  if (lds > (size_t)c.lds_limit) throw Error{EMT_EINVAL, "a split tile needs more LDS than a workgroup has"};
+  c.n_tiles = (int)tiles.size();
+  c.split_lds = lds;
+  c.inverse_lds = inv_lds;
+  int per_cu = 0, n_cu = 0;
+  hip_check(split_blocks_per_cu(c.split_bpt, c.split_rpl, lds, &per_cu), "split occupancy");
+  hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device), "CU count");
+  if ((int64_t)per_cu * n_cu < c.n_tiles)
+    throw Error{EMT_EINVAL, "the split components need " + std::to_string(c.n_tiles) +
+                                " workgroups resident at once; the device holds " + std::to_string(per_cu * n_cu)};
+  c.sc.items = c.upload(sitems);
+  c.sc.tiles = c.upload(tiles);
+  c.sc.i32 = c.upload(i32);
+  c.sc.u32 = c.upload(u32);
+  c.sc.u16 = c.upload(u16);
+  c.sc.gt = c.alloc<double>(gt_off);
+  hip_check(hipMemset(c.sc.gt, 0, (size_t)gt_off * sizeof(double)), "clear inverse");
+  c.sc.xbuf = c.alloc<double>(xb_off);
+  c.sc.flags = c.alloc<int64_t>(fl_off);
+  c.sc.err = c.dc.flags + 1;
+  c.d_inv_jobs = c.upload(jobs);
+  c.n_inv_jobs = (int)jobs.size() / 3;
+}
+
 static void upload_all(emt_ctx &c, const emt_net *nets) {
   using namespace emt;
   Analysis &A = c.A;
@@ -203,14 +417,25 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
 
   // Limits of the packed (15/16-bit) index formats.
   if (A.rec_stride > 65535) throw Error{EMT_EINVAL, "at most 65535 recorded nodes per scenario"};
+  // The dense solver splits components larger than the biggest one-
+  // workgroup dense tail over several workgroups.
+  c.is_split.assign(NI, 0);
   int max_nbr = 0, max_n = 0;
-  for (const Item &it : A.items) {
-    max_n = std::max(max_n, it.n);
+  for (int q = 0; q < NI; ++q) {
+    const Item &it = A.items[q];
     if (it.n > kMaxItemNodes - 1)
       throw Error{EMT_EINVAL, "a connected component has more than 32766 nodes"};
     if (it.n_br > 32767) throw Error{EMT_EINVAL, "a connected component has more than 32767 branches"};
+    if (sim.solver == EMT_SOLVER_DENSE && it.n > tail_max(512)) {
+      c.is_split[q] = 1;
+      continue;
+    }
+    max_n = std::max(max_n, it.n);
     max_nbr = std::max(max_nbr, it.n_br);
   }
+  if (K > 0 && std::count(c.is_split.begin(), c.is_split.end(), 1) > 0)
+    throw Error{EMT_EINVAL, "checkpoints (the adjoint) need every component in one workgroup; the dense solver "
+                            "splits components above " + std::to_string(tail_max(512)) + " nodes and runs forward only"};
 
   // Workgroup size and branches per lane.
   int max_lds = 65536;
@@ -230,7 +455,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   }
   int bpt = 0;
   for (int cand : {1, 2, 4, 6, 8, 12, 16})
-    if (cand * bs >= max_nbr) {
+    if (cand * bs >= std::max(max_nbr, 1)) {
       bpt = cand;
       break;
     }
@@ -243,6 +468,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // Pad every item's branch list to whole lane slots with inert branches, so
   // the step kernels need no per-slot bounds; sources must fit slot 0.
   for (Item &it : A.items) {
+    if (c.is_split[&it - &A.items[0]]) continue;
     if (it.n_src > bs)
       throw Error{EMT_EINVAL, "a connected component has more sources (" + std::to_string(it.n_src) +
                                   ") than lanes (" + std::to_string(bs) + ")"};
@@ -260,10 +486,15 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<SweepPlan> plans(A.syms.size());
   const int forced_tail = env_int("EMT_TAIL", -1);
   const int solver = c.sim.solver;
+  std::vector<char> sym_split(A.syms.size(), 0);
+  for (int q = 0; q < NI; ++q)
+    if (c.is_split[q]) sym_split[A.items[q].sym] = 1;
   for (size_t q = 0; q < A.syms.size(); ++q) {
     const int n = A.syms[q].n;
     int d;
-    if (solver == EMT_SOLVER_SPARSE) {
+    if (sym_split[q]) {
+      d = 0;  // factor values only; the split kernels use the explicit inverse
+    } else if (solver == EMT_SOLVER_SPARSE) {
       d = 0;
     } else if (solver == EMT_SOLVER_DENSE) {
       if (n > c.ks.dmax)
@@ -280,6 +511,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   };
   if (solver == EMT_SOLVER_AUTO) {
     for (const Item &it : A.items) {
+      if (c.is_split[&it - &A.items[0]]) continue;
       SweepPlan &P = plans[it.sym];
       if (item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
         P = plan_sweeps(A.syms[it.sym], std::min(c.ks.dmax, it.n));
@@ -288,6 +520,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   size_t f_sm = 0, a_sm = 0, f_gl = 0, a_gl = 0;
   int wpt = 1;
   for (const Item &it : A.items) {
+    if (c.is_split[&it - &A.items[0]]) continue;
     const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym]);
     f_sm = std::max(f_sm, lds_bytes(sh, true, false));
     a_sm = std::max(a_sm, lds_bytes(sh, true, true));
@@ -360,6 +593,9 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.flevrows = put(S.flev_rows);
     d.fentptr = put(S.fent_ptr);
     d.fent = put(S.fent);
+    d.nlevb = S.levels_b();
+    d.blevptr = put(S.blev_ptr);
+    d.blevrows = put(S.blev_rows);
     d.svmap = put(P.svmap);
     d.fpass = put(passes(P.fpass_ptr, P.fpass_maxcnt));
     d.bpass = put(passes(P.bpass_ptr, P.bpass_maxcnt));
@@ -394,7 +630,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     const Scenario &sc = A.scens[it.scen];
     const Symbolic &S = A.syms[it.sym];
     const SweepPlan &P = plans[it.sym];
-    if (P.d == it.n) c.dense_items++;
+    if (P.d == it.n || c.is_split[q]) c.dense_items++;
     ItemDesc d{};
     d.scen = it.scen;
     d.sym = it.sym;
@@ -490,12 +726,15 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   }
   c.n_lines_total = (int)line_id.size();
 
-  // Largest items first so their workgroups start first.
-  std::vector<int32_t> order(NI);
-  std::iota(order.begin(), order.end(), 0);
+  // One-workgroup items, largest first so their workgroups start first.
+  std::vector<int32_t> order;
+  for (int q = 0; q < NI; ++q)
+    if (!c.is_split[q]) order.push_back(q);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return (int64_t)A.items[a].n + A.items[a].n_br_real > (int64_t)A.items[b].n + A.items[b].n_br_real;
   });
+  c.n_fwd = (int)order.size();
+  if (order.empty()) order.push_back(0);
 
   DevCtx &dc = c.dc;
   dc.items = c.upload(c.items);
@@ -540,6 +779,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.seg_i = K > 0 ? c.alloc<double>(seg_off) : nullptr;
   dc.seg_u = K > 0 ? c.alloc<double>(seg_off) : nullptr;
   dc.flags = c.alloc<int32_t>(4);
+  hip_check(launch_fill_i32(dc.flags, 4, 0, nullptr), "clear flags");
   dc.dt = sim.dt;
   dc.T = T;
   dc.K = K;
@@ -564,6 +804,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   for (size_t s = 0; s + 1 < c.scen_br_off.size(); ++s)
     max_scen_br = std::max(max_scen_br, c.scen_br_off[s + 1] - c.scen_br_off[s]);
   c.d_stage = c.alloc<double>(max_scen_br);
+  build_split(c, bpack);
   // statistics
   c.sweep_levels = 0;
   for (const Item &it : A.items)
@@ -575,10 +816,29 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
   ks.sm = c.sm_fwd;
   if (!ks.sm) ks.bpt = c.bpt_global;
   switch (ks.bs) {
-    case 64: return emt::launch_forward_bs64(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
-    case 256: return emt::launch_forward_bs256(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
-    default: return emt::launch_forward_bs512(c.dc, ks, c.d_order, c.n_items, n0, ns, rec, st);
+    case 64: return emt::launch_forward_bs64(c.dc, ks, c.d_order, c.n_fwd, n0, ns, rec, st);
+    case 256: return emt::launch_forward_bs256(c.dc, ks, c.d_order, c.n_fwd, n0, ns, rec, st);
+    default: return emt::launch_forward_bs512(c.dc, ks, c.d_order, c.n_fwd, n0, ns, rec, st);
   }
+}
+
+// The split components' launch: arrival flags start at the step before the
+// first, the give-up flag clear.
+static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
+  for (const auto &f : c.split_flags)
+    hip_check(emt::launch_fill_i64(c.sc.flags + f.first, f.second, n0, st), "split flags");
+  hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
+  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.n_tiles, n0, ns, rec, c.split_lds, st),
+            "split forward");
+}
+
+// A split launch whose tiles gave up waiting leaves the error flag set.
+static void check_split(emt_ctx &c) {
+  if (c.n_tiles == 0) return;
+  int32_t err = 0;
+  hip_check(hipDeviceSynchronize(), "sync");
+  hip_check(hipMemcpy(&err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost), "split error flag");
+  if (err) throw emt::Error{EMT_EDEVICE, "a split-component launch gave up waiting for its workgroups"};
 }
 
 static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
@@ -586,9 +846,9 @@ static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
   ks.sm = c.sm_adj;
   if (!ks.sm) ks.bpt = c.bpt_global;
   switch (ks.bs) {
-    case 64: return emt::launch_adjoint_bs64(c.dc, ks, c.d_order, c.n_items, dJ, st);
-    case 256: return emt::launch_adjoint_bs256(c.dc, ks, c.d_order, c.n_items, dJ, st);
-    default: return emt::launch_adjoint_bs512(c.dc, ks, c.d_order, c.n_items, dJ, st);
+    case 64: return emt::launch_adjoint_bs64(c.dc, ks, c.d_order, c.n_fwd, dJ, st);
+    case 256: return emt::launch_adjoint_bs256(c.dc, ks, c.d_order, c.n_fwd, dJ, st);
+    default: return emt::launch_adjoint_bs512(c.dc, ks, c.d_order, c.n_fwd, dJ, st);
   }
 }
 
@@ -639,6 +899,7 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
     info->lds_limit = ctx->lds_limit;
     info->lds_staged = ctx->sm_fwd ? 1 : 0;
     info->lanes_per_block = ctx->ks.bpt;
+    info->split_tiles = ctx->n_tiles;
     return EMT_OK;
   });
 }
@@ -665,6 +926,9 @@ emt_status emt_factor(emt_ctx *ctx, void *stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     hip_check(emt::launch_fill_i32(ctx->dc.flags, 1, 0, st), "clear flags");
     hip_check(emt::launch_factor(ctx->dc, ctx->d_pairs, ctx->n_pairs, ctx->max_tail, st), "factor");
+    if (ctx->n_tiles > 0)
+      hip_check(emt::launch_inverse(ctx->dc, ctx->sc, ctx->d_inv_jobs, ctx->n_inv_jobs, ctx->inverse_lds, st),
+                "inverse");
     int32_t bad = 0;
     hip_check(hipMemcpyAsync(&bad, ctx->dc.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag");
     hip_check(hipStreamSynchronize(st), "factor sync");
@@ -685,7 +949,9 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
     if (ctx->step + n > ctx->sim.n_steps) return set_error(EMT_ESTATE, "stepping past n_steps");
     if (n == 0) return EMT_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    check_split(*ctx);
+    if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    if (ctx->n_tiles > 0) launch_split_step(*ctx, ctx->step, n, rec_dev, st);
     ctx->step += n;
     return EMT_OK;
   });
@@ -711,6 +977,7 @@ emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev
       return set_error(EMT_ESTATE, "needs a complete forward run from step 0 since the last change");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (!ctx->ks_adj_ok) return set_error(EMT_EINVAL, "a connected component is too large for the adjoint kernel");
+    if (ctx->n_tiles > 0) return set_error(EMT_EINVAL, "the split dense solver runs forward only");
     hip_check(launch_adjoint(*ctx, dJ_drec_dev, st), "adjoint");
     const int P = ctx->A.param_stride;
     hip_check(emt::launch_grad(ctx->dc, ctx->d_lptr, ctx->d_lent, ctx->d_line_scen, ctx->d_line_id,
@@ -742,6 +1009,7 @@ emt_status emt_get_state(emt_ctx *ctx, int32_t scen, double *v_host, double *i_h
   return guarded([&]() -> emt_status {
     if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size()) return set_error(EMT_EINVAL, "bad scenario");
     hip_check(hipDeviceSynchronize(), "sync");
+    check_split(*ctx);
     const emt::Scenario &sc = ctx->A.scens[scen];
     if (v_host) {
       std::vector<double> sv(ctx->nodes_total);

@@ -232,6 +232,11 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
   if (q < n) p[q] = v;
 }
 
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) p[q] = v;
@@ -351,6 +356,12 @@ hipError_t launch_grad(const DevCtx &c, const int32_t *lptr, const int64_t *lent
   if (n_lines_total > 0)
     hipLaunchKernelGGL(k_grad, dim3(blocks(n_lines_total, 256)), dim3(256), 0, st, c, lptr, lent, line_scen,
                        line_id, n_lines_total, grad, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3(blocks(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -23,9 +23,11 @@ enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2 };
 struct SymDesc {
   int32_t n, d, ns, nnz;        // nodes, dense-tail size, leading size, nonzeros of L
   int32_t nsv, nfpass, nbpass, nlev;  // sweep entries, sweep passes, factor levels
-  int32_t nfdesc, nbdesc, pad0, pad1;  // row descriptors of the passes
+  int32_t nfdesc, nbdesc, nlevb, pad1;  // row descriptors of the passes; backward levels
   // int32 (symi): full factor structure for the numeric factorisation
   int64_t rowptr, rowcol, colptr, colrow, colpos, flevptr, flevrows, fentptr, fent;
+  // int32 (symi): backward levels over all n rows (explicit inverse)
+  int64_t blevptr, blevrows;
   // int32 (symi): sweep plan: sv entry -> L entry; per pass (first row
   // descriptor, log2 lanes per row) pairs, nfpass+1 / nbpass+1 of them
   int64_t svmap, fpass, bpass;
@@ -50,6 +52,46 @@ struct ItemDesc {
   int64_t topo;  // scenario topology start steps [n_topo]
   int64_t ck;    // checkpoints (i, u) [n_ck][n_br]
   int64_t seg;   // adjoint segment buffer (i, u) [K+1][n_br]
+};
+
+// Components too large for one workgroup's dense tail, solved with their
+// whole inverse G^{-1} split by columns over P workgroups ("tiles"), each
+// tile holding kSplitCols columns in VGPRs. Per step a tile forms the
+// right-hand side of its own nodes, multiplies it into a partial voltage
+// vector for every node, publishes that, and sums the P partials of the
+// nodes its branches touch.
+constexpr int kSplitCols = 16;
+constexpr int kSplitBS = 512;
+constexpr int kSplitLanesPerNode = 8;  // lanes that sum one node's partials
+
+struct SplitItem {
+  int32_t item, P, cb, pad;  // item, tiles, inverse columns per workgroup of k_inverse
+  int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * kSplitCols + k)
+  int64_t gt;                // SplitCtx::gt: [n_topo][P][kSplitCols][n] inverse columns
+  int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] partial voltages (Pp = P rounded up to 8)
+  int64_t flag;              // SplitCtx::flags: [P] last step each tile has published
+};
+
+struct SplitTile {
+  int32_t sitem, p, cnt, nn;  // split item, tile index, owned columns, needed nodes (owned first)
+  int32_t nsrc, nrec, ne, pad;  // sources (first tile slots), owned recorded nodes, owned-node CSR entries
+  int64_t need;   // i32: [nn] item-local node of each slot
+  int64_t br;     // i32: [kSplitBS * bpt] item-local branch | writer << 30 (-1 = padding)
+  int64_t bpack;  // u32: [kSplitBS * bpt] slot terminals (ground = nn) | gamma class << 30
+  int64_t nptr;   // i32: [kSplitCols + 1] owned-node CSR of branch ends
+  int64_t nent;   // u16: (tile slot << 1 | end is m)
+  int64_t rec;    // u32: slot | output column << 16
+};
+
+struct SplitCtx {
+  const SplitItem *items;
+  const SplitTile *tiles;
+  const int32_t *i32;
+  const uint32_t *u32;
+  const uint16_t *u16;
+  double *gt, *xbuf;
+  int64_t *flags;
+  int32_t *err;  // set when a tile gives up waiting (the launch then ends early)
 };
 
 // Everything a kernel needs, passed by value.

@@ -1,0 +1,358 @@
+// Dense-inverse solve of components too large for one workgroup (Sec.
+// III-A's fourth process done as v = G^{-1} rhs, with G^{-1} formed once per
+// topology; Sec. III-B's single-task strategy spread over many compute
+// units). A component's inverse is split by columns over P workgroups
+// ("tiles"); tile p owns kSplitCols nodes (a block of a breadth-first order,
+// so a tile's branches touch few other nodes) and every branch incident to
+// them. Per step, a tile:
+//   1. sums the injections of its own nodes (fixed CSR order, DPP scan);
+//   2. multiplies them into its columns of G^{-1}: a partial voltage for
+//      every node, written to the component's exchange buffer;
+//   3. publishes the step number in its arrival flag (release) and waits for
+//      the flags of all P tiles (acquire; bounded wait);
+//   4. sums the P partials of each node its branches touch, always in tile
+//      order, so every tile obtains bitwise the same voltages;
+//   5. updates its branches (u, i, history, next injection) as the one-
+//      workgroup kernel does.
+// The exchange buffer is double-buffered by step parity: a tile writes the
+// buffer of step n+2 only after every tile has published step n+1, which
+// each does only after reading the partials of step n.
+// All tiles of a launch must be resident together: the launch is
+// cooperative, and a wait that outlasts kSpinLimit polls sets an error flag
+// and ends every tile's loop instead of hanging.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "launch.h"
+#include "step.h"
+
+namespace emt {
+
+namespace {
+
+using step::gamma_of;
+using step::group_sum;
+using step::kNever;
+using step::lds_barrier;
+using step::topo_of;
+
+constexpr int64_t kSpinLimit = int64_t(1) << 22;
+
+__device__ __forceinline__ int tid_() { return step::lane_id(); }
+
+}  // namespace
+
+// Columns of G^{-1} = (L D L^T)^{-1} for one (split item, topology, block of
+// cb columns): forward substitution L y = e_j level by level, then
+// x = D^{-1} y - L^T x level by level (backward levels over all rows), with
+// the block's columns side by side in LDS ([row][cb]). Column j is written
+// to its tile's slot in gt.
+__global__ __launch_bounds__(256) void k_inverse(DevCtx c, SplitCtx s, const int32_t *jobs) {
+  double *Y = reinterpret_cast<double *>(step::emt_lds);
+  const int si = jobs[3 * blockIdx.x], t = jobs[3 * blockIdx.x + 1], j0 = jobs[3 * blockIdx.x + 2];
+  const SplitItem sp = s.items[si];
+  const ItemDesc it = c.items[sp.item];
+  const SymDesc sd = c.syms[it.sym];
+  const int n = it.n, cb = sp.cb;
+  const int nc = min(cb, n - j0);
+  const double *Lr = c.lfull + it.fac + (int64_t)t * sd.nnz;
+  const double *D = c.dpiv + it.dfac + (int64_t)t * n;
+  const int32_t *rowptr = c.symi + sd.rowptr, *rowcol = c.symi + sd.rowcol;
+  const int32_t *colptr = c.symi + sd.colptr, *colrow = c.symi + sd.colrow, *colpos = c.symi + sd.colpos;
+  const int32_t *flevptr = c.symi + sd.flevptr, *flevrows = c.symi + sd.flevrows;
+  const int32_t *blevptr = c.symi + sd.blevptr, *blevrows = c.symi + sd.blevrows;
+  for (int l = 0; l < sd.nlev; ++l) {
+    const int p0 = flevptr[l], cnt = (flevptr[l + 1] - p0) * cb;
+    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+      const int i = flevrows[p0 + idx / cb], cc = idx % cb;
+      double acc = (i == j0 + cc) ? 1.0 : 0.0;
+      for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) acc = acc - Lr[q] * Y[rowcol[q] * cb + cc];
+      Y[i * cb + cc] = acc;
+    }
+    __syncthreads();
+  }
+  for (int l = 0; l < sd.nlevb; ++l) {
+    const int p0 = blevptr[l], cnt = (blevptr[l + 1] - p0) * cb;
+    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+      const int i = blevrows[p0 + idx / cb], cc = idx % cb;
+      double acc = Y[i * cb + cc] / D[i];
+      for (int e = colptr[i]; e < colptr[i + 1]; ++e) acc = acc - Lr[colpos[e]] * Y[colrow[e] * cb + cc];
+      Y[i * cb + cc] = acc;
+    }
+    __syncthreads();
+  }
+  const int32_t *pos = s.i32 + sp.pos;
+  for (int cc = 0; cc < nc; ++cc) {
+    const int tp = pos[j0 + cc];
+    double *dst = s.gt + sp.gt + ((int64_t)t * sp.P * kSplitCols + tp) * n;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) dst[r] = Y[r * cb + cc];
+  }
+}
+
+// Forward time loop of the split components: one workgroup per tile, all
+// steps n0+1 .. n0+nsteps.
+template <int BPT, int RPL>
+__global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_t n0, int64_t nsteps,
+                                                   double *rec) {
+  constexpr int BS = kSplitBS, RT = kSplitCols, LQ = kSplitLanesPerNode;
+  const SplitTile tl = s.tiles[blockIdx.x];
+  const SplitItem sp = s.items[tl.sitem];
+  const ItemDesc it = c.items[sp.item];
+  const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7;
+
+  // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
+  // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag.
+  auto take = [](uint32_t &off, size_t bytes) {
+    const uint32_t o = off;
+    off += (uint32_t)((bytes + 15) & ~(size_t)15);
+    return o;
+  };
+  uint32_t off = 0;
+  const uint32_t ox = take(off, (size_t)(nn + 1) * 8), oJ = take(off, (size_t)BS * BPT * 8),
+                 orhs = take(off, RT * 8), oneed = take(off, (size_t)nn * 4), onp = take(off, (RT + 1) * 4),
+                 one = take(off, (size_t)tl.ne * 2), orec = take(off, (size_t)tl.nrec * 4),
+                 oab = take(off, 4);
+  step::Lds<double> x{ox}, J{oJ}, rhs{orhs};
+  step::Lds<int32_t> need{oneed}, nptr{onp}, abort_flag{oab};
+  step::Lds<uint16_t> nent{one};
+  step::Lds<uint32_t> recl{orec};
+  for (int q = threadIdx.x; q < nn; q += BS) need[q] = s.i32[tl.need + q];
+  for (int q = threadIdx.x; q <= RT; q += BS) nptr[q] = q <= tl.cnt ? s.i32[tl.nptr + q] : s.i32[tl.nptr + tl.cnt];
+  for (int q = threadIdx.x; q < tl.ne; q += BS) nent[q] = s.u16[tl.nent + q];
+  for (int q = threadIdx.x; q < tl.nrec; q += BS) recl[q] = s.u32[tl.rec + q];
+  for (int q = threadIdx.x; q < RT; q += BS) rhs[q] = 0.0;
+  if (threadIdx.x == 0) {
+    x[nn] = 0.0;
+    abort_flag[0] = 0;
+  }
+
+  const int64_t *topo = c.topo + it.topo;
+  int t = topo_of(topo, it.n_topo, n0 + 1);
+  int64_t next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
+
+  // Branch slots of this lane: item-local branch (or -1), owner bit, packed
+  // terminals, coefficients and history.
+  int bid[BPT];
+  bool own[BPT];
+  uint32_t pk[BPT];
+  double g[BPT], be[BPT], h[BPT];
+  const int tid0 = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    const int v = s.i32[tl.br + tid0 + j * BS];
+    bid[j] = v < 0 ? -1 : (v & 0x3FFFFFFF);
+    own[j] = v >= 0 && ((v >> 30) & 1);
+    pk[j] = s.u32[tl.bpack + tid0 + j * BS];
+    const int64_t cbase = it.coef + (int64_t)t * it.n_br;
+    g[j] = bid[j] >= 0 ? c.cg[cbase + bid[j]] : 0.0;
+    be[j] = bid[j] >= 0 ? c.cb[cbase + bid[j]] : 0.0;
+    h[j] = bid[j] >= 0 ? be[j] * c.si[it.br + bid[j]] + gamma_of(pk[j], g[j]) * c.su[it.br + bid[j]] : 0.0;
+  }
+  const bool src = tid0 < tl.nsrc;
+  const double sE = src ? c.bE[it.br + bid[0]] : 0.0, sw = src ? c.bw[it.br + bid[0]] : 0.0,
+               sph = src ? c.bph[it.br + bid[0]] : 0.0;
+  auto emf = [&](int64_t m) { return src ? sE * emf_cos(sw * ((double)m * c.dt) + sph) : 0.0; };
+
+  // This tile's columns of G^{-1} for the rows r = lane + rr * BS.
+  double w[RPL * RT];
+  auto load_inverse = [&](int tt) {
+    const double *gsrc = s.gt + sp.gt + ((int64_t)tt * P + tl.p) * RT * (int64_t)n;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+      const int r = tid0 + rr * BS;
+#pragma unroll
+      for (int k = 0; k < RT; ++k) w[rr * RT + k] = r < n ? gsrc[(int64_t)k * n + r] : 0.0;
+    }
+  };
+  load_inverse(t);
+
+  double e0 = emf(n0 + 1);
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) J[tid0 + j * BS] = g[j] * (j == 0 ? e0 : 0.0) - h[j];
+  __syncthreads();
+
+  double *xb = s.xbuf + sp.xbuf;
+  int64_t *fl = s.flags + sp.flag;
+  const int R = c.rec_stride;
+  const int64_t n_end = n0 + nsteps;
+  for (int64_t m = n0 + 1; m <= n_end; ++m) {
+    const int tid = tid_();
+    // 1. injections of the owned nodes, 16 lanes per node
+    {
+      const int node = tid >> 4, sub = tid & 15;
+      double acc = 0.0;
+      if (node < tl.cnt) {
+        for (int e = nptr[node] + sub; e < nptr[node + 1]; e += 16) {
+          const int ent = nent[e];
+          const double jv = J[ent >> 1];
+          acc = (ent & 1) ? acc - jv : acc + jv;
+        }
+      }
+      acc = group_sum(acc, 4, sub);
+      if (node < tl.cnt && sub == 15) rhs[node] = acc;
+    }
+    lds_barrier();
+    // 2. partial voltages of every node from this tile's columns
+    double rv[RT];
+#pragma unroll
+    for (int k = 0; k < RT; ++k) rv[k] = rhs[k];
+    double *xw = xb + (int64_t)(m & 1) * n * Pp;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+      const int r = tid + rr * BS;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < RT; ++k) acc = acc + w[rr * RT + k] * rv[k];
+      if (r < n) xw[(int64_t)r * Pp + tl.p] = acc;
+    }
+    // 3. publish, then wait for every tile of the component. The pattern is
+    // that of a grid barrier: the workgroup barrier orders every wave's
+    // partial stores before lane 0's device-scope release (the stores of
+    // one compute unit reach its L2 in issue order), lane 0 publishes, wave
+    // 0 polls and acquires, and a second workgroup barrier releases the
+    // other waves.
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(fl + tl.p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < 64) {
+      int64_t spins = 0;
+      bool give_up = false;
+      for (;;) {
+        bool ready = true;
+        for (int q = tid; q < P; q += 64)
+          ready = ready && (__hip_atomic_load(fl + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= m);
+        if (__all(ready)) break;
+        if (++spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          give_up = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (give_up && tid == 0) {
+        __hip_atomic_store(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        abort_flag[0] = 1;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (abort_flag[0]) break;
+    // 4. voltages of the needed nodes: the P partials summed in tile order
+    {
+      const double *xr = xb + (int64_t)(m & 1) * n * Pp;
+      const int sub = tid & (LQ - 1);
+      for (int slot = tid / LQ; slot < nn; slot += BS / LQ) {
+        const double *row = xr + (int64_t)need[slot] * Pp;
+        double acc = 0.0;
+        for (int q = sub; q < P; q += LQ) acc = acc + row[q];
+        acc = group_sum(acc, 3, sub);
+        if (sub == LQ - 1) x[slot] = acc;
+      }
+    }
+    lds_barrier();
+    // 5. record, branch update, next injection
+    if (rec) {
+      double *row = rec + ((int64_t)it.scen * nsteps + (m - n0 - 1)) * R;
+      for (int q = tid; q < tl.nrec; q += BS) {
+        const uint32_t pr = recl[q];
+        row[pr >> 16] = x[(int)(pr & 0xFFFF)];
+      }
+    }
+    const bool swn = (m + 1 == next);
+    const bool last = (m == n_end);
+    const double e_next = last ? 0.0 : emf(m + 1);
+    const int64_t ncoef = it.coef + (int64_t)(t + 1) * it.n_br;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const double vk = x[(int)(pk[j] & kTermGround)], vm = x[(int)((pk[j] >> 15) & kTermGround)];
+      const double e = j == 0 ? e0 : 0.0;
+      const double u = (g[j] != 0.0) ? (vk - vm) - e : 0.0;
+      const double i = g[j] * u + h[j];
+      if (last && own[j]) {
+        c.si[it.br + bid[j]] = i;
+        c.su[it.br + bid[j]] = u;
+      }
+      if (swn) {
+        g[j] = bid[j] >= 0 ? c.cg[ncoef + bid[j]] : 0.0;
+        be[j] = bid[j] >= 0 ? c.cb[ncoef + bid[j]] : 0.0;
+      }
+      h[j] = be[j] * i + gamma_of(pk[j], g[j]) * u;
+      if (!last) J[tid + j * BS] = g[j] * (j == 0 ? e_next : 0.0) - h[j];
+    }
+    e0 = e_next;
+    if (swn) {
+      ++t;
+      next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
+      load_inverse(t);
+    }
+    if (last)
+      for (int q = tid; q < tl.cnt; q += BS) c.sv_state[it.node + need[q]] = x[q];
+    lds_barrier();
+  }
+}
+
+size_t split_lds_bytes(int nn, int bpt, int ne, int nrec) {
+  auto arr = [](size_t bytes) { return (bytes + 15) & ~(size_t)15; };
+  return arr((size_t)(nn + 1) * 8) + arr((size_t)kSplitBS * bpt * 8) + arr(kSplitCols * 8) + arr((size_t)nn * 4) +
+         arr((kSplitCols + 1) * 4) + arr((size_t)ne * 2) + arr((size_t)nrec * 4) + arr(4);
+}
+
+hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *jobs, int n_jobs, size_t lds,
+                          hipStream_t st) {
+  if (n_jobs == 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_inverse),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_inverse, dim3(n_jobs), dim3(256), lds, st, c, s, jobs);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <int BPT, int RPL>
+hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_tiles, int64_t n0, int64_t ns, double *rec,
+                        size_t lds, hipStream_t st) {
+  auto k = k_split<BPT, RPL>;
+  hipError_t e =
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  DevCtx ca = c;
+  SplitCtx sa = s;
+  void *args[] = {&ca, &sa, &n0, &ns, &rec};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(n_tiles), dim3(kSplitBS), args,
+                                    (unsigned)lds, st);
+}
+
+template <int BPT, int RPL>
+hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
+  auto k = k_split<BPT, RPL>;
+  hipError_t e =
+      hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(k), kSplitBS,
+                                                      lds);
+}
+
+}  // namespace
+
+#define EMT_SPLIT_SHAPES(X) X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4)
+
+hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int n_tiles, int64_t n0, int64_t ns,
+                        double *rec, size_t lds, hipStream_t st) {
+#define EMT_CASE(B, R) \
+  if (bpt == B && rpl == R) return split_launch<B, R>(c, s, n_tiles, n0, ns, rec, lds, st);
+  EMT_SPLIT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t split_blocks_per_cu(int bpt, int rpl, size_t lds, int *blocks) {
+#define EMT_CASE(B, R) \
+  if (bpt == B && rpl == R) return split_occupancy<B, R>(blocks, lds);
+  EMT_SPLIT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace emt

@@ -1,5 +1,5 @@
 // Instantiations of the step kernels for one workgroup size (EMT_BS, set by
-// the build: 64, 256 or 1024), so the three sizes compile in parallel.
+// the build: 64, 256 or 512), so the three sizes compile in parallel.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
