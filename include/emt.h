@@ -144,6 +144,7 @@ typedef struct {
   int32_t lds_staged;    /* 1 if index arrays and factors are staged in LDS */
   int32_t lanes_per_block; /* branches per lane */
   int32_t split_tiles;   /* workgroups of the split dense components (0 if none) */
+  int32_t split_cols;    /* inverse columns per split workgroup (16 or 32; 0 if none) */
 } emt_info;
 
 /* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and

@@ -60,7 +60,7 @@ class EmtInfo(C.Structure):
         ("dense_items", C.c_int32), ("block_size", C.c_int32),
         ("sweep_levels", C.c_int32), ("max_tail", C.c_int32), ("lds_bytes", C.c_int32),
         ("lds_limit", C.c_int32), ("lds_staged", C.c_int32), ("lanes_per_block", C.c_int32),
-        ("split_tiles", C.c_int32),
+        ("split_tiles", C.c_int32), ("split_cols", C.c_int32),
     ]
 
     def as_dict(self):

@@ -76,7 +76,7 @@ struct emt_ctx {
   int n_fwd = 0;
   std::vector<char> is_split;
   emt::SplitCtx sc{};
-  int n_tiles = 0, split_bpt = 1, split_rpl = 1;
+  int n_tiles = 0, split_bpt = 1, split_rpl = 1, split_rt = 16;
   size_t split_lds = 0, inverse_lds = 0;
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
@@ -202,16 +202,38 @@ static int pass_lanes_log2(int rows, int maxcnt, int bs) {
 }
 
 // Tiles of the split dense components: a breadth-first order of each
-// component's nodes cut into blocks of kSplitCols columns; a tile takes every
+// component's nodes cut into blocks of rt columns; a tile takes every
 // branch incident to its block (a branch between two blocks belongs to both,
 // and the block of its k terminal writes its state), the nodes those
 // branches touch, the CSR of its own nodes' branch ends and its recorded
 // nodes. Then the device arrays, the inverse jobs and the launch shape.
+static bool split_shape_exists(int bpt, int rpl, int rt) { return rt == 16 || (rpl <= 2 && bpt * rpl <= 4); }
+
+static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int rt);
+
 static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
+  // columns per tile: 32 halves the tiles and the partials each node sums;
+  // 16 where the lane state of 32 would not fit the VGPRs
+  const int want = env_int("EMT_SPLIT_COLS", 32) == 16 ? 16 : 32;
+  if (!build_split_with(c, bpack, want)) (void)build_split_with(c, bpack, 16);
+}
+
+static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int rt) {
   using namespace emt;
   const Analysis &A = c.A;
   const int NI = (int)A.items.size();
-  constexpr int RT = kSplitCols;
+  int max_split_n = 0;
+  for (int q = 0; q < NI; ++q)
+    if (c.is_split[q]) max_split_n = std::max(max_split_n, A.items[q].n);
+  if (max_split_n == 0) return true;
+  const int rpl = (max_split_n + kSplitBS - 1) / kSplitBS;
+  if (rpl > 4) throw Error{EMT_EINVAL, "the dense solver splits components of at most " +
+                                           std::to_string(4 * kSplitBS) + " nodes"};
+  c.split_rpl = rpl <= 1 ? 1 : (rpl <= 2 ? 2 : 4);
+  if (!split_shape_exists(1, c.split_rpl, rt)) return false;
+  c.split_rt = rt;
+  c.split_flags.clear();
+  const int RT = rt;
   std::vector<SplitItem> sitems;
   std::vector<SplitTile> tiles;
   std::vector<int32_t> i32;
@@ -219,7 +241,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
   std::vector<uint16_t> u16;
   std::vector<int32_t> jobs;
   int64_t gt_off = 0, xb_off = 0, fl_off = 0;
-  int max_slots = 0, max_n = 0;
+  int max_slots = 0;
   size_t inv_lds = 0;
   struct TileLists {
     std::vector<int> br, need, nptr, nent;
@@ -232,7 +254,6 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
     const Item &it = A.items[q];
     const Scenario &sc = A.scens[it.scen];
     const int n = it.n;
-    max_n = std::max(max_n, n);
     // adjacency over real branches, breadth-first order from node 0
     std::vector<std::vector<int>> adj(n);
     for (int b = 0; b < it.n_br; ++b) {
@@ -259,6 +280,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
     SplitItem si{};
     si.item = q;
     si.P = P;
+    si.rt = RT;
     si.cb = std::max(1, std::min(16, 20000 / n));
     si.pos = (int64_t)i32.size();
     i32.insert(i32.end(), pos.begin(), pos.end());
@@ -337,7 +359,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
     sitems.push_back(si);
     all.push_back(std::move(tl));
   }
-  if (sitems.empty()) return;
+  if (sitems.empty()) return true;
   int bpt = 0;
   for (int cand : {1, 2, 4})
     if (cand * kSplitBS >= max_slots) {
@@ -345,10 +367,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
       break;
     }
   if (bpt == 0) throw Error{EMT_EINVAL, "a split tile has more than " + std::to_string(4 * kSplitBS) + " branches"};
-  const int rpl = (max_n + kSplitBS - 1) / kSplitBS;
-  if (rpl > 4) throw Error{EMT_EINVAL, "the dense solver splits components of at most " +
-                                           std::to_string(4 * kSplitBS) + " nodes"};
-  c.split_rpl = rpl <= 1 ? 1 : (rpl <= 2 ? 2 : 4);
+  if (!split_shape_exists(bpt, c.split_rpl, rt)) return false;
   c.split_bpt = bpt;
   const int slots = bpt * kSplitBS;
   size_t lds = 0;
@@ -377,7 +396,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
       for (int e : T.nent) u16.push_back((uint16_t)e);
       d.rec = (int64_t)u32.size();
       u32.insert(u32.end(), T.rec.begin(), T.rec.end());
-      lds = std::max(lds, split_lds_bytes(d.nn, bpt, d.ne, d.nrec));
+      lds = std::max(lds, split_lds_bytes(d.nn, bpt, d.ne, d.nrec, RT));
       tiles.push_back(d);
     }
   }
@@ -386,7 +405,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
   c.split_lds = lds;
   c.inverse_lds = inv_lds;
   int per_cu = 0, n_cu = 0;
-  hip_check(split_blocks_per_cu(c.split_bpt, c.split_rpl, lds, &per_cu), "split occupancy");
+  hip_check(split_blocks_per_cu(c.split_bpt, c.split_rpl, c.split_rt, lds, &per_cu), "split occupancy");
   hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device), "CU count");
   if ((int64_t)per_cu * n_cu < c.n_tiles)
     throw Error{EMT_EINVAL, "the split components need " + std::to_string(c.n_tiles) +
@@ -403,6 +422,7 @@ static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
   c.sc.err = c.dc.flags + 1;
   c.d_inv_jobs = c.upload(jobs);
   c.n_inv_jobs = (int)jobs.size() / 3;
+  return true;
 }
 
 static void upload_all(emt_ctx &c, const emt_net *nets) {
@@ -828,7 +848,8 @@ static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, h
   for (const auto &f : c.split_flags)
     hip_check(emt::launch_fill_i64(c.sc.flags + f.first, f.second, n0, st), "split flags");
   hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
-  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.n_tiles, n0, ns, rec, c.split_lds, st),
+  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.n_tiles, n0, ns, rec,
+                              c.split_lds, st),
             "split forward");
 }
 
@@ -900,6 +921,7 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
     info->lds_staged = ctx->sm_fwd ? 1 : 0;
     info->lanes_per_block = ctx->ks.bpt;
     info->split_tiles = ctx->n_tiles;
+    info->split_cols = ctx->n_tiles > 0 ? ctx->split_rt : 0;
     return EMT_OK;
   });
 }

@@ -56,18 +56,18 @@ struct ItemDesc {
 
 // Components too large for one workgroup's dense tail, solved with their
 // whole inverse G^{-1} split by columns over P workgroups ("tiles"), each
-// tile holding kSplitCols columns in VGPRs. Per step a tile forms the
+// tile holding rt (16 or 32) columns in VGPRs. Per step a tile forms the
 // right-hand side of its own nodes, multiplies it into a partial voltage
 // vector for every node, publishes that, and sums the P partials of the
 // nodes its branches touch.
-constexpr int kSplitCols = 16;
+constexpr int kSplitColsMax = 32;
 constexpr int kSplitBS = 512;
 constexpr int kSplitLanesPerNode = 8;  // lanes that sum one node's partials
 
 struct SplitItem {
-  int32_t item, P, cb, pad;  // item, tiles, inverse columns per workgroup of k_inverse
-  int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * kSplitCols + k)
-  int64_t gt;                // SplitCtx::gt: [n_topo][P][kSplitCols][n] inverse columns
+  int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile
+  int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * rt + k)
+  int64_t gt;                // SplitCtx::gt: [n_topo][P][rt][n] inverse columns
   int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] partial voltages (Pp = P rounded up to 8)
   int64_t flag;              // SplitCtx::flags: [P] last step each tile has published
 };
@@ -78,7 +78,7 @@ struct SplitTile {
   int64_t need;   // i32: [nn] item-local node of each slot
   int64_t br;     // i32: [kSplitBS * bpt] item-local branch | writer << 30 (-1 = padding)
   int64_t bpack;  // u32: [kSplitBS * bpt] slot terminals (ground = nn) | gamma class << 30
-  int64_t nptr;   // i32: [kSplitCols + 1] owned-node CSR of branch ends
+  int64_t nptr;   // i32: [cnt + 1] owned-node CSR of branch ends
   int64_t nent;   // u16: (tile slot << 1 | end is m)
   int64_t rec;    // u32: slot | output column << 16
 };

@@ -2,7 +2,7 @@
 // III-A's fourth process done as v = G^{-1} rhs, with G^{-1} formed once per
 // topology; Sec. III-B's single-task strategy spread over many compute
 // units). A component's inverse is split by columns over P workgroups
-// ("tiles"); tile p owns kSplitCols nodes (a block of a breadth-first order,
+// ("tiles"); tile p owns rt nodes (a block of a breadth-first order,
 // so a tile's branches touch few other nodes) and every branch incident to
 // them. Per step, a tile:
 //   1. sums the injections of its own nodes (fixed CSR order, DPP scan);
@@ -37,6 +37,9 @@ using step::lds_barrier;
 using step::topo_of;
 
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
+// partials summed by one lane: P <= kSplitLanesPerNode * this (P <= 128
+// tiles, components of up to 2048 nodes)
+constexpr int kMaxPartialsPerLane = 16;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
 
@@ -84,17 +87,18 @@ __global__ __launch_bounds__(256) void k_inverse(DevCtx c, SplitCtx s, const int
   const int32_t *pos = s.i32 + sp.pos;
   for (int cc = 0; cc < nc; ++cc) {
     const int tp = pos[j0 + cc];
-    double *dst = s.gt + sp.gt + ((int64_t)t * sp.P * kSplitCols + tp) * n;
+    double *dst = s.gt + sp.gt + ((int64_t)t * sp.P * sp.rt + tp) * n;
     for (int r = threadIdx.x; r < n; r += blockDim.x) dst[r] = Y[r * cb + cc];
   }
 }
 
 // Forward time loop of the split components: one workgroup per tile, all
 // steps n0+1 .. n0+nsteps.
-template <int BPT, int RPL>
+template <int BPT, int RPL, int RT>
 __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_t n0, int64_t nsteps,
                                                    double *rec) {
-  constexpr int BS = kSplitBS, RT = kSplitCols, LQ = kSplitLanesPerNode;
+  constexpr int BS = kSplitBS, LQ = kSplitLanesPerNode;
+  static_assert(RT * 16 <= BS, "16 lanes per owned node");
   const SplitTile tl = s.tiles[blockIdx.x];
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
@@ -203,7 +207,9 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < RT; ++k) acc = acc + w[rr * RT + k] * rv[k];
-      if (r < n) xw[(int64_t)r * Pp + tl.p] = acc;
+      // device-coherent stores: written through to where other compute
+      // units read them, so the release below has no dirty lines to flush
+      if (r < n) __hip_atomic_store(xw + (int64_t)r * Pp + tl.p, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // 3. publish, then wait for every tile of the component. The pattern is
     // that of a grid barrier: the workgroup barrier orders every wave's
@@ -244,8 +250,16 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       const int sub = tid & (LQ - 1);
       for (int slot = tid / LQ; slot < nn; slot += BS / LQ) {
         const double *row = xr + (int64_t)need[slot] * Pp;
+        // all loads in flight before the in-order sum
+        double pv[kMaxPartialsPerLane];
+#pragma unroll
+        for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+          const int q = sub + k * LQ;
+          pv[k] = q < P ? row[q] : 0.0;
+        }
         double acc = 0.0;
-        for (int q = sub; q < P; q += LQ) acc = acc + row[q];
+#pragma unroll
+        for (int k = 0; k < kMaxPartialsPerLane; ++k) acc = acc + pv[k];
         acc = group_sum(acc, 3, sub);
         if (sub == LQ - 1) x[slot] = acc;
       }
@@ -292,10 +306,10 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   }
 }
 
-size_t split_lds_bytes(int nn, int bpt, int ne, int nrec) {
+size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt) {
   auto arr = [](size_t bytes) { return (bytes + 15) & ~(size_t)15; };
-  return arr((size_t)(nn + 1) * 8) + arr((size_t)kSplitBS * bpt * 8) + arr(kSplitCols * 8) + arr((size_t)nn * 4) +
-         arr((kSplitCols + 1) * 4) + arr((size_t)ne * 2) + arr((size_t)nrec * 4) + arr(4);
+  return arr((size_t)(nn + 1) * 8) + arr((size_t)kSplitBS * bpt * 8) + arr((size_t)rt * 8) + arr((size_t)nn * 4) +
+         arr((size_t)(rt + 1) * 4) + arr((size_t)ne * 2) + arr((size_t)nrec * 4) + arr(4);
 }
 
 hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *jobs, int n_jobs, size_t lds,
@@ -310,10 +324,10 @@ hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *job
 
 namespace {
 
-template <int BPT, int RPL>
+template <int BPT, int RPL, int RT>
 hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_tiles, int64_t n0, int64_t ns, double *rec,
                         size_t lds, hipStream_t st) {
-  auto k = k_split<BPT, RPL>;
+  auto k = k_split<BPT, RPL, RT>;
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -324,9 +338,9 @@ hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_tiles, int64_t
                                     (unsigned)lds, st);
 }
 
-template <int BPT, int RPL>
+template <int BPT, int RPL, int RT>
 hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
-  auto k = k_split<BPT, RPL>;
+  auto k = k_split<BPT, RPL, RT>;
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -336,20 +350,24 @@ hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
 
 }  // namespace
 
-#define EMT_SPLIT_SHAPES(X) X(1, 1) X(1, 2) X(1, 4) X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4)
+// (branch slots per lane, inverse rows per lane, columns per tile); 32
+// columns only where the lane state fits the VGPRs without spilling
+#define EMT_SPLIT_SHAPES(X)                                                                          \
+  X(1, 1, 16) X(1, 2, 16) X(1, 4, 16) X(2, 1, 16) X(2, 2, 16) X(2, 4, 16) X(4, 1, 16) X(4, 2, 16) \
+  X(4, 4, 16) X(1, 1, 32) X(1, 2, 32) X(2, 1, 32) X(2, 2, 32) X(4, 1, 32)
 
-hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int n_tiles, int64_t n0, int64_t ns,
-                        double *rec, size_t lds, hipStream_t st) {
-#define EMT_CASE(B, R) \
-  if (bpt == B && rpl == R) return split_launch<B, R>(c, s, n_tiles, n0, ns, rec, lds, st);
+hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_tiles, int64_t n0,
+                        int64_t ns, double *rec, size_t lds, hipStream_t st) {
+#define EMT_CASE(B, R, W) \
+  if (bpt == B && rpl == R && rt == W) return split_launch<B, R, W>(c, s, n_tiles, n0, ns, rec, lds, st);
   EMT_SPLIT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t split_blocks_per_cu(int bpt, int rpl, size_t lds, int *blocks) {
-#define EMT_CASE(B, R) \
-  if (bpt == B && rpl == R) return split_occupancy<B, R>(blocks, lds);
+hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks) {
+#define EMT_CASE(B, R, W) \
+  if (bpt == B && rpl == R && rt == W) return split_occupancy<B, R, W>(blocks, lds);
   EMT_SPLIT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;

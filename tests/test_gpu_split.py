@@ -40,13 +40,19 @@ def dense_sim(nets, dt, T):
     return sim
 
 
-def test_split_grid200_events_vs_oracle(torch_cuda, oracle_mod):
+def tiles(n_bus, cols):
+    return 3 * -(-n_bus // cols)
+
+
+@pytest.mark.parametrize("cols", [16, 32])
+def test_split_grid200_events_vs_oracle(torch_cuda, oracle_mod, monkeypatch, cols):
+    monkeypatch.setenv("EMT_SPLIT_COLS", str(cols))
     net = netgen.small_grid(41, 200, fault_step=150, remove_series=5, remove_step=300, n_mon=40)
-    say("split: grid200 (3 x 200 nodes), fault at 150, branch out at 300, 500 steps")
+    say(f"split: grid200 (3 x 200 nodes), {cols} columns per tile, fault at 150, branch out at 300, 500 steps")
     sim = dense_sim([net], 20e-6, 500)
     info = sim.info()
     say("split tiles", info["split_tiles"])
-    assert info["split_tiles"] == 3 * 13
+    assert info["split_cols"] == cols and info["split_tiles"] == tiles(200, cols)
     rec = sim.step(500).cpu().numpy()
     ref = oracle_mod.run(net, 20e-6, 500)
     err = rel(rec[0], ref)
@@ -61,7 +67,8 @@ def test_split_grid1000_fault_vs_oracle(torch_cuda, oracle_mod):
     nets, cfg = netgen.config1(n_steps=320, fault_step=150)
     say("split: grid1000 (3 x 1000 nodes), fault at 150, 320 steps")
     sim = dense_sim(nets, cfg["dt"], 320)
-    assert sim.info()["split_tiles"] == 3 * 63
+    info = sim.info()
+    assert info["split_tiles"] == tiles(1000, info["split_cols"])
     rec = sim.step(320).cpu().numpy()[0]
     ref = oracle_mod.run(nets[0], cfg["dt"], 320)
     err = rel(rec, ref)
@@ -108,7 +115,8 @@ def test_split_mixed_with_one_workgroup_components(torch_cuda, oracle_mod):
     b = netgen.small_grid(44, 180, fault_step=120, n_mon=20)
     say("split: mixed batch of a 40-bus and a 180-bus grid, 250 steps")
     sim = dense_sim([a, b], 20e-6, 250)
-    assert sim.info()["split_tiles"] == 3 * 12
+    info = sim.info()
+    assert info["split_tiles"] == tiles(180, info["split_cols"])
     rec = sim.step(250).cpu().numpy()
     for s, net in enumerate((a, b)):
         ref = oracle_mod.run(net, 20e-6, 250)
