@@ -34,39 +34,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_step(info, n_rec_total):
+def algorithmic_bytes_per_step(info, n_rec_total, component_sizes=None):
     """Bytes one time step touches if nothing stayed on chip: branch
     coefficients, terminals and state (g, beta, gamma, k, m, i, u read;
-    i, u written: 64 B per branch), the L factor read twice with its index
-    (24 B per strictly-lower nonzero), D^-1 (8 B per node) and the recorded
-    outputs (8 B each)."""
-    return (64 * info["total_branches"] + 24 * info["nnz_L"] + 8 * info["total_nodes"]
-            + 8 * n_rec_total)
+    i, u written: 64 B per branch) and the recorded outputs (8 B each),
+    plus the solve: for the sweeps the L factor read twice with its index
+    (24 B per strictly-lower nonzero) and D^-1 (8 B per node); for the dense
+    inverse (component_sizes given) the whole inverse of every component
+    (8 n^2 B)."""
+    b = 64 * info["total_branches"] + 8 * n_rec_total
+    if component_sizes is None:
+        return b + 24 * info["nnz_L"] + 8 * info["total_nodes"]
+    return b + 8 * sum(int(n) ** 2 for n in component_sizes)
 
 
-KERNEL_SOURCES = ("paper_1903_01081_amd/csrc/step.h", "paper_1903_01081_amd/csrc/step.hip",
-                  "paper_1903_01081_amd/csrc/device.h")
-TRAFFIC_PROFILE = "profiles/k_forward_grid1000.md"
+def component_sizes(net):
+    """Node counts of the connected components of a network's branch graph."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    ok = (net.k >= 0) & (net.m >= 0)
+    g = sp.coo_matrix((np.ones(int(ok.sum())), (net.k[ok], net.m[ok])), shape=(net.n_nodes, net.n_nodes))
+    _, lab = connected_components(g, directed=False)
+    return np.bincount(lab)
 
 
-def kernel_source_digest():
+# Per step kernel: its sources and the committed rocprofv3 summary of the
+# grid1000 workload that holds its measured HBM traffic.
+KERNELS = {
+    "k_forward": (("paper_1903_01081_amd/csrc/step.h", "paper_1903_01081_amd/csrc/step.hip",
+                   "paper_1903_01081_amd/csrc/device.h"), "profiles/k_forward_grid1000.md"),
+    "k_split": (("paper_1903_01081_amd/csrc/split.hip", "paper_1903_01081_amd/csrc/step.h",
+                 "paper_1903_01081_amd/csrc/device.h"), "profiles/k_split_grid1000.md"),
+}
+KERNEL_SOURCES, TRAFFIC_PROFILE = KERNELS["k_forward"]
+
+
+def kernel_source_digest(sources=None):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if sources is None else sources):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_forward launch from the committed rocprofv3
+def measured_traffic(kernel=None):
+    """HBM bytes per launch of a step kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or
     None when the kernel sources have changed since it was taken."""
+    sources, profile = (KERNEL_SOURCES, TRAFFIC_PROFILE) if kernel is None else KERNELS[kernel]
     try:
-        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+        with open(os.path.join(ROOT, profile)) as fh:
             for line in fh:
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
-                    if rec.get("source_digest") == kernel_source_digest():
+                    if rec.get("source_digest") == kernel_source_digest(sources):
                         return float(rec["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         pass
@@ -127,33 +148,57 @@ def cpu_baseline_config1(nets, cfg):
                       f"factorisation {factor:.2f} s extrapolated to 50,000 steps and 2 factorisations"}
 
 
+def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
+    """grid1000 over the whole horizon with the other solver family than the
+    tuned one (one-workgroup sparse sweeps + dense tail vs the column-split
+    dense inverse), plus the tuner's prefix timings of every shape."""
+    from paper_1903_01081_amd.sim import Simulator
+    N, T = nets[0].n_nodes, cfg["n_steps"]
+    other = dict(solver="auto") if shape.get("solver") == "dense" else dict(solver="dense")
+    sim = Simulator(nets, cfg["dt"], T, **other)
+    rec = torch.empty((1, T, sim.R), dtype=torch.float64, device=sim.device)
+    wall, kern = time_simulation(torch, sim, rec, 1, 1)
+    sim.close()
+    return {"tuned_shape": shape, "tuned_node_steps_per_s": N * T / best_run_s,
+            "other_shape": other, "other_node_steps_per_s": N * T / wall,
+            "other_us_per_time_step": kern / T * 1e6,
+            "tuner_trials": [
+                {"shape": t["shape"], "us_per_step": t["s_per_step"] * 1e6, "factor_ms": t["factor_s"] * 1e3}
+                if "s_per_step" in t else {"shape": t["shape"], "rejected": t["rejected"]}
+                for t in tuned["trials"]]}
+
+
 def extras(torch, args):
     """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
     uneven batched gradients; each measured once after a warmup."""
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator, theta_matrix
     out = {}
-    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps.
+    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps;
+    # each side with its own tuned launch shape.
+    from paper_1903_01081_amd.tune import tune
     nets, cfg = netgen.config2()
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    shape_b = tune(nets, cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], **shape_b)
     rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     wall, kern = time_simulation(torch, sim, rec, 1, 1)
     N = nets[0].n_nodes
     batched = len(nets) * N * cfg["n_steps"] / wall
     # plain per-scenario loop: a sample of scenarios run one at a time
+    shape_1 = tune(nets[:1], cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
     n_plain = 8
     plain_t = []
     for s in range(n_plain):
-        one = Simulator([nets[s]], cfg["dt"], cfg["n_steps"])
+        one = Simulator([nets[s]], cfg["dt"], cfg["n_steps"], **shape_1)
         r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
         w1, _ = time_simulation(torch, one, r1, 1, 1 if s == 0 else 0)
         plain_t.append(w1)
         one.close()
     plain = N * cfg["n_steps"] / float(np.mean(plain_t))
     out["batched_n1"] = {"workload": "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us",
-                         "value": batched, "unit": "node-steps/s", "seconds": wall,
+                         "value": batched, "unit": "node-steps/s", "seconds": wall, "launch_shape": shape_b,
                          "plain_loop_value": plain, "plain_loop_sample": f"{n_plain} scenarios run one at a time",
-                         "speedup_vs_plain_loop": batched / plain}
+                         "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
     sim.close()
     del rec
     # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500.
@@ -252,19 +297,30 @@ def main():
         return
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
+    from paper_1903_01081_amd.tune import tune
 
     nets, cfg = netgen.config1()
     net = nets[0]
+    N, T = net.n_nodes, cfg["n_steps"]
+    # launch shape: the tuner times every feasible shape on a 400-step prefix
+    # (outside the timed region, like building the context)
     t0 = time.perf_counter()
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    tuned = tune(nets, cfg["dt"], T, probe_steps=400)
+    tune_s = time.perf_counter() - t0
+    shape = tuned["shape"]
+    log(f"tuned in {tune_s:.1f} s: {shape}; trials "
+        f"{[(t['shape'], t.get('s_per_step'), t.get('rejected')) for t in tuned['trials']]}")
+    t0 = time.perf_counter()
+    sim = Simulator(nets, cfg["dt"], T, **shape)
     build_s = time.perf_counter() - t0
     info = sim.info()
     rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     log(f"built grid1000 in {build_s:.2f} s: {info}")
     wall, kern = time_simulation(torch, sim, rec, args.steps, args.warmup)
-    N, T = net.n_nodes, cfg["n_steps"]
     value = N * T * args.steps / wall
-    per_step_bytes = algorithmic_bytes_per_step(info, net.n_rec)
+    kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
+    sizes = component_sizes(net) if kernel == "k_split" else None
+    per_step_bytes = algorithmic_bytes_per_step(info, net.n_rec, sizes)
     achieved = per_step_bytes * T / kern / 1e9
     line = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1,
@@ -274,19 +330,21 @@ def main():
         "config": {"workload": "grid1000: 1000-bus three-phase grid, 3000 nodes, 15903 branches, "
                                "50000 steps at 20 us, three-phase fault at step 25000, all nodes recorded",
                    "nodes": N, "branches": int(net.n_branches), "time_steps": T,
-                   "bench_step": "emt_factor + emt_step over the whole horizon"},
+                   "bench_step": "emt_factor + emt_step over the whole horizon",
+                   "launch_shape": shape, "split_tiles": info["split_tiles"],
+                   "split_cols": info["split_cols"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": "k_forward", "kernel_s": kern,
+                     "kernel": kernel, "kernel_s": kern,
                      "algorithmic_bytes_per_time_step": per_step_bytes},
-        "latency": {"us_per_time_step": kern / T * 1e6,
-                    "sweep_levels": info["max_levels"], "block_size": info["block_size"]},
-        "build_s": build_s,
+        "latency": {"us_per_time_step": kern / T * 1e6, "block_size": info["block_size"]},
+        "build_s": build_s, "tune_s": tune_s,
     }
     sim.close()
     del rec
     if not args.no_extras:
+        line["solver_comparison"] = solver_comparison(torch, nets, cfg, tuned, shape, wall / args.steps)
         line.update(extras(torch, args))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_config1(nets, cfg)

@@ -108,17 +108,31 @@ typedef struct {
  *     over the LDL^T factor. DENSE: v = G^{-1} rhs with the component's whole
  *     inverse, formed by emt_factor for every topology; a component of up to
  *     128 nodes keeps it in one workgroup, a larger one (up to 2048 nodes) is
- *     split by columns over ceil(n/16) workgroups that exchange partial
- *     voltages every step (all must be resident at once: EMT_EINVAL from
- *     emt_build otherwise; forward only: EMT_EINVAL with checkpoint_every
- *     > 0). AUTO: sweeps over the
- *     leading rows of the elimination order and the dense inverse of its
- *     trailing block, cut where a cost model finds fewest dependent phases. */
+ *     split by columns over ceil(n/split_cols) workgroups that exchange
+ *     partial voltages every step (all must be resident at once: EMT_EINVAL
+ *     from emt_build otherwise; forward only: EMT_EINVAL with
+ *     checkpoint_every > 0). AUTO: sweeps over the leading rows of the
+ *     elimination order and the dense inverse of its trailing block, cut
+ *     where a cost model finds fewest dependent phases.
+ * Launch shape (0 / -1 = chosen by the library; paper_1903_01081_amd.tune
+ * times the alternatives):
+ *   block_size: lanes of a one-workgroup component (64, 256 or 512);
+ *     EMT_EINVAL if a component's branches or dense tail do not fit.
+ *   split_cols: inverse columns per workgroup of a split component (16 or
+ *     32; 0 = 32 where the lane state fits, else 16).
+ *   dense_tail: AUTO solver only, the dense tail size in nodes (capped by
+ *     the block size's limit); -1 = the cost model.
+ *   sweep_from_global: 1 = the sweep data (factor values, row descriptors,
+ *     node CSR) stay in global memory even where LDS would hold them. */
 typedef struct {
   double dt;
   int64_t n_steps;
   int32_t checkpoint_every;
   int32_t solver;
+  int32_t block_size;
+  int32_t split_cols;
+  int32_t dense_tail;
+  int32_t sweep_from_global;
 } emt_sim;
 
 /* Sizes of a built context (emt_info) or of a host-only analysis. */

@@ -46,7 +46,9 @@ class EmtNet(C.Structure):
 
 class EmtSim(C.Structure):
     _fields_ = [("dt", C.c_double), ("n_steps", C.c_int64),
-                ("checkpoint_every", C.c_int32), ("solver", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("solver", C.c_int32),
+                ("block_size", C.c_int32), ("split_cols", C.c_int32),
+                ("dense_tail", C.c_int32), ("sweep_from_global", C.c_int32)]
 
 
 class EmtInfo(C.Structure):
@@ -153,8 +155,10 @@ class PackedNets:
         return C.addressof(self.array)
 
 
-def make_sim(dt, n_steps, checkpoint_every=0, solver=0) -> EmtSim:
-    return EmtSim(float(dt), int(n_steps), int(checkpoint_every), int(solver))
+def make_sim(dt, n_steps, checkpoint_every=0, solver=0, block_size=0, split_cols=0, dense_tail=-1,
+             sweep_from_global=0) -> EmtSim:
+    return EmtSim(float(dt), int(n_steps), int(checkpoint_every), int(solver), int(block_size),
+                  int(split_cols), int(dense_tail), int(sweep_from_global))
 
 
 def analyze(nets, dt, n_steps, checkpoint_every=0, solver=0) -> dict:

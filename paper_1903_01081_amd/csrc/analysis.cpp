@@ -349,6 +349,12 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
   if (sim.checkpoint_every < 0) fail(EMT_EINVAL, "checkpoint_every must be >= 0");
   if (sim.solver < EMT_SOLVER_AUTO || sim.solver > EMT_SOLVER_SPARSE)
     fail(EMT_EINVAL, "unknown solver");
+  if (sim.block_size != 0 && sim.block_size != 64 && sim.block_size != 256 && sim.block_size != 512)
+    fail(EMT_EINVAL, "block_size must be 0, 64, 256 or 512");
+  if (sim.split_cols != 0 && sim.split_cols != 16 && sim.split_cols != 32)
+    fail(EMT_EINVAL, "split_cols must be 0, 16 or 32");
+  if (sim.dense_tail < -1) fail(EMT_EINVAL, "dense_tail must be >= -1");
+  if (sim.sweep_from_global != 0 && sim.sweep_from_global != 1) fail(EMT_EINVAL, "sweep_from_global must be 0 or 1");
 
   Analysis A;
   std::map<std::vector<int64_t>, std::pair<int, std::vector<int>>> sym_cache;  // key -> (sym, perm)

@@ -107,11 +107,6 @@ struct emt_ctx {
 
 namespace {
 
-int env_int(const char *name, int dflt) {
-  const char *s = std::getenv(name);
-  return s ? std::atoi(s) : dflt;
-}
-
 // Largest dense tail whose inverse fits the lanes of one workgroup: 16
 // entries per lane up to 256 lanes (d <= 4 sqrt(lanes)), 32 with 512 lanes.
 int tail_max(int bs) { return bs >= 512 ? 128 : (bs >= 256 ? 64 : 32); }
@@ -214,8 +209,12 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
 static void build_split(emt_ctx &c, const std::vector<uint32_t> &bpack) {
   // columns per tile: 32 halves the tiles and the partials each node sums;
   // 16 where the lane state of 32 would not fit the VGPRs
-  const int want = env_int("EMT_SPLIT_COLS", 32) == 16 ? 16 : 32;
-  if (!build_split_with(c, bpack, want)) (void)build_split_with(c, bpack, 16);
+  const int want = c.sim.split_cols == 16 ? 16 : 32;
+  if (!build_split_with(c, bpack, want)) {
+    if (c.sim.split_cols == 32)
+      throw emt::Error{EMT_EINVAL, "split_cols = 32 does not fit these components' lane state; use 16 or 0"};
+    (void)build_split_with(c, bpack, 16);
+  }
 }
 
 static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int rt) {
@@ -464,8 +463,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // The smallest workgroup that holds the largest component's branches with
   // at most 8 per lane (12 with 512 lanes); 512 lanes run 2 waves per SIMD,
   // which leaves 256 VGPRs per lane for the branch state and tail inverse.
-  int bs = env_int("EMT_BLOCK", 0);
-  if (bs != 64 && bs != 256 && bs != 512) {
+  int bs = sim.block_size;
+  if (bs == 0) {
     bs = 512;
     for (int cand : {64, 256})
       if ((max_nbr + cand - 1) / cand <= 8 && (c.sim.solver != EMT_SOLVER_DENSE || tail_max(cand) >= max_n)) {
@@ -504,7 +503,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // component is the dense tail (it must fit one workgroup's tail); AUTO:
   // dense tail chosen by cost and grown where the LDS would overflow.
   std::vector<SweepPlan> plans(A.syms.size());
-  const int forced_tail = env_int("EMT_TAIL", -1);
+  const int forced_tail = sim.dense_tail;
   const int solver = c.sim.solver;
   std::vector<char> sym_split(A.syms.size(), 0);
   for (int q = 0; q < NI; ++q)
@@ -552,9 +551,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   }
   c.ks.wpt = wpt <= 4 ? 4 : (wpt <= 16 ? 16 : 32);
   if (wpt > 32 || (wpt > 16 && bs < 512)) throw Error{EMT_EINVAL, "internal: dense tail too large for the block size"};
-  const int force_sm = env_int("EMT_LDS_STAGE", -1);
-  c.sm_fwd = f_sm <= (size_t)max_lds && force_sm != 0;
-  c.sm_adj = a_sm <= (size_t)max_lds && force_sm != 0;
+  c.sm_fwd = f_sm <= (size_t)max_lds && !sim.sweep_from_global;
+  c.sm_adj = a_sm <= (size_t)max_lds && !sim.sweep_from_global;
   if (!c.sm_fwd || !c.sm_adj) {
     // the global-memory variants exist for 4, 8 and 16 branches per lane
     c.bpt_global = bpt <= 4 ? 4 : (bpt <= 8 ? 8 : 16);

@@ -41,7 +41,8 @@ class Simulator:
     """
 
     def __init__(self, nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0,
-                 solver: str = "auto", device: Optional[torch.device] = None):
+                 solver: str = "auto", device: Optional[torch.device] = None, block_size: int = 0,
+                 split_cols: int = 0, dense_tail: int = -1, sweep_from_global: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("the EMT library needs a HIP device")
         self.lib = _lib.load()
@@ -51,7 +52,10 @@ class Simulator:
         self.n_steps = int(n_steps)
         self.checkpoint_every = int(checkpoint_every)
         packed = _lib.PackedNets(self.nets)
-        sim = _lib.make_sim(dt, n_steps, checkpoint_every, SOLVERS[solver])
+        self.shape = dict(solver=solver, block_size=int(block_size), split_cols=int(split_cols),
+                          dense_tail=int(dense_tail), sweep_from_global=bool(sweep_from_global))
+        sim = _lib.make_sim(dt, n_steps, checkpoint_every, SOLVERS[solver], block_size, split_cols, dense_tail,
+                            int(bool(sweep_from_global)))
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             check(self.lib.emt_build(packed.ref, packed.n, C.addressof(sim), C.byref(self._ctx)))

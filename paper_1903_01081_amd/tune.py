@@ -1,0 +1,90 @@
+"""Launch-shape autotuner: times the feasible solver and shape choices of a
+batch on a short prefix of its own run and returns the fastest.
+
+The choices (all fields of emt_sim, see include/emt.h):
+  * solver "auto" (sparse sweeps + dense tail in one workgroup) at each
+    feasible block size, and with the sweep data read from global memory;
+  * solver "sparse" (sweeps only);
+  * solver "dense": components up to 128 nodes with their inverse in one
+    workgroup, larger ones split by columns over 16- or 32-column
+    workgroups (forward only, so skipped when checkpoints are asked for).
+Every candidate factorises and runs the same prefix of `probe_steps` steps
+(recorded like the real run) twice; the second run's factorisation time
+plus n_steps times its time per step ranks it, so a long horizon is not
+judged by the factorisation of a short prefix.
+Candidates the library rejects for this batch (EMT_EINVAL: shapes that do
+not fit) are skipped and listed with the reason.
+"""
+from __future__ import annotations
+
+import time
+from typing import List, Optional, Sequence
+
+import torch
+
+from ._lib import EMTError
+from .sim import Simulator
+
+
+def candidates(checkpoint_every: int = 0) -> List[dict]:
+    c = [dict(solver="auto", block_size=b) for b in (0, 64, 256, 512)]
+    c.append(dict(solver="auto", sweep_from_global=True))
+    c.append(dict(solver="sparse"))
+    if checkpoint_every == 0:
+        c += [dict(solver="dense", split_cols=k) for k in (16, 32)]
+    else:
+        c.append(dict(solver="dense"))
+    return c
+
+
+def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
+    sim = Simulator(nets, dt, n_steps, checkpoint_every=checkpoint_every, device=device, **shape)
+    try:
+        k = min(probe_steps, n_steps)
+        rec = torch.empty((sim.S, k, sim.R), dtype=torch.float64, device=sim.device)
+        t_fac = t_step = 0.0
+        for _ in range(2):
+            sim.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.factor()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sim.step(k, rec=rec)
+            torch.cuda.synchronize()
+            t_fac, t_step = t1 - t0, (time.perf_counter() - t1) / k
+        return t_fac, t_step, sim.info()
+    finally:
+        sim.close()
+
+
+def tune(nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0, probe_steps: int = 400,
+         shapes: Optional[List[dict]] = None, device=None) -> dict:
+    """Returns {"shape": best shape (Simulator keyword arguments),
+    "s_per_step": its time per step on the prefix, "run_s": its estimated
+    factorisation + n_steps time, "trials": [...]}."""
+    trials = []
+    for shape in (shapes if shapes is not None else candidates(checkpoint_every)):
+        try:
+            t_fac, t_step, info = _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device)
+            trials.append(dict(shape=shape, s_per_step=t_step, factor_s=t_fac,
+                               run_s=t_fac + n_steps * t_step, block_size=info["block_size"],
+                               split_tiles=info["split_tiles"], split_cols=info["split_cols"],
+                               max_tail=info["max_tail"]))
+        except EMTError as e:
+            trials.append(dict(shape=shape, rejected=str(e)))
+    ok = [t for t in trials if "s_per_step" in t]
+    if not ok:
+        raise RuntimeError("no launch shape fits this batch: " + "; ".join(t["rejected"] for t in trials))
+    best = min(ok, key=lambda t: t["run_s"])
+    return dict(shape=best["shape"], s_per_step=best["s_per_step"], run_s=best["run_s"], trials=trials)
+
+
+def tuned_simulator(nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0, probe_steps: int = 400,
+                    device=None) -> Simulator:
+    """A Simulator built with the fastest shape for this batch."""
+    r = tune(nets, dt, n_steps, checkpoint_every, probe_steps, device=device)
+    return Simulator(nets, dt, n_steps, checkpoint_every=checkpoint_every, device=device, **r["shape"])
+
+
+__all__ = ["candidates", "tune", "tuned_simulator"]

@@ -106,3 +106,23 @@ def test_autograd_function(torch_cuda, oracle_mod):
     ref = oracle_mod.adjoint(net, dt, T, 2.0 * v)
     err = grad_err(theta.grad.cpu().numpy()[0], ref, net.theta0())
     assert err < 1e-6
+
+
+def test_vjp_sweep_data_from_global_memory(torch_cuda, oracle_mod):
+    # the adjoint's global-memory variant (used when LDS cannot hold the
+    # sweep data) against the oracle's adjoint
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(61, 40, fault_step=60, n_mon=12)
+    T, K, dt = 150, 25, 20e-6
+    say("vjp with sweep data in global memory")
+    sim = Simulator([net], dt, T, checkpoint_every=K, sweep_from_global=True)
+    assert sim.info()["lds_staged"] == 0
+    sim.factor()
+    sim.step(T)
+    rng = np.random.default_rng(7)
+    cot = rng.standard_normal((1, T, net.n_rec))
+    g = sim.adjoint(torch_cuda.tensor(cot, dtype=torch_cuda.float64, device=sim.device)).cpu().numpy()
+    ref = oracle_mod.adjoint(net, dt, T, cot[0])
+    err = grad_err(g[0][:net.n_params], ref, net.theta0())
+    say("grad rel err", err)
+    assert err < 1e-6

@@ -210,3 +210,53 @@ def test_dense_solver_rejects_component_above_split_limit(torch_cuda):
     with pytest.raises(EMTError) as e:
         Simulator([net], 20e-6, 10, solver="dense")
     assert e.value.status == EMT_EINVAL and "2048 nodes" in str(e.value)
+
+
+@pytest.mark.parametrize("shape", [
+    dict(block_size=256), dict(block_size=512), dict(sweep_from_global=True),
+    dict(dense_tail=0), dict(dense_tail=12), dict(block_size=512, sweep_from_global=True),
+])
+def test_launch_shapes_vs_oracle(torch_cuda, oracle_mod, shape):
+    # every launch shape the tuner may pick computes the same trajectory
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(51, 60, fault_step=120, remove_series=3, remove_step=240, n_mon=30)
+    say(f"shape {shape}: grid60, 400 steps")
+    sim = Simulator([net], 20e-6, 400, **shape)
+    sim.factor()
+    rec = sim.step(400).cpu().numpy()
+    info = sim.info()
+    if "block_size" in shape:
+        assert info["block_size"] == shape["block_size"]
+    if shape.get("sweep_from_global"):
+        assert info["lds_staged"] == 0
+    if "dense_tail" in shape:
+        assert info["max_tail"] == shape["dense_tail"]
+    ref = oracle_mod.run(net, 20e-6, 400)
+    err = rel(rec[0], ref)
+    say("rel err", err)
+    assert err < TOL
+
+
+def test_bad_shapes_rejected(torch_cuda):
+    from paper_1903_01081_amd._lib import EMTError, EMT_EINVAL
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(52, 60, n_mon=10)
+    for shape in (dict(block_size=128), dict(split_cols=8), dict(dense_tail=-5)):
+        with pytest.raises(EMTError) as e:
+            Simulator([net], 20e-6, 10, **shape)
+        assert e.value.status == EMT_EINVAL
+
+
+def test_tuner_picks_a_shape_that_matches_the_oracle(torch_cuda, oracle_mod):
+    from paper_1903_01081_amd.tune import tune
+    from paper_1903_01081_amd.sim import Simulator
+    nets = [netgen.small_grid(53 + s, 150, fault_step=100, n_mon=20) for s in range(2)]
+    say("tuner: two 150-bus grids, 200-step probes")
+    r = tune(nets, 20e-6, 300, probe_steps=200)
+    say("tuner trials", [(t["shape"], t.get("s_per_step"), t.get("rejected")) for t in r["trials"]])
+    assert r["s_per_step"] > 0
+    sim = Simulator(nets, 20e-6, 300, **r["shape"])
+    sim.factor()
+    rec = sim.step(300).cpu().numpy()
+    for s, net in enumerate(nets):
+        assert rel(rec[s][:, :net.n_rec], oracle_mod.run(net, 20e-6, 300)) < TOL

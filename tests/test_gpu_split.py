@@ -33,9 +33,9 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / (s if s > 0 else 1.0))
 
 
-def dense_sim(nets, dt, T):
+def dense_sim(nets, dt, T, cols=0):
     from paper_1903_01081_amd.sim import Simulator
-    sim = Simulator(nets, dt, T, solver="dense")
+    sim = Simulator(nets, dt, T, solver="dense", split_cols=cols)
     sim.factor()
     return sim
 
@@ -45,11 +45,10 @@ def tiles(n_bus, cols):
 
 
 @pytest.mark.parametrize("cols", [16, 32])
-def test_split_grid200_events_vs_oracle(torch_cuda, oracle_mod, monkeypatch, cols):
-    monkeypatch.setenv("EMT_SPLIT_COLS", str(cols))
+def test_split_grid200_events_vs_oracle(torch_cuda, oracle_mod, cols):
     net = netgen.small_grid(41, 200, fault_step=150, remove_series=5, remove_step=300, n_mon=40)
     say(f"split: grid200 (3 x 200 nodes), {cols} columns per tile, fault at 150, branch out at 300, 500 steps")
-    sim = dense_sim([net], 20e-6, 500)
+    sim = dense_sim([net], 20e-6, 500, cols)
     info = sim.info()
     say("split tiles", info["split_tiles"])
     assert info["split_cols"] == cols and info["split_tiles"] == tiles(200, cols)
