@@ -62,7 +62,6 @@ struct ItemDesc {
 // nodes its branches touch.
 constexpr int kSplitColsMax = 32;
 constexpr int kSplitBS = 512;
-constexpr int kSplitLanesPerNode = 8;  // lanes that sum one node's partials
 
 struct SplitItem {
   int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile

@@ -37,8 +37,8 @@ using step::lds_barrier;
 using step::topo_of;
 
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
-// partials summed by one lane: P <= kSplitLanesPerNode * this (P <= 128
-// tiles, components of up to 2048 nodes)
+// partials summed by one lane: with 4 or 8 lanes per node, up to 64 or
+// 128 tiles (components of up to 2048 nodes at 16 columns per tile)
 constexpr int kMaxPartialsPerLane = 16;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
@@ -97,12 +97,16 @@ __global__ __launch_bounds__(256) void k_inverse(DevCtx c, SplitCtx s, const int
 template <int BPT, int RPL, int RT>
 __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_t n0, int64_t nsteps,
                                                    double *rec) {
-  constexpr int BS = kSplitBS, LQ = kSplitLanesPerNode;
+  constexpr int BS = kSplitBS;
   static_assert(RT * 16 <= BS, "16 lanes per owned node");
   const SplitTile tl = s.tiles[blockIdx.x];
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
   const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7;
+  // lanes that sum one node's partials: 4 up to 64 tiles, else 8
+  const int lq_lg = P <= 4 * kMaxPartialsPerLane ? 2 : 3;
+  const int slot0 = (int)threadIdx.x >> lq_lg;
+  const int64_t row0 = slot0 < nn ? (int64_t)s.i32[tl.need + slot0] * Pp : 0;
 
   // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
   // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag.
@@ -245,23 +249,26 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     __syncthreads();
     if (abort_flag[0]) break;
     // 4. voltages of the needed nodes: the P partials summed in tile order
+    // (the same lanes-per-node split in every tile of the component, so all
+    // tiles round alike); the first round's node offsets sit in a register
     {
       const double *xr = xb + (int64_t)(m & 1) * n * Pp;
-      const int sub = tid & (LQ - 1);
-      for (int slot = tid / LQ; slot < nn; slot += BS / LQ) {
-        const double *row = xr + (int64_t)need[slot] * Pp;
+      const int sub = tid & ((1 << lq_lg) - 1);
+      int round = 0;
+      for (int slot = tid >> lq_lg; slot < nn; slot += BS >> lq_lg, ++round) {
+        const double *row = xr + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
         // all loads in flight before the in-order sum
         double pv[kMaxPartialsPerLane];
 #pragma unroll
         for (int k = 0; k < kMaxPartialsPerLane; ++k) {
-          const int q = sub + k * LQ;
+          const int q = sub + (k << lq_lg);
           pv[k] = q < P ? row[q] : 0.0;
         }
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxPartialsPerLane; ++k) acc = acc + pv[k];
-        acc = group_sum(acc, 3, sub);
-        if (sub == LQ - 1) x[slot] = acc;
+        acc = group_sum(acc, lq_lg, sub);
+        if (sub == (1 << lq_lg) - 1) x[slot] = acc;
       }
     }
     lds_barrier();

@@ -402,12 +402,14 @@ __device__ __forceinline__ void solve_after_gather(const View<SM> &v, const doub
   }
 }
 
-// Lane state of the forward loop: coefficients of the current topology and
-// the history current of the next step for each slot (branches padded to
-// whole slots with inert ones, so every slot is valid).
+// Lane state of the forward loop: coefficients of the current topology for
+// each slot (branches padded to whole slots with inert ones, so every slot
+// is valid) and the history current of slot 0. The history of the other
+// slots lives in LDS as their injection: a slot j > 0 carries no source, so
+// J = -h there exactly and h = -J is read back where it is needed.
 template <int BPT>
 struct Lane {
-  double g[BPT], be[BPT], h[BPT];
+  double g[BPT], be[BPT], h0;
   uint32_t pk[BPT];
   // the source of slot 0 (sources are numbered first and fit in one slot):
   // EMF parameters and the EMF of the current step
@@ -438,12 +440,19 @@ __device__ __forceinline__ void load_coefs(const DevCtx &c, const ItemDesc &it, 
 }
 
 // History current h = beta*i + gamma*u from a stored state (i, u).
-template <int BS, int BPT>
-__device__ __forceinline__ void history_from_state(const double *si, const double *su, Lane<BPT> &L) {
+// History of the next step from a stored state (i, u): slot 0 into L.h0,
+// the other slots straight into their injections J = -h.
+template <int BS, int BPT, bool SM>
+__device__ __forceinline__ void history_from_state(const double *si, const double *su, Lane<BPT> &L,
+                                                   const View<SM> &v) {
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = threadIdx.x + j * BS;
-    L.h[j] = L.be[j] * si[b] + gamma_of(L.pk[j], L.g[j]) * su[b];
+    const double h = L.be[j] * si[b] + gamma_of(L.pk[j], L.g[j]) * su[b];
+    if (j == 0)
+      L.h0 = h;
+    else
+      v.J[b] = -h;
   }
 }
 
@@ -453,16 +462,13 @@ __device__ __forceinline__ double slot0_emf(const DevCtx &c, const Lane<BPT> &L,
   return tid < nsrc ? L.sE * emf_cos(L.sw * ((double)n * c.dt) + L.sph) : 0.0;
 }
 
-// Branch injections of step n: J = g e - h.
+// Slot 0's injection of step n: J = g e - h (the other slots' injections
+// were written with their history).
 template <int BS, int BPT, bool SM>
 __device__ __forceinline__ void inject(const DevCtx &c, const View<SM> &v, Lane<BPT> &L, int64_t n) {
   const int tid = lane_id();
   L.e0 = slot0_emf<BPT>(c, L, tid, v.nsrc, n);
-#pragma unroll
-  for (int j = 0; j < BPT; ++j) {
-    const double e = j == 0 ? L.e0 : 0.0;
-    v.J[tid + j * BS] = L.g[j] * e - L.h[j];
-  }
+  v.J[tid] = L.g[0] * L.e0 - L.h0;
 }
 
 // Branch phase after the solve of step n: u, i of step n with the current
@@ -481,8 +487,9 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
     const uint32_t pk = L.pk[j];
     const double vk = v.x[pk & kTermGround], vm = v.x[(pk >> 15) & kTermGround];
     const double e = j == 0 ? L.e0 : 0.0;
+    const double h = j == 0 ? L.h0 : -v.J[b];
     const double u = (L.g[j] != 0.0) ? (vk - vm) - e : 0.0;
-    const double i = L.g[j] * u + L.h[j];
+    const double i = L.g[j] * u + h;
     if (st_i) {
       st_i[b] = i;
       st_u[b] = u;
@@ -495,8 +502,13 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
       L.g[j] = c.cg[next_coef + b];
       L.be[j] = c.cb[next_coef + b];
     }
-    L.h[j] = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
-    if (inj) v.J[b] = L.g[j] * (j == 0 ? e_next : 0.0) - L.h[j];
+    const double hn = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
+    if (j == 0) {
+      L.h0 = hn;
+      if (inj) v.J[b] = L.g[j] * e_next - hn;
+    } else if (inj) {
+      v.J[b] = -hn;
+    }
   }
   L.e0 = e_next;
 }
@@ -516,7 +528,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-  history_from_state<BS, BPT>(c.si + it.br, c.su + it.br, L);
+  history_from_state<BS, BPT, SM>(c.si + it.br, c.su + it.br, L, v);
   select_factor<BS, WPT, SM>(c, it, v, t, w);
   inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
@@ -562,20 +574,34 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
 //   hbar_n = ibar - A^T w
 //   gbar += hbar_n u_n, betabar += hbar_n i_{n-1}, gammabar += hbar_n u_{n-1}
 // ---------------------------------------------------------------------------
+// Runs f(j, g_nx, be_nx) for every slot with the coefficients of step n+1:
+// those of step n (in L) unless a switching event lies between the two
+// steps (t_nx != t, uniform over the workgroup), then reloaded. Two fully
+// unrolled loops, so every slot index is a constant.
+template <int BS, int BPT, class F>
+__device__ __forceinline__ void with_next_coefs(const DevCtx &c, const ItemDesc &it, const Lane<BPT> &L, int t,
+                                                int t_nx, F &&f) {
+  if (t_nx == t) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) f(j, L.g[j], L.be[j]);
+  } else {
+    const int64_t o = it.coef + (int64_t)t_nx * it.n_br + lane_id();
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) f(j, c.cg[o + j * BS], c.cb[o + j * BS]);
+  }
+}
+
 template <int BS, int BPT, bool SM>
 __device__ __forceinline__ void adjoint_seed(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
-                                             const Lane<BPT> &L, const double (&g_nx)[BPT],
-                                             const double (&be_nx)[BPT], const double (&hb_nx)[BPT],
-                                             double (&ib)[BPT], const double *dJ, int64_t n) {
+                                             const Lane<BPT> &L, int t, int t_nx, const double (&hb_nx)[BPT],
+                                             const double *dJ, int64_t n) {
   const int tid = lane_id();
-#pragma unroll
-  for (int j = 0; j < BPT; ++j) {
+  with_next_coefs<BS, BPT>(c, it, L, t, t_nx, [&](int j, double g_nx, double be_nx) {
     const int b = tid + j * BS;
-    const double ibar = be_nx[j] * hb_nx[j];
-    ib[j] = ibar;
-    const double ga_nx = gamma_of(L.pk[j], g_nx[j]);
+    const double ibar = be_nx * hb_nx[j];
+    const double ga_nx = gamma_of(L.pk[j], g_nx);
     v.J[b] = (L.g[j] != 0.0) ? ga_nx * hb_nx[j] + L.g[j] * ibar : 0.0;
-  }
+  });
   const double *drow = dJ + ((int64_t)it.scen * c.T + (n - 1)) * c.rec_stride;
   for (int r = tid; r < v.n; r += BS) {
     double acc = 0.0;
@@ -599,10 +625,10 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
   Lane<BPT> L;
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
-  double g_nx[BPT], be_nx[BPT], hb_nx[BPT], ib[BPT];
-  double gb[BPT], bb[BPT], cb[BPT];
+  // per slot: hbar of step n+1 and the three gradient accumulators
+  double hb_nx[BPT], gb[BPT], bb[BPT], cb[BPT];
 #pragma unroll
-  for (int j = 0; j < BPT; ++j) g_nx[j] = be_nx[j] = hb_nx[j] = gb[j] = bb[j] = cb[j] = ib[j] = 0.0;
+  for (int j = 0; j < BPT; ++j) hb_nx[j] = gb[j] = bb[j] = cb[j] = 0.0;
 
   for (int64_t s = nseg - 1; s >= 0; --s) {
     const int64_t lo = s * K, hi = (lo + K < T) ? lo + K : T;
@@ -617,7 +643,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
     int t = topo_of(topo, it.n_topo, lo + 1);
     int64_t next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
     load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-    history_from_state<BS, BPT>(c.ck_i + cko, c.ck_u + cko, L);
+    history_from_state<BS, BPT, SM>(c.ck_i + cko, c.ck_u + cko, L, v);
     select_factor<BS, WPT, SM>(c, it, v, t, w);
     inject<BS, BPT, SM>(c, v, L, lo + 1);
     lds_barrier();
@@ -635,27 +661,30 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
       }
       lds_barrier();
     }
-    // L.g, L.be and the factors now belong to step hi.
-    adjoint_seed<BS, BPT, SM>(c, it, v, L, g_nx, be_nx, hb_nx, ib, dJ, hi);
+    // L.g, L.be and the factors now belong to step hi; the coefficients of
+    // step hi+1 are those of topology t_nx (unused at hi = T: hbar = 0).
+    int t_nx = hi < T ? topo_of(topo, it.n_topo, hi + 1) : t;
+    adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, hi);
     lds_barrier();
     for (int64_t n = hi; n >= lo + 1; --n) {
       gather_all<BS, true, SM>(v);
       solve_after_gather<BS, WPT, SM>(v, w);
       const int64_t on = (n - lo) * (int64_t)nbr, op = (n - 1 - lo) * (int64_t)nbr;
       const int tid = lane_id();
-#pragma unroll
-      for (int j = 0; j < BPT; ++j) {
+      with_next_coefs<BS, BPT>(c, it, L, t, t_nx, [&](int j, double g_nx, double be_nx) {
+        (void)g_nx;
         const int b = tid + j * BS;
         const uint32_t pk = L.pk[j];
         const double wk = v.x[pk & kTermGround], wm = v.x[(pk >> 15) & kTermGround];
-        const double hb = (L.g[j] != 0.0) ? ib[j] - (wk - wm) : 0.0;
+        const double ibar = be_nx * hb_nx[j];
+        const double hb = (L.g[j] != 0.0) ? ibar - (wk - wm) : 0.0;
         gb[j] = gb[j] + hb * seg_u[on + b];
         bb[j] = bb[j] + hb * seg_i[op + b];
         cb[j] = cb[j] + hb * seg_u[op + b];
         hb_nx[j] = hb;
-        g_nx[j] = L.g[j];
-        be_nx[j] = L.be[j];
-      }
+      });
+      // step n's coefficients become the next-step ones of step n-1
+      t_nx = t;
       if (n - 1 >= lo + 1) {
         const int tp = topo_of(topo, it.n_topo, n - 1);
         if (tp != t) {
@@ -663,7 +692,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
           load_coefs<BS, BPT>(c, it, t, L.g, L.be);
           select_factor<BS, WPT, SM>(c, it, v, t, w);
         }
-        adjoint_seed<BS, BPT, SM>(c, it, v, L, g_nx, be_nx, hb_nx, ib, dJ, n - 1);
+        adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, n - 1);
       }
       lds_barrier();
     }
