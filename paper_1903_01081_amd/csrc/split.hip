@@ -215,12 +215,13 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       // units read them, so the release below has no dirty lines to flush
       if (r < n) __hip_atomic_store(xw + (int64_t)r * Pp + tl.p, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // 3. publish, then wait for every tile of the component. The pattern is
-    // that of a grid barrier: the workgroup barrier orders every wave's
-    // partial stores before lane 0's device-scope release (the stores of
-    // one compute unit reach its L2 in issue order), lane 0 publishes, wave
-    // 0 polls and acquires, and a second workgroup barrier releases the
-    // other waves.
+    // 3. publish, then wait for every tile of the component. Every wave
+    // first waits until its own device-coherent partial stores are
+    // acknowledged (a workgroup barrier alone does not wait for them), then
+    // the pattern is that of a grid barrier: lane 0 releases at device scope
+    // and raises the flag, wave 0 polls and acquires, and a second
+    // workgroup barrier releases the other waves.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
