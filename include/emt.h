@@ -123,7 +123,11 @@ typedef struct {
  *   dense_tail: AUTO solver only, the dense tail size in nodes (capped by
  *     the block size's limit); -1 = the cost model.
  *   sweep_from_global: 1 = the sweep data (factor values, row descriptors,
- *     node CSR) stay in global memory even where LDS would hold them. */
+ *     node CSR) stay in global memory even where LDS would hold them.
+ *   serial_adjoint: 1 = emt_adjoint recomputes and reverses each checkpoint
+ *     segment in turn with one workgroup per item; 0 = where both fit on the
+ *     device at once, a second workgroup per item recomputes segment s-1
+ *     while the first reverses segment s (twice the segment buffer). */
 typedef struct {
   double dt;
   int64_t n_steps;
@@ -133,6 +137,7 @@ typedef struct {
   int32_t split_cols;
   int32_t dense_tail;
   int32_t sweep_from_global;
+  int32_t serial_adjoint;
 } emt_sim;
 
 /* Sizes of a built context (emt_info) or of a host-only analysis. */
@@ -159,6 +164,8 @@ typedef struct {
   int32_t lanes_per_block; /* branches per lane */
   int32_t split_tiles;   /* workgroups of the split dense components (0 if none) */
   int32_t split_cols;    /* inverse columns per split workgroup (16 or 32; 0 if none) */
+  int32_t adjoint_pipelined; /* 1 if emt_adjoint overlaps each segment's recompute with
+                                the previous segment's reversal (two workgroups per item) */
 } emt_info;
 
 /* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and

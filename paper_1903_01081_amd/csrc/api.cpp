@@ -69,6 +69,10 @@ struct emt_ctx {
   double *d_stage = nullptr;  // staging for set_state currents
   std::vector<emt::ItemDesc> items;
   bool sm_fwd = true, sm_adj = true, ks_adj_ok = true;
+  // pipelined adjoint: two workgroups per item resident together, two
+  // segment buffers per item, per-item progress counters
+  bool adj_pipe = false;
+  int32_t *d_pipe = nullptr;
   int bpt_global = 0;
   int max_tail = 0, dense_items = 0, sweep_levels = 0, lds_limit = 0;
   // items solved in one workgroup (k_forward launches the first n_fwd of
@@ -561,6 +565,21 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   c.ks.lds_adj = c.sm_adj ? a_sm : a_gl;
   if (f_gl > (size_t)max_lds) throw Error{EMT_EINVAL, "a connected component needs more LDS than a workgroup has"};
   c.ks_adj_ok = a_gl <= (size_t)max_lds;
+  // Pipelined adjoint where both workgroups of every item fit on the device
+  // at once (cooperative launch) and it was not turned off.
+  c.adj_pipe = false;
+  if (K > 0 && c.ks_adj_ok && !sim.serial_adjoint) {
+    KernelShape ks = c.ks;
+    ks.sm = c.sm_adj;
+    if (!ks.sm) ks.bpt = c.bpt_global;
+    int per_cu = 0, n_cu = 0, n_fwd = 0;
+    for (int q = 0; q < NI; ++q) n_fwd += c.is_split[q] ? 0 : 1;
+    hipError_t e = bs == 64 ? adjoint_pipe_blocks_per_cu_bs64(ks, &per_cu)
+                            : (bs == 256 ? adjoint_pipe_blocks_per_cu_bs256(ks, &per_cu)
+                                         : adjoint_pipe_blocks_per_cu_bs512(ks, &per_cu));
+    hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device), "CU count");
+    c.adj_pipe = e == hipSuccess && (int64_t)per_cu * n_cu >= 2 * (int64_t)n_fwd;
+  }
 
   // Symbolic arrays.
   std::vector<int32_t> symi;
@@ -677,7 +696,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     sv_off += (int64_t)sc.n_topo * P.nsv();
     w_off += (int64_t)sc.n_topo * P.d * P.d;
     ck_off += n_ck * it.n_br;
-    seg_off += seg_rows * it.n_br;
+    seg_off += (c.adj_pipe ? 2 : 1) * seg_rows * it.n_br;
     node_off += it.n;
     for (int t = 0; t < sc.n_topo; ++t) {
       pairs.push_back(q);
@@ -796,6 +815,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.ck_u = K > 0 ? c.alloc<double>(ck_off) : nullptr;
   dc.seg_i = K > 0 ? c.alloc<double>(seg_off) : nullptr;
   dc.seg_u = K > 0 ? c.alloc<double>(seg_off) : nullptr;
+  if (c.adj_pipe) c.d_pipe = c.alloc<int32_t>(2 * (size_t)NI);
   dc.flags = c.alloc<int32_t>(4);
   hip_check(launch_fill_i32(dc.flags, 4, 0, nullptr), "clear flags");
   dc.dt = sim.dt;
@@ -919,6 +939,7 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
     info->lds_staged = ctx->sm_fwd ? 1 : 0;
     info->lanes_per_block = ctx->ks.bpt;
     info->split_tiles = ctx->n_tiles;
+    info->adjoint_pipelined = ctx->adj_pipe ? 1 : 0;
     info->split_cols = ctx->n_tiles > 0 ? ctx->split_rt : 0;
     return EMT_OK;
   });
@@ -998,7 +1019,25 @@ emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (!ctx->ks_adj_ok) return set_error(EMT_EINVAL, "a connected component is too large for the adjoint kernel");
     if (ctx->n_tiles > 0) return set_error(EMT_EINVAL, "the split dense solver runs forward only");
-    hip_check(launch_adjoint(*ctx, dJ_drec_dev, st), "adjoint");
+    if (ctx->adj_pipe) {
+      emt::KernelShape ks = ctx->ks;
+      ks.sm = ctx->sm_adj;
+      if (!ks.sm) ks.bpt = ctx->bpt_global;
+      hip_check(emt::launch_fill_i32(ctx->d_pipe, 2 * (int64_t)ctx->A.items.size(), 0, st), "pipe counters");
+      hip_check(emt::launch_fill_i32(ctx->dc.flags + 2, 1, 0, st), "pipe error flag");
+      const int n = ctx->n_fwd;
+      hip_check(ks.bs == 64 ? emt::launch_adjoint_pipe_bs64(ctx->dc, ks, ctx->d_order, n, dJ_drec_dev, ctx->d_pipe, st)
+                : ks.bs == 256
+                    ? emt::launch_adjoint_pipe_bs256(ctx->dc, ks, ctx->d_order, n, dJ_drec_dev, ctx->d_pipe, st)
+                    : emt::launch_adjoint_pipe_bs512(ctx->dc, ks, ctx->d_order, n, dJ_drec_dev, ctx->d_pipe, st),
+                "adjoint");
+      int32_t err = 0;
+      hip_check(hipStreamSynchronize(st), "adjoint sync");
+      hip_check(hipMemcpy(&err, ctx->dc.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost), "pipe error flag");
+      if (err) return set_error(EMT_EDEVICE, "the pipelined adjoint gave up waiting for its recompute workgroups");
+    } else {
+      hip_check(launch_adjoint(*ctx, dJ_drec_dev, st), "adjoint");
+    }
     const int P = ctx->A.param_stride;
     hip_check(emt::launch_grad(ctx->dc, ctx->d_lptr, ctx->d_lent, ctx->d_line_scen, ctx->d_line_id,
                                ctx->n_lines_total, grad_dev, P, (int64_t)ctx->A.scens.size() * P, st),

@@ -297,7 +297,7 @@ __global__ void k_grad(DevCtx c, const int32_t *lptr, const int64_t *lent, const
 
 size_t lds_bytes(const LdsShape &s, bool sm, bool adjoint) {
   auto arr = [](size_t cnt, size_t size) { return (cnt * size + 15) & ~(size_t)15; };
-  size_t b = arr(s.d + 1, 8) + arr(s.n + 1, 8) + arr(s.nbr, 8) + arr(adjoint ? s.n : 0, 8);
+  size_t b = arr(s.d + 1, 8) + arr(s.n + 1, 8) + arr(s.nbr, 8) + arr(adjoint ? s.n : 0, 8) + arr(adjoint ? 1 : 0, 4);
   if (sm) {
     b += arr(s.nsv, 8) + arr(s.ns, 8) + arr(s.nfdesc, 8) + arr(s.nbdesc, 8) + arr(s.n + 1, 4) +
          arr(adjoint ? s.n + 1 : 0, 4) + 3 * arr(s.nsv, 2) + arr(s.nent, 2) + 2 * arr(s.nrec, 2);

@@ -46,6 +46,18 @@ hipError_t launch_adjoint_bs256(const DevCtx &, const KernelShape &, const int32
 hipError_t launch_adjoint_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                 hipStream_t);
 
+// Pipelined adjoint (two workgroups per item, cooperative launch) and its
+// resident workgroups per compute unit.
+hipError_t launch_adjoint_pipe_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                    int32_t *, hipStream_t);
+hipError_t launch_adjoint_pipe_bs256(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                     int32_t *, hipStream_t);
+hipError_t launch_adjoint_pipe_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
+                                     int32_t *, hipStream_t);
+hipError_t adjoint_pipe_blocks_per_cu_bs64(const KernelShape &, int *);
+hipError_t adjoint_pipe_blocks_per_cu_bs256(const KernelShape &, int *);
+hipError_t adjoint_pipe_blocks_per_cu_bs512(const KernelShape &, int *);
+
 hipError_t launch_factor(const DevCtx &c, const int32_t *pairs, int n_pairs, int max_tail, hipStream_t st);
 hipError_t launch_companions(const DevCtx &c, const CompanionArgs &a, hipStream_t st);
 hipError_t launch_set_params(const DevCtx &c, const double *theta, int P, const int32_t *bscen,

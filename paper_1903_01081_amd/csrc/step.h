@@ -113,6 +113,7 @@ struct View {
   Ref<uint16_t, SM> fcol, brow, bpos, nent, rnode, rcolumn;
   Ref<int32_t, SM> nptr, rptr;
   Lds<double> x, J, cD, dv, sv_s, dinv_s;  // x has n+1 entries, x[n] = 0
+  Lds<int32_t> flag;                       // adjoint: a word for broadcasts
   Ref<double, SM> sv, dinv;
 };
 
@@ -166,6 +167,7 @@ __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint)
   v.x.off = take(v.n + 1, 8);
   v.J.off = take(v.nbr, 8);
   v.dv.off = take(adjoint ? v.n : 0, 8);
+  v.flag.off = take(adjoint ? 1 : 0, 4);
   if (threadIdx.x == 0) {
     v.cD[v.d] = 0.0;  // spare slot read by the last pair of the tail product
     v.x[v.n] = 0.0;   // the ground: every grounded terminal points here
@@ -611,92 +613,100 @@ __device__ __forceinline__ void adjoint_seed(const DevCtx &c, const ItemDesc &it
   }
 }
 
+// Recomputes steps lo+1..hi of segment s from its checkpoint into a
+// segment buffer (row 0 = the checkpoint, row n-lo = step n). Afterwards L's
+// coefficients and the factors are those of step hi.
 template <int BS, int BPT, int WPT, bool SM>
-__global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, const double *dJ) {
-  const ItemDesc it = c.items[order[blockIdx.x]];
-  View<SM> v = make_view<BS, SM>(c, it, true);
+__device__ __forceinline__ void recompute_segment(const DevCtx &c, const ItemDesc &it, View<SM> &v,
+                                                  Lane<BPT> &L, double (&w)[WPT], int64_t s, double *seg_i,
+                                                  double *seg_u) {
   const int64_t *topo = c.topo + it.topo;
-  const int K = c.K;
-  const int64_t T = c.T;
-  const int64_t nseg = (T + K - 1) / K;
-  double *seg_i = c.seg_i + it.seg, *seg_u = c.seg_u + it.seg;
   const int nbr = v.nbr;
-
-  Lane<BPT> L;
-  double w[WPT];
-  load_lane<BS, BPT>(c, it, L);
-  // per slot: hbar of step n+1 and the three gradient accumulators
-  double hb_nx[BPT], gb[BPT], bb[BPT], cb[BPT];
+  const int64_t lo = s * c.K, hi = (lo + c.K < c.T) ? lo + c.K : c.T;
+  const int64_t cko = it.ck + s * (int64_t)nbr;
 #pragma unroll
-  for (int j = 0; j < BPT; ++j) hb_nx[j] = gb[j] = bb[j] = cb[j] = 0.0;
-
-  for (int64_t s = nseg - 1; s >= 0; --s) {
-    const int64_t lo = s * K, hi = (lo + K < T) ? lo + K : T;
-    // Recompute steps lo+1..hi from the checkpoint at lo.
-    const int64_t cko = it.ck + s * (int64_t)nbr;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      const int b = threadIdx.x + j * BS;
-      seg_i[b] = c.ck_i[cko + b];
-      seg_u[b] = c.ck_u[cko + b];
+  for (int j = 0; j < BPT; ++j) {
+    const int b = threadIdx.x + j * BS;
+    seg_i[b] = c.ck_i[cko + b];
+    seg_u[b] = c.ck_u[cko + b];
+  }
+  int t = topo_of(topo, it.n_topo, lo + 1);
+  int64_t next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
+  load_coefs<BS, BPT>(c, it, t, L.g, L.be);
+  history_from_state<BS, BPT, SM>(c.ck_i + cko, c.ck_u + cko, L, v);
+  select_factor<BS, WPT, SM>(c, it, v, t, w);
+  inject<BS, BPT, SM>(c, v, L, lo + 1);
+  lds_barrier();
+  for (int64_t n = lo + 1; n <= hi; ++n) {
+    gather_all<BS, false, SM>(v);
+    solve_after_gather<BS, WPT, SM>(v, w);
+    const int64_t o = (n - lo) * (int64_t)nbr;
+    const bool sw = (n + 1 == next) && n < hi;
+    update_inject<BS, BPT, SM>(c, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw,
+                               it.coef + (int64_t)(t + 1) * nbr, n < hi, n);
+    if (sw) {
+      ++t;
+      next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
+      select_factor<BS, WPT, SM>(c, it, v, t, w);
     }
-    int t = topo_of(topo, it.n_topo, lo + 1);
-    int64_t next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
-    load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-    history_from_state<BS, BPT, SM>(c.ck_i + cko, c.ck_u + cko, L, v);
-    select_factor<BS, WPT, SM>(c, it, v, t, w);
-    inject<BS, BPT, SM>(c, v, L, lo + 1);
     lds_barrier();
-    for (int64_t n = lo + 1; n <= hi; ++n) {
-      gather_all<BS, false, SM>(v);
-      solve_after_gather<BS, WPT, SM>(v, w);
-      const int64_t o = (n - lo) * (int64_t)nbr;
-      const bool sw = (n + 1 == next) && n < hi;
-      update_inject<BS, BPT, SM>(c, v, L, seg_i + o, seg_u + o, nullptr, nullptr, sw,
-                                 it.coef + (int64_t)(t + 1) * nbr, n < hi, n);
-      if (sw) {
-        ++t;
-        next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
+  }
+}
+
+// Reverses steps hi..lo+1 of segment s from its buffer. On entry L's
+// coefficients and the factors are those of step hi (topology t) and hb_nx
+// holds hbar of step hi+1 (0 past the horizon); on exit hb_nx holds hbar of
+// step lo+1, and the gradient accumulators have taken the segment's terms.
+template <int BS, int BPT, int WPT, bool SM>
+__device__ __forceinline__ void reverse_segment(const DevCtx &c, const ItemDesc &it, View<SM> &v,
+                                                Lane<BPT> &L, double (&w)[WPT], int64_t s, int t,
+                                                const double *seg_i, const double *seg_u, double (&hb_nx)[BPT],
+                                                double (&gb)[BPT], double (&bb)[BPT], double (&cb)[BPT],
+                                                const double *dJ) {
+  const int64_t *topo = c.topo + it.topo;
+  const int nbr = v.nbr;
+  const int64_t T = c.T;
+  const int64_t lo = s * c.K, hi = (lo + c.K < T) ? lo + c.K : T;
+  // the coefficients of step hi+1 are those of topology t_nx (unused at
+  // hi = T, where hbar = 0)
+  int t_nx = hi < T ? topo_of(topo, it.n_topo, hi + 1) : t;
+  adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, hi);
+  lds_barrier();
+  for (int64_t n = hi; n >= lo + 1; --n) {
+    gather_all<BS, true, SM>(v);
+    solve_after_gather<BS, WPT, SM>(v, w);
+    const int64_t on = (n - lo) * (int64_t)nbr, op = (n - 1 - lo) * (int64_t)nbr;
+    const int tid = lane_id();
+    with_next_coefs<BS, BPT>(c, it, L, t, t_nx, [&](int j, double g_nx, double be_nx) {
+      (void)g_nx;
+      const int b = tid + j * BS;
+      const uint32_t pk = L.pk[j];
+      const double wk = v.x[pk & kTermGround], wm = v.x[(pk >> 15) & kTermGround];
+      const double ibar = be_nx * hb_nx[j];
+      const double hb = (L.g[j] != 0.0) ? ibar - (wk - wm) : 0.0;
+      gb[j] = gb[j] + hb * seg_u[on + b];
+      bb[j] = bb[j] + hb * seg_i[op + b];
+      cb[j] = cb[j] + hb * seg_u[op + b];
+      hb_nx[j] = hb;
+    });
+    // step n's coefficients become the next-step ones of step n-1
+    t_nx = t;
+    if (n - 1 >= lo + 1) {
+      const int tp = topo_of(topo, it.n_topo, n - 1);
+      if (tp != t) {
+        t = tp;
+        load_coefs<BS, BPT>(c, it, t, L.g, L.be);
         select_factor<BS, WPT, SM>(c, it, v, t, w);
       }
-      lds_barrier();
+      adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, n - 1);
     }
-    // L.g, L.be and the factors now belong to step hi; the coefficients of
-    // step hi+1 are those of topology t_nx (unused at hi = T: hbar = 0).
-    int t_nx = hi < T ? topo_of(topo, it.n_topo, hi + 1) : t;
-    adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, hi);
     lds_barrier();
-    for (int64_t n = hi; n >= lo + 1; --n) {
-      gather_all<BS, true, SM>(v);
-      solve_after_gather<BS, WPT, SM>(v, w);
-      const int64_t on = (n - lo) * (int64_t)nbr, op = (n - 1 - lo) * (int64_t)nbr;
-      const int tid = lane_id();
-      with_next_coefs<BS, BPT>(c, it, L, t, t_nx, [&](int j, double g_nx, double be_nx) {
-        (void)g_nx;
-        const int b = tid + j * BS;
-        const uint32_t pk = L.pk[j];
-        const double wk = v.x[pk & kTermGround], wm = v.x[(pk >> 15) & kTermGround];
-        const double ibar = be_nx * hb_nx[j];
-        const double hb = (L.g[j] != 0.0) ? ibar - (wk - wm) : 0.0;
-        gb[j] = gb[j] + hb * seg_u[on + b];
-        bb[j] = bb[j] + hb * seg_i[op + b];
-        cb[j] = cb[j] + hb * seg_u[op + b];
-        hb_nx[j] = hb;
-      });
-      // step n's coefficients become the next-step ones of step n-1
-      t_nx = t;
-      if (n - 1 >= lo + 1) {
-        const int tp = topo_of(topo, it.n_topo, n - 1);
-        if (tp != t) {
-          t = tp;
-          load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-          select_factor<BS, WPT, SM>(c, it, v, t, w);
-        }
-        adjoint_seed<BS, BPT, SM>(c, it, v, L, t, t_nx, hb_nx, dJ, n - 1);
-      }
-      lds_barrier();
-    }
   }
+}
+
+template <int BS, int BPT>
+__device__ __forceinline__ void store_branch_adjoints(const DevCtx &c, const ItemDesc &it, const double (&gb)[BPT],
+                                                      const double (&bb)[BPT], const double (&cb)[BPT]) {
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     const int b = threadIdx.x + j * BS;
@@ -704,6 +714,114 @@ __global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, 
     c.bbar[it.br + b] = bb[j];
     c.cbar[it.br + b] = cb[j];
   }
+}
+
+// Serial adjoint: one workgroup per item recomputes and reverses each
+// segment in turn, last segment first.
+template <int BS, int BPT, int WPT, bool SM>
+__global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, const double *dJ) {
+  const ItemDesc it = c.items[order[blockIdx.x]];
+  View<SM> v = make_view<BS, SM>(c, it, true);
+  const int64_t nseg = (c.T + c.K - 1) / c.K;
+  double *seg_i = c.seg_i + it.seg, *seg_u = c.seg_u + it.seg;
+  Lane<BPT> L;
+  double w[WPT];
+  load_lane<BS, BPT>(c, it, L);
+  // per slot: hbar of step n+1 and the three gradient accumulators
+  double hb_nx[BPT], gb[BPT], bb[BPT], cb[BPT];
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) hb_nx[j] = gb[j] = bb[j] = cb[j] = 0.0;
+  for (int64_t s = nseg - 1; s >= 0; --s) {
+    recompute_segment<BS, BPT, WPT, SM>(c, it, v, L, w, s, seg_i, seg_u);
+    const int64_t hi = (s * c.K + c.K < c.T) ? s * c.K + c.K : c.T;
+    const int t = topo_of(c.topo + it.topo, it.n_topo, hi);
+    reverse_segment<BS, BPT, WPT, SM>(c, it, v, L, w, s, t, seg_i, seg_u, hb_nx, gb, bb, cb, dJ);
+  }
+  store_branch_adjoints<BS, BPT>(c, it, gb, bb, cb);
+}
+
+// Waits until *flag >= target: wave 0 polls (bounded), acquires at device
+// scope, and the workgroup barrier releases the other waves. Returns false
+// (and sets the error flag) if the wait gave up.
+__device__ __forceinline__ bool wait_flag(const int32_t *flag, int32_t target, int32_t *err,
+                                          Lds<int32_t> give_up) {
+  if (threadIdx.x < 64) {
+    int64_t spins = 0;
+    bool quit = false;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > (int64_t(1) << 24) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        quit = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (threadIdx.x == 0) {
+      give_up[0] = quit ? 1 : 0;
+      if (quit) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return give_up[0] == 0;
+}
+
+// Publishes *flag = value after every wave's global stores: each wave
+// waits for its own stores, the workgroup barrier joins them, lane 0
+// releases at device scope and stores the flag.
+__device__ __forceinline__ void publish_flag(int32_t *flag, int32_t value) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Pipelined adjoint: two workgroups per item, resident together
+// (cooperative launch). Workgroup n_items + i recomputes the segments of
+// item order[i], last first, into two alternating segment buffers;
+// workgroup i reverses each segment as soon as it is recomputed, so the
+// recompute of segment s-1 overlaps the reversal of segment s. Per item,
+// pipe[2q] counts recomputed segments and pipe[2q+1] reversed ones; the
+// recompute of the k-th segment waits until the (k-2)-th is reversed.
+template <int BS, int BPT, int WPT, bool SM>
+__global__ __launch_bounds__(BS) void k_adjoint_pipe(DevCtx c, const int32_t *order, int n_items,
+                                                     const double *dJ, int32_t *pipe) {
+  const bool recompute = (int)blockIdx.x >= n_items;
+  const int q = order[recompute ? blockIdx.x - n_items : blockIdx.x];
+  const ItemDesc it = c.items[q];
+  View<SM> v = make_view<BS, SM>(c, it, true);
+  const int64_t nseg = (c.T + c.K - 1) / c.K;
+  const int64_t seg_len = ((c.K < c.T ? c.K : c.T) + 1) * (int64_t)v.nbr;
+  int32_t *ready = pipe + 2 * q, *done = pipe + 2 * q + 1;
+  Lane<BPT> L;
+  double w[WPT];
+  load_lane<BS, BPT>(c, it, L);
+  if (recompute) {
+    for (int64_t k = 0; k < nseg; ++k) {
+      if (k >= 2 && !wait_flag(done, (int32_t)(k - 1), c.flags + 2, v.flag)) return;
+      const int64_t o = it.seg + (k & 1) * seg_len;
+      recompute_segment<BS, BPT, WPT, SM>(c, it, v, L, w, nseg - 1 - k, c.seg_i + o, c.seg_u + o);
+      publish_flag(ready, (int32_t)(k + 1));
+    }
+    return;
+  }
+  double hb_nx[BPT], gb[BPT], bb[BPT], cb[BPT];
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) hb_nx[j] = gb[j] = bb[j] = cb[j] = 0.0;
+  for (int64_t k = 0; k < nseg; ++k) {
+    const int64_t s = nseg - 1 - k;
+    if (!wait_flag(ready, (int32_t)(k + 1), c.flags + 2, v.flag)) return;
+    const int64_t hi = (s * c.K + c.K < c.T) ? s * c.K + c.K : c.T;
+    const int t = topo_of(c.topo + it.topo, it.n_topo, hi);
+    load_coefs<BS, BPT>(c, it, t, L.g, L.be);
+    select_factor<BS, WPT, SM>(c, it, v, t, w);
+    lds_barrier();
+    const int64_t o = it.seg + (k & 1) * seg_len;
+    reverse_segment<BS, BPT, WPT, SM>(c, it, v, L, w, s, t, c.seg_i + o, c.seg_u + o, hb_nx, gb, bb, cb, dJ);
+    publish_flag(done, (int32_t)(k + 1));
+  }
+  store_branch_adjoints<BS, BPT>(c, it, gb, bb, cb);
 }
 
 }  // namespace step

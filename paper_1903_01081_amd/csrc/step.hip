@@ -35,6 +35,32 @@ hipError_t adj(const DevCtx &c, const int32_t *order, int n_items, const double 
   return hipGetLastError();
 }
 
+template <int BPT, int WPT, bool SM>
+hipError_t adj_pipe(const DevCtx &c, const int32_t *order, int n_items, const double *dJ, int32_t *pipe,
+                    size_t lds, hipStream_t st) {
+  auto k = step::k_adjoint_pipe<EMT_BS, BPT, WPT, SM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  DevCtx ca = c;
+  const int32_t *oa = order;
+  int na = n_items;
+  const double *da = dJ;
+  int32_t *pa = pipe;
+  void *args[] = {&ca, &oa, &na, &da, &pa};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(2 * n_items), dim3(EMT_BS), args,
+                                    (unsigned)lds, st);
+}
+
+template <int BPT, int WPT, bool SM>
+hipError_t adj_pipe_occupancy(size_t lds, int *blocks) {
+  auto k = step::k_adjoint_pipe<EMT_BS, BPT, WPT, SM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(k), EMT_BS, lds);
+}
+
 }  // namespace
 
 #define EMT_CAT2(a, b) a##b
@@ -65,6 +91,23 @@ hipError_t EMT_CAT(launch_adjoint_bs, EMT_BS)(const DevCtx &c, const KernelShape
                                               int n_items, const double *dJ, hipStream_t st) {
 #define EMT_CASE(BPT, WPT, SM) \
   if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return adj<BPT, WPT, SM>(c, order, n_items, dJ, ks.lds_adj, st);
+  EMT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t EMT_CAT(launch_adjoint_pipe_bs, EMT_BS)(const DevCtx &c, const KernelShape &ks, const int32_t *order,
+                                                   int n_items, const double *dJ, int32_t *pipe, hipStream_t st) {
+#define EMT_CASE(BPT, WPT, SM) \
+  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return adj_pipe<BPT, WPT, SM>(c, order, n_items, dJ, pipe, ks.lds_adj, st);
+  EMT_SHAPES(EMT_CASE)
+#undef EMT_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t EMT_CAT(adjoint_pipe_blocks_per_cu_bs, EMT_BS)(const KernelShape &ks, int *blocks) {
+#define EMT_CASE(BPT, WPT, SM) \
+  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return adj_pipe_occupancy<BPT, WPT, SM>(ks.lds_adj, blocks);
   EMT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;

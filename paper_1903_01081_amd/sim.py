@@ -42,7 +42,8 @@ class Simulator:
 
     def __init__(self, nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0,
                  solver: str = "auto", device: Optional[torch.device] = None, block_size: int = 0,
-                 split_cols: int = 0, dense_tail: int = -1, sweep_from_global: bool = False):
+                 split_cols: int = 0, dense_tail: int = -1, sweep_from_global: bool = False,
+                 serial_adjoint: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("the EMT library needs a HIP device")
         self.lib = _lib.load()
@@ -53,9 +54,10 @@ class Simulator:
         self.checkpoint_every = int(checkpoint_every)
         packed = _lib.PackedNets(self.nets)
         self.shape = dict(solver=solver, block_size=int(block_size), split_cols=int(split_cols),
-                          dense_tail=int(dense_tail), sweep_from_global=bool(sweep_from_global))
+                          dense_tail=int(dense_tail), sweep_from_global=bool(sweep_from_global),
+                          serial_adjoint=bool(serial_adjoint))
         sim = _lib.make_sim(dt, n_steps, checkpoint_every, SOLVERS[solver], block_size, split_cols, dense_tail,
-                            int(bool(sweep_from_global)))
+                            int(bool(sweep_from_global)), int(bool(serial_adjoint)))
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             check(self.lib.emt_build(packed.ref, packed.n, C.addressof(sim), C.byref(self._ctx)))

@@ -126,3 +126,25 @@ def test_vjp_sweep_data_from_global_memory(torch_cuda, oracle_mod):
     err = grad_err(g[0][:net.n_params], ref, net.theta0())
     say("grad rel err", err)
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("K", [16, 45])
+def test_pipelined_adjoint_equals_serial_bitwise(torch_cuda, oracle_mod, K):
+    # the pipelined adjoint (segment s-1 recomputed by a second workgroup
+    # while segment s is reversed) against the serial one and the oracle
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(81, 30, fault_step=70, remove_series=4, remove_step=110, n_mon=15)
+    dt, T = 50e-6, 200
+    rng = np.random.default_rng(K + 1)
+    cot = rng.standard_normal((1, T, net.n_rec))
+    grads = {}
+    for serial in (False, True):
+        sim = Simulator([net], dt, T, checkpoint_every=K, serial_adjoint=serial)
+        assert sim.info()["adjoint_pipelined"] == (0 if serial else 1)
+        sim.factor()
+        sim.step(T)
+        say(f"K={K} serial={serial}")
+        grads[serial] = sim.adjoint(torch_cuda.tensor(cot, device=sim.device)).cpu().numpy()[0]
+    assert np.array_equal(grads[False], grads[True])
+    ref = oracle_mod.adjoint(net, dt, T, cot[0])
+    assert grad_err(grads[False][:net.n_params], ref, net.theta0()) < 1e-6
