@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
+    ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
+                    help="headline launch shape: tuned (default) or a fixed solver with library defaults")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the EMT time loop runs each scenario on one device "
@@ -305,11 +307,15 @@ def main():
     # launch shape: the tuner times every feasible shape on a 400-step prefix
     # (outside the timed region, like building the context)
     t0 = time.perf_counter()
-    tuned = tune(nets, cfg["dt"], T, probe_steps=400)
+    if args.solver == "tuned":
+        tuned = tune(nets, cfg["dt"], T, probe_steps=400)
+        shape = tuned["shape"]
+        log(f"tuned: {shape}; trials "
+            f"{[(t['shape'], t.get('s_per_step'), t.get('rejected')) for t in tuned['trials']]}")
+    else:
+        tuned = {"shape": dict(solver=args.solver), "trials": []}
+        shape = tuned["shape"]
     tune_s = time.perf_counter() - t0
-    shape = tuned["shape"]
-    log(f"tuned in {tune_s:.1f} s: {shape}; trials "
-        f"{[(t['shape'], t.get('s_per_step'), t.get('rejected')) for t in tuned['trials']]}")
     t0 = time.perf_counter()
     sim = Simulator(nets, cfg["dt"], T, **shape)
     build_s = time.perf_counter() - t0
