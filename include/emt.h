@@ -208,9 +208,14 @@ emt_status emt_reset(emt_ctx *ctx, void *stream);
  * waveform: given dJ_drec_dev [S][T][R] returns grad_dev [S][P] = dJ/dtheta
  * (entries past a scenario's n_params are set to 0). Recomputes each
  * checkpoint segment, then runs transposed solves through the same factors
- * backwards in time. Requires checkpoint_every > 0 and a forward run of all
- * n_steps since the last emt_set_params/emt_factor/emt_reset (else
- * EMT_ESTATE). Leaves the forward state at step n_steps. */
+ * backwards in time; where both fit on the device at once, a second
+ * workgroup per component recomputes segment s-1 while segment s is
+ * reversed (emt_info.adjoint_pipelined; the call then synchronises `stream`
+ * and returns EMT_EDEVICE if a workgroup gave up waiting). dJ_drec_dev may be
+ * NULL when no node is recorded (R = 0). Requires checkpoint_every > 0 and a
+ * forward run of all n_steps since the last emt_set_params/emt_factor/
+ * emt_reset (else EMT_ESTATE); EMT_EINVAL with split dense components.
+ * Leaves the forward state at step n_steps. */
 emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream);
 
 /* Per-branch adjoints of the companion coefficients from the last

@@ -1012,7 +1012,8 @@ emt_status emt_reset(emt_ctx *ctx, void *stream) {
 
 emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream) {
   return guarded([&]() -> emt_status {
-    if (!ctx || !dJ_drec_dev || !grad_dev) return set_error(EMT_EINVAL, "ctx, dJ_drec and grad are required");
+    if (!ctx || !grad_dev) return set_error(EMT_EINVAL, "ctx and grad are required");
+    if (!dJ_drec_dev && ctx->A.rec_stride > 0) return set_error(EMT_EINVAL, "dJ_drec is required");
     if (ctx->sim.checkpoint_every <= 0) return set_error(EMT_ESTATE, "built without checkpoints");
     if (!ctx->factored || !ctx->clean || ctx->step != ctx->sim.n_steps)
       return set_error(EMT_ESTATE, "needs a complete forward run from step 0 since the last change");

@@ -133,3 +133,44 @@ def test_levels_bound_and_fill(lib):
     info = lib.analyze([netgen.circuit(n, br)], 50e-6, 10)
     assert info["nnz_L"] == n - 1
     assert info["max_levels"] <= n
+
+
+def _analyze_sim(lib, nets, **fields):
+    so = lib.load()
+    P = lib.PackedNets(nets)
+    sim = lib.make_sim(50e-6, 10, **fields)
+    info = lib.EmtInfo()
+    return so.emt_analyze(P.ref, P.n, C.addressof(sim), C.addressof(info)), info
+
+
+def test_empty_batch_and_null_arguments(lib):
+    so = lib.load()
+    sim = lib.make_sim(50e-6, 10)
+    info = lib.EmtInfo()
+    assert so.emt_analyze(None, 0, C.addressof(sim), C.addressof(info)) == lib.EMT_EINVAL
+    good = lib.PackedNets([netgen.small_grid(2, 4)])
+    assert so.emt_analyze(good.ref, good.n, None, C.addressof(info)) == lib.EMT_EINVAL
+    assert so.emt_analyze(good.ref, good.n, C.addressof(sim), None) == lib.EMT_EINVAL
+    assert so.emt_last_error()  # a message for the last failure
+
+
+def test_launch_shape_fields_validated(lib):
+    net = netgen.small_grid(3, 5)
+    assert _analyze_sim(lib, [net])[0] == lib.EMT_OK
+    for bad in (dict(block_size=128), dict(block_size=-1), dict(split_cols=8), dict(dense_tail=-2),
+                dict(sweep_from_global=2), dict(serial_adjoint=-1), dict(solver=7)):
+        st, _ = _analyze_sim(lib, [net], **bad)
+        assert st == lib.EMT_EINVAL, bad
+
+
+def test_network_without_branches_is_singular(lib):
+    # nodes with no branch at all have no path to ground
+    net = netgen.circuit(2, [dict(k=0, m=-1, kind=CAP, C=1e-6)])
+    assert _status(lib, [net]) == lib.EMT_ESINGULAR
+
+
+def test_one_node_and_empty_recording_analyse(lib):
+    net = netgen.circuit(1, [dict(k=0, m=-1, kind=SRC, R=0.5, L=1e-2, E=1.0, omega=377.0),
+                             dict(k=0, m=-1, kind=CAP, C=1e-6)], rec_nodes=[])
+    info = lib.analyze([net], 50e-6, 10)
+    assert info["n_items"] == 1 and info["max_item_nodes"] == 1 and info["rec_stride"] == 0
