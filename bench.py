@@ -201,9 +201,11 @@ def extras(torch, args):
                          "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
     sim.close()
     del rec
-    # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500.
+    # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500 (tuned shape).
     nets, cfg = netgen.config3()
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+    shape_a = tune(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"],
+                   probe_steps=300)["shape"]
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"], **shape_a)
     rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     cot = torch.randn((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     for _ in range(2):
@@ -219,11 +221,15 @@ def extras(torch, args):
         torch.cuda.synchronize()
         t_adj = time.perf_counter() - t0
     out["adjoint"] = {"workload": "grid100: 300 nodes, 10,000 steps at 50 us, 450 parameters, checkpoint every 500",
+                      "launch_shape": shape_a, "pipelined": bool(sim.info()["adjoint_pipelined"]),
                       "forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_over_forward": t_adj / t_fwd}
     sim.close()
-    # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint.
+    # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint (tuned
+    # shape for the batch; the per-instance loop keeps the library default).
     nets, cfg = netgen.config4()
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+    shape_u = tune(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"],
+                   probe_steps=300)["shape"]
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"], **shape_u)
     theta = theta_matrix(nets, device=sim.device)
     rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     cot = torch.randn_like(rec)
@@ -255,6 +261,7 @@ def extras(torch, args):
         loop_t.append(tj)
         one.close()
     out["uneven_gradients"] = {"workload": "256 grids of 90-900 nodes, 5000 steps at 50 us, forward + adjoint",
+                               "launch_shape": shape_u, "pipelined": bool(sim.info()["adjoint_pipelined"]),
                                "gradients_per_s": len(nets) / t_b, "seconds": t_b,
                                "per_instance_loop_gradients_per_s": 1.0 / float(np.mean(loop_t)),
                                "loop_sample": f"{n_loop} instances run one at a time"}

@@ -3,7 +3,8 @@ batch on a short prefix of its own run and returns the fastest.
 
 The choices (all fields of emt_sim, see include/emt.h):
   * solver "auto" (sparse sweeps + dense tail in one workgroup) at each
-    feasible block size, and with the sweep data read from global memory;
+    feasible block size, with the largest dense tail of the 256- and
+    512-lane blocks, and with the sweep data read from global memory;
   * solver "sparse" (sweeps only);
   * solver "dense": components up to 128 nodes with their inverse in one
     workgroup, larger ones split by columns over 16- or 32-column
@@ -11,7 +12,10 @@ The choices (all fields of emt_sim, see include/emt.h):
 Every candidate factorises and runs the same prefix of `probe_steps` steps
 (recorded like the real run) twice; the second run's factorisation time
 plus n_steps times its time per step ranks it, so a long horizon is not
-judged by the factorisation of a short prefix.
+judged by the factorisation of a short prefix. With checkpoints (a
+gradient workload) each candidate instead runs forward and adjoint over a
+horizon of at least two checkpoint segments, and the per-step time counts
+both.
 Candidates the library rejects for this batch (EMT_EINVAL: shapes that do
 not fit) are skipped and listed with the reason.
 """
@@ -28,6 +32,9 @@ from .sim import Simulator
 
 def candidates(checkpoint_every: int = 0) -> List[dict]:
     c = [dict(solver="auto", block_size=b) for b in (0, 64, 256, 512)]
+    # the largest dense tail a block size holds (fewer sweep passes, more
+    # tail work per lane)
+    c += [dict(solver="auto", block_size=b, dense_tail=d) for b, d in ((256, 64), (512, 128))]
     c.append(dict(solver="auto", sweep_from_global=True))
     c.append(dict(solver="sparse"))
     if checkpoint_every == 0:
@@ -38,10 +45,16 @@ def candidates(checkpoint_every: int = 0) -> List[dict]:
 
 
 def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
-    sim = Simulator(nets, dt, n_steps, checkpoint_every=checkpoint_every, device=device, **shape)
-    try:
+    if checkpoint_every > 0:
+        # forward + adjoint over a short horizon of its own
+        k = min(n_steps, max(probe_steps, 2 * checkpoint_every))
+        sim = Simulator(nets, dt, k, checkpoint_every=checkpoint_every, device=device, **shape)
+    else:
         k = min(probe_steps, n_steps)
+        sim = Simulator(nets, dt, n_steps, device=device, **shape)
+    try:
         rec = torch.empty((sim.S, k, sim.R), dtype=torch.float64, device=sim.device)
+        cot = torch.ones_like(rec) if checkpoint_every > 0 else None
         t_fac = t_step = 0.0
         for _ in range(2):
             sim.reset()
@@ -51,6 +64,8 @@ def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             sim.step(k, rec=rec)
+            if cot is not None:
+                sim.adjoint(cot)
             torch.cuda.synchronize()
             t_fac, t_step = t1 - t0, (time.perf_counter() - t1) / k
         return t_fac, t_step, sim.info()
@@ -61,8 +76,9 @@ def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
 def tune(nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0, probe_steps: int = 400,
          shapes: Optional[List[dict]] = None, device=None) -> dict:
     """Returns {"shape": best shape (Simulator keyword arguments),
-    "s_per_step": its time per step on the prefix, "run_s": its estimated
-    factorisation + n_steps time, "trials": [...]}."""
+    "s_per_step": its time per step on the probe (forward, plus adjoint
+    with checkpoints), "run_s": its estimated factorisation + n_steps time,
+    "trials": [...]}."""
     trials = []
     for shape in (shapes if shapes is not None else candidates(checkpoint_every)):
         try:

@@ -7,6 +7,7 @@ def test_candidates_cover_every_solver_and_shape():
     solvers = {s["solver"] for s in c}
     assert solvers == {"auto", "sparse", "dense"}
     assert {s.get("block_size") for s in c if s["solver"] == "auto"} >= {0, 64, 256, 512}
+    assert {s.get("dense_tail") for s in c if s["solver"] == "auto"} >= {64, 128}
     assert {s.get("split_cols") for s in c if s["solver"] == "dense"} == {16, 32}
 
 
