@@ -65,6 +65,7 @@ constexpr int kSplitBS = 512;
 
 struct SplitItem {
   int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile
+  int32_t lq_lg, pad;        // log2 of the lanes that sum one node's partials (same in every tile)
   int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * rt + k)
   int64_t gt;                // SplitCtx::gt: [n_topo][P][rt][n] inverse columns
   int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] partial voltages (Pp = P rounded up to 8)

@@ -37,8 +37,7 @@ using step::lds_barrier;
 using step::topo_of;
 
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
-// partials summed by one lane: with 4 or 8 lanes per node, up to 64 or
-// 128 tiles (components of up to 2048 nodes at 16 columns per tile)
+// partials summed by one lane (the host keeps P / lanes-per-node within it)
 constexpr int kMaxPartialsPerLane = 16;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
@@ -103,8 +102,9 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
   const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7;
-  // lanes that sum one node's partials: 4 up to 64 tiles, else 8
-  const int lq_lg = P <= 4 * kMaxPartialsPerLane ? 2 : 3;
+  // lanes that sum one node's partials, chosen per component so that one
+  // round covers every tile's nodes
+  const int lq_lg = sp.lq_lg;
   const int slot0 = (int)threadIdx.x >> lq_lg;
   const int64_t row0 = slot0 < nn ? (int64_t)s.i32[tl.need + slot0] * Pp : 0;
 
@@ -208,13 +208,20 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 #pragma unroll
     for (int rr = 0; rr < RPL; ++rr) {
       const int r = tid + rr * BS;
-      double acc = 0.0;
+      // four independent chains (columns k mod 4), then a fixed pairing
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < RT; ++k) acc = acc + w[rr * RT + k] * rv[k];
+      for (int k = 0; k < RT; ++k) a[k & 3] = a[k & 3] + w[rr * RT + k] * rv[k];
+      const double acc = (a[0] + a[1]) + (a[2] + a[3]);
       // device-coherent stores: written through to where other compute
       // units read them, so the release below has no dirty lines to flush
       if (r < n) __hip_atomic_store(xw + (int64_t)r * Pp + tl.p, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // the next step's source EMF does not depend on this step's voltages:
+    // computed here, it overlaps the wait below
+    const bool last = (m == n_end);
+    double e_next = last ? 0.0 : emf(m + 1);
+    asm volatile("" : "+v"(e_next));  // keep it here, ahead of the wait
     // 3. publish, then wait for every tile of the component. Every wave
     // first waits until its own device-coherent partial stores are
     // acknowledged (a workgroup barrier alone does not wait for them), then
@@ -282,8 +289,6 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       }
     }
     const bool swn = (m + 1 == next);
-    const bool last = (m == n_end);
-    const double e_next = last ? 0.0 : emf(m + 1);
     const int64_t ncoef = it.coef + (int64_t)(t + 1) * it.n_br;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
