@@ -84,7 +84,7 @@ struct emt_ctx {
   size_t split_lds = 0, inverse_lds = 0;
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
-  std::vector<std::pair<int64_t, int32_t>> split_flags;  // (offset, count) per split item
+  std::vector<std::pair<int64_t, int64_t>> split_xbuf;  // (offset, doubles per step parity) per split item
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -235,7 +235,7 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   c.split_rpl = rpl <= 1 ? 1 : (rpl <= 2 ? 2 : 4);
   if (!split_shape_exists(1, c.split_rpl, rt)) return false;
   c.split_rt = rt;
-  c.split_flags.clear();
+  c.split_xbuf.clear();
   const int RT = rt;
   std::vector<SplitItem> sitems;
   std::vector<SplitTile> tiles;
@@ -243,7 +243,7 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   std::vector<uint32_t> u32;
   std::vector<uint16_t> u16;
   std::vector<int32_t> jobs;
-  int64_t gt_off = 0, xb_off = 0, fl_off = 0;
+  int64_t gt_off = 0, xb_off = 0;
   int max_slots = 0;
   size_t inv_lds = 0;
   struct TileLists {
@@ -289,11 +289,9 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
     i32.insert(i32.end(), pos.begin(), pos.end());
     si.gt = gt_off;
     si.xbuf = xb_off;
-    si.flag = fl_off;
     gt_off += (int64_t)sc.n_topo * P * RT * n;
+    c.split_xbuf.emplace_back(xb_off, (int64_t)n * ((P + 7) & ~7));
     xb_off += 2 * (int64_t)n * ((P + 7) & ~7);
-    fl_off += P;
-    c.split_flags.emplace_back(si.flag, P);
     inv_lds = std::max(inv_lds, (size_t)si.cb * n * sizeof(double));
     for (int t = 0; t < sc.n_topo; ++t)
       for (int j0 = 0; j0 < n; j0 += si.cb) {
@@ -432,7 +430,6 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   c.sc.gt = c.alloc<double>(gt_off);
   hip_check(hipMemset(c.sc.gt, 0, (size_t)gt_off * sizeof(double)), "clear inverse");
   c.sc.xbuf = c.alloc<double>(xb_off);
-  c.sc.flags = c.alloc<int64_t>(fl_off);
   c.sc.err = c.dc.flags + 1;
   c.d_inv_jobs = c.upload(jobs);
   c.n_inv_jobs = (int)jobs.size() / 3;
@@ -871,11 +868,16 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
   }
 }
 
-// The split components' launch: arrival flags start at the step before the
-// first, the give-up flag clear.
+// The split components' launch: both exchange buffers hold values whose
+// tag matches neither of the first two steps ((step / 2) mod 4 in the two
+// lowest bits, step parity choosing the buffer), the give-up flag clear.
 static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
-  for (const auto &f : c.split_flags)
-    hip_check(emt::launch_fill_i64(c.sc.flags + f.first, f.second, n0, st), "split flags");
+  for (const auto &f : c.split_xbuf)
+    for (int64_t m = n0 + 1; m <= n0 + 2; ++m) {
+      const int64_t stale = (((m >> 1) & 3) + 2) & 3;
+      int64_t *buf = reinterpret_cast<int64_t *>(c.sc.xbuf + f.first + (m & 1) * f.second);
+      hip_check(emt::launch_fill_i64(buf, f.second, stale, st), "split exchange buffer");
+    }
   hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
   hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.n_tiles, n0, ns, rec,
                               c.split_lds, st),

@@ -58,8 +58,8 @@ struct ItemDesc {
 // whole inverse G^{-1} split by columns over P workgroups ("tiles"), each
 // tile holding rt (16 or 32) columns in VGPRs. Per step a tile forms the
 // right-hand side of its own nodes, multiplies it into a partial voltage
-// vector for every node, publishes that, and sums the P partials of the
-// nodes its branches touch.
+// vector for every node, writes that with a step tag, and sums the P
+// partials of the nodes its branches touch once their tags are current.
 constexpr int kSplitColsMax = 32;
 constexpr int kSplitBS = 512;
 
@@ -68,8 +68,7 @@ struct SplitItem {
   int32_t lq_lg, pad;        // log2 of the lanes that sum one node's partials (same in every tile)
   int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * rt + k)
   int64_t gt;                // SplitCtx::gt: [n_topo][P][rt][n] inverse columns
-  int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] partial voltages (Pp = P rounded up to 8)
-  int64_t flag;              // SplitCtx::flags: [P] last step each tile has published
+  int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] tagged partial voltages (Pp = P rounded up to 8)
 };
 
 struct SplitTile {
@@ -90,7 +89,6 @@ struct SplitCtx {
   const uint32_t *u32;
   const uint16_t *u16;
   double *gt, *xbuf;
-  int64_t *flags;
   int32_t *err;  // set when a tile gives up waiting (the launch then ends early)
 };
 

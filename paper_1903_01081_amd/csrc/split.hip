@@ -8,18 +8,23 @@
 //   1. sums the injections of its own nodes (fixed CSR order, DPP scan);
 //   2. multiplies them into its columns of G^{-1}: a partial voltage for
 //      every node, written to the component's exchange buffer;
-//   3. publishes the step number in its arrival flag (release) and waits for
-//      the flags of all P tiles (acquire; bounded wait);
-//   4. sums the P partials of each node its branches touch, always in tile
-//      order, so every tile obtains bitwise the same voltages;
-//   5. updates its branches (u, i, history, next injection) as the one-
+//   3. reads the P partials of each node its branches touch, polling until
+//      each carries the step's tag, and sums them in tile order, so every
+//      tile obtains bitwise the same voltages;
+//   4. updates its branches (u, i, history, next injection) as the one-
 //      workgroup kernel does.
-// The exchange buffer is double-buffered by step parity: a tile writes the
-// buffer of step n+2 only after every tile has published step n+1, which
-// each does only after reading the partials of step n.
+// The exchange needs no flags or fences: every partial is one 8-byte
+// relaxed atomic store whose two lowest mantissa bits hold (step / 2) mod 4
+// (a change of at most 3 ulp, the same in every tile), and readers use
+// 8-byte relaxed atomic loads, so a value read is either the old one or the
+// new one and the tag tells which. The buffer is double-buffered by step
+// parity: a tile writes the buffer of step n+2 only after reading step
+// n+1's partials from every tile, each of which wrote them only after
+// reading step n's; steps n and n-2 share a buffer and differ in tag. The
+// host fills both buffers with non-matching tags before each launch.
 // All tiles of a launch must be resident together: the launch is
-// cooperative, and a wait that outlasts kSpinLimit polls sets an error flag
-// and ends every tile's loop instead of hanging.
+// cooperative, and a poll that outlasts kSpinLimit rounds sets an error
+// flag and ends every tile's loop instead of hanging.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -107,6 +112,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const int lq_lg = sp.lq_lg;
   const int slot0 = (int)threadIdx.x >> lq_lg;
   const int64_t row0 = slot0 < nn ? (int64_t)s.i32[tl.need + slot0] * Pp : 0;
+  const int64_t row0_hint = (int64_t)s.i32[tl.need] * Pp;
 
   // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
   // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag.
@@ -180,7 +186,6 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   __syncthreads();
 
   double *xb = s.xbuf + sp.xbuf;
-  int64_t *fl = s.flags + sp.flag;
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
   for (int64_t m = n0 + 1; m <= n_end; ++m) {
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 #pragma unroll
     for (int k = 0; k < RT; ++k) rv[k] = rhs[k];
     double *xw = xb + (int64_t)(m & 1) * n * Pp;
+    const uint64_t tag = (uint64_t)((m >> 1) & 3);
 #pragma unroll
     for (int rr = 0; rr < RPL; ++rr) {
       const int r = tid + rr * BS;
@@ -213,74 +219,92 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 #pragma unroll
       for (int k = 0; k < RT; ++k) a[k & 3] = a[k & 3] + w[rr * RT + k] * rv[k];
       const double acc = (a[0] + a[1]) + (a[2] + a[3]);
-      // device-coherent stores: written through to where other compute
-      // units read them, so the release below has no dirty lines to flush
-      if (r < n) __hip_atomic_store(xw + (int64_t)r * Pp + tl.p, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // tagged, device-coherent 8-byte store: the two lowest mantissa bits
+      // carry the step's tag, so readers recognise this step's value
+      if (r < n) {
+        const uint64_t bits = (__builtin_bit_cast(uint64_t, acc) & ~uint64_t(3)) | tag;
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(xw) + (int64_t)r * Pp + tl.p, bits, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     // the next step's source EMF does not depend on this step's voltages:
-    // computed here, it overlaps the wait below
+    // computed here, it overlaps the reads below
     const bool last = (m == n_end);
     double e_next = last ? 0.0 : emf(m + 1);
-    asm volatile("" : "+v"(e_next));  // keep it here, ahead of the wait
-    // 3. publish, then wait for every tile of the component. Every wave
-    // first waits until its own device-coherent partial stores are
-    // acknowledged (a workgroup barrier alone does not wait for them), then
-    // the pattern is that of a grid barrier: lane 0 releases at device scope
-    // and raises the flag, wave 0 polls and acquires, and a second
-    // workgroup barrier releases the other waves.
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(fl + tl.p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (tid < 64) {
-      int64_t spins = 0;
-      bool give_up = false;
-      for (;;) {
-        bool ready = true;
-        for (int q = tid; q < P; q += 64)
-          ready = ready && (__hip_atomic_load(fl + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= m);
-        if (__all(ready)) break;
-        if (++spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          give_up = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      if (give_up && tid == 0) {
-        __hip_atomic_store(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        abort_flag[0] = 1;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    if (abort_flag[0]) break;
-    // 4. voltages of the needed nodes: the P partials summed in tile order
-    // (the same lanes-per-node split in every tile of the component, so all
-    // tiles round alike); the first round's node offsets sit in a register
+    asm volatile("" : "+v"(e_next));  // keep it here, ahead of the reads
+    // 3. voltages of the needed nodes: each lane loads its share of a node's
+    // P partials and reloads any whose tag is not this step's until all are
+    // (8-byte atomic accesses: a value is either the old or the new one),
+    // then the partials are summed in tile order (the same lanes-per-node
+    // split in every tile of the component, so all tiles round alike). The
+    // first round's node offsets sit in a register.
     {
-      const double *xr = xb + (int64_t)(m & 1) * n * Pp;
+      const uint64_t *xr = reinterpret_cast<const uint64_t *>(xb) + (int64_t)(m & 1) * n * Pp;
+      bool quit = false;
+      // readiness hint: wave 0 polls the P partials of this tile's first
+      // node (P loads a round, as cheap as arrival flags) before everyone
+      // reads; the tags decide correctness, the hint only spares memory
+      // traffic
+      if (tid < 64) {
+        uint64_t *hint = const_cast<uint64_t *>(xr) + row0_hint;
+        for (int64_t spins = 0;;) {
+          bool ok = true;
+          for (int q = tid; q < P; q += 64)
+            ok = ok && (__hip_atomic_load(hint + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 3) == tag;
+          if (__all(ok)) break;
+          if ((++spins & 255) == 0 &&
+              (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            quit = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      lds_barrier();
       const int sub = tid & ((1 << lq_lg) - 1);
       int round = 0;
       for (int slot = tid >> lq_lg; slot < nn; slot += BS >> lq_lg, ++round) {
-        const double *row = xr + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
-        // all loads in flight before the in-order sum
-        double pv[kMaxPartialsPerLane];
+        uint64_t *row = const_cast<uint64_t *>(xr) + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
+        uint64_t pv[kMaxPartialsPerLane];
 #pragma unroll
         for (int k = 0; k < kMaxPartialsPerLane; ++k) {
           const int q = sub + (k << lq_lg);
-          pv[k] = q < P ? row[q] : 0.0;
+          pv[k] = q < P ? __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+        }
+        for (int64_t spins = 0;;) {
+          bool ok = true;
+#pragma unroll
+          for (int k = 0; k < kMaxPartialsPerLane; ++k) ok = ok && (pv[k] & 3) == tag;
+          if (ok) break;
+          if ((++spins & 255) == 0 &&
+              (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            quit = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+          for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+            const int q = sub + (k << lq_lg);
+            if ((pv[k] & 3) != tag) pv[k] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMaxPartialsPerLane; ++k) acc = acc + pv[k];
+        for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+          const int q = sub + (k << lq_lg);
+          acc = acc + (q < P ? __builtin_bit_cast(double, pv[k]) : 0.0);
+        }
         acc = group_sum(acc, lq_lg, sub);
         if (sub == (1 << lq_lg) - 1) x[slot] = acc;
       }
+      if (quit) {
+        __hip_atomic_store(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        abort_flag[0] = 1;
+      }
     }
     lds_barrier();
-    // 5. record, branch update, next injection
+    if (abort_flag[0]) break;
+    // 4. record, branch update, next injection
     if (rec) {
       double *row = rec + ((int64_t)it.scen * nsteps + (m - n0 - 1)) * R;
       for (int q = tid; q < tl.nrec; q += BS) {
