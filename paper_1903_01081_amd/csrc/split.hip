@@ -44,6 +44,8 @@ using step::topo_of;
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
 // partials summed by one lane (the host keeps P / lanes-per-node within it)
 constexpr int kMaxPartialsPerLane = 16;
+// rows whose partials each tile stores last (components here have more nodes)
+constexpr int kHintRows = 8;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
 
@@ -112,7 +114,10 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const int lq_lg = sp.lq_lg;
   const int slot0 = (int)threadIdx.x >> lq_lg;
   const int64_t row0 = slot0 < nn ? (int64_t)s.i32[tl.need + slot0] * Pp : 0;
-  const int64_t row0_hint = (int64_t)s.i32[tl.need] * Pp;
+  // readiness hint: the partials of one of the component's last kHintRows
+  // nodes (each tile stores those last), spread over the reading tiles so
+  // that no one row draws every tile's polls
+  const int64_t row0_hint = (int64_t)(n - 1 - tl.p % kHintRows) * Pp;
 
   // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
   // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag.
@@ -211,6 +216,8 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     for (int k = 0; k < RT; ++k) rv[k] = rhs[k];
     double *xw = xb + (int64_t)(m & 1) * n * Pp;
     const uint64_t tag = (uint64_t)((m >> 1) & 3);
+    uint64_t hint_bits = 0;
+    int hint_r = -1;
 #pragma unroll
     for (int rr = 0; rr < RPL; ++rr) {
       const int r = tid + rr * BS;
@@ -220,13 +227,23 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       for (int k = 0; k < RT; ++k) a[k & 3] = a[k & 3] + w[rr * RT + k] * rv[k];
       const double acc = (a[0] + a[1]) + (a[2] + a[3]);
       // tagged, device-coherent 8-byte store: the two lowest mantissa bits
-      // carry the step's tag, so readers recognise this step's value
-      if (r < n) {
-        const uint64_t bits = (__builtin_bit_cast(uint64_t, acc) & ~uint64_t(3)) | tag;
+      // carry the step's tag, so readers recognise this step's value. The
+      // last kHintRows nodes' partials are stored after the others (below,
+      // at most one per lane): readers poll them as the sign that the
+      // tile's partials have landed.
+      const uint64_t bits = (__builtin_bit_cast(uint64_t, acc) & ~uint64_t(3)) | tag;
+      if (r >= n - kHintRows && r < n) {
+        hint_bits = bits;
+        hint_r = r;
+      } else if (r < n) {
         __hip_atomic_store(reinterpret_cast<uint64_t *>(xw) + (int64_t)r * Pp + tl.p, bits, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
     }
+    lds_barrier();
+    if (hint_r >= 0)
+      __hip_atomic_store(reinterpret_cast<uint64_t *>(xw) + (int64_t)hint_r * Pp + tl.p, hint_bits,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the next step's source EMF does not depend on this step's voltages:
     // computed here, it overlaps the reads below
     const bool last = (m == n_end);
@@ -241,10 +258,10 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     {
       const uint64_t *xr = reinterpret_cast<const uint64_t *>(xb) + (int64_t)(m & 1) * n * Pp;
       bool quit = false;
-      // readiness hint: wave 0 polls the P partials of this tile's first
-      // node (P loads a round, as cheap as arrival flags) before everyone
-      // reads; the tags decide correctness, the hint only spares memory
-      // traffic
+      // readiness hint: wave 0 polls the P partials of its hint row, among
+      // each tile's final stores (P loads a round, as cheap as arrival
+      // flags), before everyone reads; the tags decide correctness, the
+      // hint only spares memory traffic
       if (tid < 64) {
         uint64_t *hint = const_cast<uint64_t *>(xr) + row0_hint;
         for (int64_t spins = 0;;) {
