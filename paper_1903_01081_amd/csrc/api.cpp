@@ -402,14 +402,14 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
     }
   }
   // Lanes per node for the partial sums, per component: the most lanes
-  // (fewest loads each, at most 16) with which one round of the 512 lanes
-  // covers the largest tile's nodes.
+  // (fewest loads each, at most split_max_partials) with which one round of
+  // the 512 lanes covers the largest tile's nodes.
   for (size_t k = 0; k < sitems.size(); ++k) {
     int max_nn = 0;
     for (int p = 0; p < sitems[k].P; ++p) max_nn = std::max(max_nn, (int)all[k][p].need.size());
     int lg = 3;
     while (lg > 0 && (kSplitBS >> lg) < max_nn) --lg;
-    while ((sitems[k].P + (1 << lg) - 1) >> lg > 16) ++lg;  // at most 16 partials per lane
+    while ((sitems[k].P + (1 << lg) - 1) >> lg > split_max_partials(RT)) ++lg;
     sitems[k].lq_lg = lg;
   }
   if (lds > (size_t)c.lds_limit) throw Error{EMT_EINVAL, "a split tile needs more LDS than a workgroup has"};

@@ -62,6 +62,10 @@ struct ItemDesc {
 // partials of the nodes its branches touch once their tags are current.
 constexpr int kSplitColsMax = 32;
 constexpr int kSplitBS = 512;
+// Most partials one lane sums for a node: a component has at most
+// 2048 / rt tiles, and the lanes per node are raised until each lane's share
+// fits (smaller for 32-column tiles, whose weight cache fills the registers).
+constexpr int split_max_partials(int rt) { return rt >= 32 ? 8 : 16; }
 
 struct SplitItem {
   int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile

@@ -42,8 +42,6 @@ using step::lds_barrier;
 using step::topo_of;
 
 constexpr int64_t kSpinLimit = int64_t(1) << 22;
-// partials summed by one lane (the host keeps P / lanes-per-node within it)
-constexpr int kMaxPartialsPerLane = 16;
 // rows whose partials each tile stores last (components here have more nodes)
 constexpr int kHintRows = 8;
 
@@ -105,6 +103,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
                                                    double *rec) {
   constexpr int BS = kSplitBS;
   static_assert(RT * 16 <= BS, "16 lanes per owned node");
+  constexpr int kPPL = split_max_partials(RT);  // partials summed per lane
   const SplitTile tl = s.tiles[blockIdx.x];
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
@@ -282,16 +281,16 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       int round = 0;
       for (int slot = tid >> lq_lg; slot < nn; slot += BS >> lq_lg, ++round) {
         uint64_t *row = const_cast<uint64_t *>(xr) + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
-        uint64_t pv[kMaxPartialsPerLane];
+        uint64_t pv[kPPL];
 #pragma unroll
-        for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+        for (int k = 0; k < kPPL; ++k) {
           const int q = sub + (k << lq_lg);
           pv[k] = q < P ? __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
         }
         for (int64_t spins = 0;;) {
           bool ok = true;
 #pragma unroll
-          for (int k = 0; k < kMaxPartialsPerLane; ++k) ok = ok && (pv[k] & 3) == tag;
+          for (int k = 0; k < kPPL; ++k) ok = ok && (pv[k] & 3) == tag;
           if (ok) break;
           if ((++spins & 255) == 0 &&
               (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
@@ -300,14 +299,14 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
           }
           __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-          for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+          for (int k = 0; k < kPPL; ++k) {
             const int q = sub + (k << lq_lg);
             if ((pv[k] & 3) != tag) pv[k] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMaxPartialsPerLane; ++k) {
+        for (int k = 0; k < kPPL; ++k) {
           const int q = sub + (k << lq_lg);
           acc = acc + (q < P ? __builtin_bit_cast(double, pv[k]) : 0.0);
         }
