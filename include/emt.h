@@ -127,7 +127,13 @@ typedef struct {
  *   serial_adjoint: 1 = emt_adjoint recomputes and reverses each checkpoint
  *     segment in turn with one workgroup per item; 0 = where both fit on the
  *     device at once, a second workgroup per item recomputes segment s-1
- *     while the first reverses segment s (twice the segment buffer). */
+ *     while the first reverses segment s (twice the segment buffer).
+ *   split_device_scope: 1 = the workgroups of a split component always
+ *     exchange their partial voltages through device-coherent memory; 0 =
+ *     through the L2 of their XCD when all of them run on one XCD (the
+ *     library places each component on one XCD where its workgroups fit;
+ *     they check where they run at the start of every launch). Results are
+ *     bitwise the same either way. */
 typedef struct {
   double dt;
   int64_t n_steps;
@@ -138,6 +144,7 @@ typedef struct {
   int32_t dense_tail;
   int32_t sweep_from_global;
   int32_t serial_adjoint;
+  int32_t split_device_scope;
 } emt_sim;
 
 /* Sizes of a built context (emt_info) or of a host-only analysis. */
@@ -166,6 +173,8 @@ typedef struct {
   int32_t split_cols;    /* inverse columns per split workgroup (16 or 32; 0 if none) */
   int32_t adjoint_pipelined; /* 1 if emt_adjoint overlaps each segment's recompute with
                                 the previous segment's reversal (two workgroups per item) */
+  int32_t split_local;   /* split components whose last launch exchanged through one XCD's L2
+                            (0 before the first step; synchronises the device) */
 } emt_info;
 
 /* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and

@@ -356,6 +356,8 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
   if (sim.dense_tail < -1) fail(EMT_EINVAL, "dense_tail must be >= -1");
   if (sim.sweep_from_global != 0 && sim.sweep_from_global != 1) fail(EMT_EINVAL, "sweep_from_global must be 0 or 1");
   if (sim.serial_adjoint != 0 && sim.serial_adjoint != 1) fail(EMT_EINVAL, "serial_adjoint must be 0 or 1");
+  if (sim.split_device_scope != 0 && sim.split_device_scope != 1)
+    fail(EMT_EINVAL, "split_device_scope must be 0 or 1");
 
   Analysis A;
   std::map<std::vector<int64_t>, std::pair<int, std::vector<int>>> sym_cache;  // key -> (sym, perm)

@@ -81,6 +81,8 @@ struct emt_ctx {
   std::vector<char> is_split;
   emt::SplitCtx sc{};
   int n_tiles = 0, split_bpt = 1, split_rpl = 1, split_rt = 16;
+  int split_grid = 0;                            // workgroups of a split launch (idle ones included)
+  std::vector<std::pair<int, int>> split_range;  // (first tile, tiles) per split item
   size_t split_lds = 0, inverse_lds = 0;
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
@@ -373,6 +375,7 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   const int slots = bpt * kSplitBS;
   size_t lds = 0;
   for (size_t k = 0; k < sitems.size(); ++k) {
+    sitems[k].t0 = (int32_t)tiles.size();
     for (int p = 0; p < sitems[k].P; ++p) {
       TileLists &T = all[k][p];
       SplitTile d{};
@@ -422,6 +425,50 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   if ((int64_t)per_cu * n_cu < c.n_tiles)
     throw Error{EMT_EINVAL, "the split components need " + std::to_string(c.n_tiles) +
                                 " workgroups resident at once; the device holds " + std::to_string(per_cu * n_cu)};
+  // Placement over the XCDs, each with its own L2. Workgroups are handed
+  // to the XCDs in turn (workgroup b on XCD b mod n_xcc), so the block
+  // order decides where a tile runs. Components are taken largest first; a
+  // component whose tiles fit the room left on one XCD goes to the XCD with
+  // the most room (its tiles can then exchange through that XCD's L2), the
+  // others are spread over what remains. Unused workgroup slots stay idle.
+  int n_xcc = 1;
+  if (hipDeviceGetAttribute(&n_xcc, hipDeviceAttributeNumberOfXccs, c.device) != hipSuccess || n_xcc < 1 ||
+      n_cu % n_xcc != 0)
+    n_xcc = 1;
+  const int room = per_cu * (n_cu / n_xcc);
+  std::vector<std::vector<int32_t>> on_xcd(n_xcc);
+  auto roomiest = [&]() {
+    int best = 0;
+    for (int x = 1; x < n_xcc; ++x)
+      if (on_xcd[x].size() < on_xcd[best].size()) best = x;
+    return best;
+  };
+  std::vector<int> by_size(sitems.size());
+  for (size_t k = 0; k < sitems.size(); ++k) by_size[k] = (int)k;
+  std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) { return sitems[a].P > sitems[b].P; });
+  std::vector<int> spread;
+  for (int k : by_size) {
+    const int x = roomiest();
+    if (room - (int)on_xcd[x].size() >= sitems[k].P) {
+      for (int p = 0; p < sitems[k].P; ++p) on_xcd[x].push_back(sitems[k].t0 + p);
+    } else {
+      spread.push_back(k);
+    }
+  }
+  for (int k : spread)
+    for (int p = 0; p < sitems[k].P; ++p) on_xcd[roomiest()].push_back(sitems[k].t0 + p);
+  size_t rows = 0;
+  for (const auto &v : on_xcd) rows = std::max(rows, v.size());
+  std::vector<int32_t> blk((size_t)n_xcc * rows, -1);
+  for (int x = 0; x < n_xcc; ++x)
+    for (size_t j = 0; j < on_xcd[x].size(); ++j) blk[x + (size_t)n_xcc * j] = on_xcd[x][j];
+  c.split_grid = (int)blk.size();
+  c.split_range.clear();
+  for (const SplitItem &si : sitems) c.split_range.emplace_back(si.t0, si.P);
+  c.sc.blk = c.upload(blk);
+  c.sc.xcc = c.alloc<int32_t>(tiles.size());
+  hip_check(hipMemset(c.sc.xcc, 0xFF, tiles.size() * sizeof(int32_t)), "split placement record");  // all -1
+  c.sc.allow_local = c.sim.split_device_scope ? 0 : 1;
   c.sc.items = c.upload(sitems);
   c.sc.tiles = c.upload(tiles);
   c.sc.i32 = c.upload(i32);
@@ -870,7 +917,8 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
 
 // The split components' launch: both exchange buffers hold values whose
 // tag matches neither of the first two steps ((step / 2) mod 4 in the two
-// lowest bits, step parity choosing the buffer), the give-up flag clear.
+// lowest bits, step parity choosing the buffer), the give-up flag clear and
+// the tiles' XCD record empty.
 static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
   for (const auto &f : c.split_xbuf)
     for (int64_t m = n0 + 1; m <= n0 + 2; ++m) {
@@ -879,7 +927,8 @@ static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, h
       hip_check(emt::launch_fill_i64(buf, f.second, stale, st), "split exchange buffer");
     }
   hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
-  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.n_tiles, n0, ns, rec,
+  hip_check(emt::launch_fill_i32(c.sc.xcc, c.n_tiles, -1, st), "split placement record");
+  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.split_grid, n0, ns, rec,
                               c.split_lds, st),
             "split forward");
 }
@@ -954,6 +1003,19 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
     info->split_tiles = ctx->n_tiles;
     info->adjoint_pipelined = ctx->adj_pipe ? 1 : 0;
     info->split_cols = ctx->n_tiles > 0 ? ctx->split_rt : 0;
+    info->split_local = 0;
+    if (ctx->n_tiles > 0 && ctx->sc.allow_local) {
+      // the XCD record of the last launch (all -1 before the first one)
+      std::vector<int32_t> xcc(ctx->n_tiles);
+      hip_check(hipDeviceSynchronize(), "sync");
+      hip_check(hipMemcpy(xcc.data(), ctx->sc.xcc, xcc.size() * sizeof(int32_t), hipMemcpyDeviceToHost),
+                "split placement record");
+      for (const auto &r : ctx->split_range) {
+        bool same = xcc[r.first] >= 0;
+        for (int p = 1; p < r.second; ++p) same = same && xcc[r.first + p] == xcc[r.first];
+        info->split_local += same ? 1 : 0;
+      }
+    }
     return EMT_OK;
   });
 }

@@ -69,7 +69,8 @@ constexpr int split_max_partials(int rt) { return rt >= 32 ? 8 : 16; }
 
 struct SplitItem {
   int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile
-  int32_t lq_lg, pad;        // log2 of the lanes that sum one node's partials (same in every tile)
+  int32_t lq_lg;             // log2 of the lanes that sum one node's partials (same in every tile)
+  int32_t t0;                // index of its first tile (its tiles are t0 .. t0 + P - 1)
   int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * rt + k)
   int64_t gt;                // SplitCtx::gt: [n_topo][P][rt][n] inverse columns
   int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] tagged partial voltages (Pp = P rounded up to 8)
@@ -89,11 +90,14 @@ struct SplitTile {
 struct SplitCtx {
   const SplitItem *items;
   const SplitTile *tiles;
+  const int32_t *blk;  // [grid] tile of each workgroup, -1 = none (workgroup b runs on XCD b mod n_xcc)
   const int32_t *i32;
   const uint32_t *u32;
   const uint16_t *u16;
   double *gt, *xbuf;
   int32_t *err;  // set when a tile gives up waiting (the launch then ends early)
+  int32_t *xcc;  // [n_tiles] XCD each tile ran on in the last launch (-1 before it starts)
+  int32_t allow_local;  // 0: always exchange through device-coherent memory
 };
 
 // Everything a kernel needs, passed by value.

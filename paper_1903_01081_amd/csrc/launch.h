@@ -77,7 +77,7 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
 size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt);
 hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *jobs, int n_jobs, size_t lds,
                           hipStream_t st);
-hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_tiles, int64_t n0,
+hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_blocks, int64_t n0,
                         int64_t ns, double *rec, size_t lds, hipStream_t st);
 hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks);
 

@@ -14,14 +14,17 @@
 //   4. updates its branches (u, i, history, next injection) as the one-
 //      workgroup kernel does.
 // The exchange needs no flags or fences: every partial is one 8-byte
-// relaxed atomic store whose two lowest mantissa bits hold (step / 2) mod 4
-// (a change of at most 3 ulp, the same in every tile), and readers use
-// 8-byte relaxed atomic loads, so a value read is either the old one or the
-// new one and the tag tells which. The buffer is double-buffered by step
-// parity: a tile writes the buffer of step n+2 only after reading step
-// n+1's partials from every tile, each of which wrote them only after
-// reading step n's; steps n and n-2 share a buffer and differ in tag. The
-// host fills both buffers with non-matching tags before each launch.
+// store whose two lowest mantissa bits hold (step / 2) mod 4 (a change of
+// at most 3 ulp, the same in every tile), and readers use 8-byte loads, so
+// a value read is either the old one or the new one and the tag tells
+// which. The buffer is double-buffered by step parity: a tile writes the
+// buffer of step n+2 only after reading step n+1's partials from every
+// tile, each of which wrote them only after reading step n's; steps n and
+// n-2 share a buffer and differ in tag. The host fills both buffers with
+// non-matching tags before each launch.
+// The host places each component's tiles on one XCD where they fit (one
+// L2 per XCD); the tiles confirm it at the start of the launch and then
+// exchange through that L2, else through device-coherent memory.
 // All tiles of a launch must be resident together: the launch is
 // cooperative, and a poll that outlasts kSpinLimit rounds sets an error
 // flag and ends every tile's loop instead of hanging.
@@ -46,6 +49,62 @@ constexpr int64_t kSpinLimit = int64_t(1) << 22;
 constexpr int kHintRows = 8;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
+
+// Accesses to an exchange buffer. Device-wide (the component's tiles span
+// XCDs): 8-byte relaxed atomics at agent scope, served by device-coherent
+// memory. XCD-local (all its tiles on one XCD): stores at workgroup scope,
+// which go through the CU's write-through L1 into the XCD's L2, and raw
+// buffer loads with the workgroup-scope and non-temporal bits (sc0 nt),
+// which are not served from the L1 (a line there could be stale: other CUs'
+// stores do not update it) but from that L2. A workgroup-scope load without
+// the non-temporal bit may hit such a stale L1 line and never see the new
+// value. Either way a value read is one aligned 8-byte access, old or new,
+// and the step tag tells which; poll loops hold a compiler barrier so every
+// round issues its loads again.
+__device__ __forceinline__ void xput(bool local, uint64_t *p, uint64_t v) {
+  if (local)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// raw buffer load, sc0 nt, at a byte offset (offsets past the resource's
+// size read 0)
+__device__ __forceinline__ uint64_t l2_load_off(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 3));
+}
+
+__device__ __forceinline__ uint64_t xget(bool local, __amdgpu_buffer_rsrc_t r, const uint64_t *base,
+                                         const uint64_t *p) {
+  return local ? l2_load_off(r, (int)((p - base) * 8))
+               : __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads a lane's share of one node's P partials (q = sub + k * 2^lg): all of
+// them, or (stale_only) those whose tag is not `tag`. Slots past P read as
+// current.
+template <int K>
+__device__ __forceinline__ void load_partials(bool local, __amdgpu_buffer_rsrc_t rs, const uint64_t *base,
+                                              uint64_t (&pv)[K], const uint64_t *row, int sub, int lg, int P,
+                                              uint64_t tag, bool stale_only) {
+  uint64_t *r = const_cast<uint64_t *>(row);
+  if (!local) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = sub + (k << lg);
+      if (stale_only && (pv[k] & 3) == tag) continue;
+      pv[k] = q < P ? __hip_atomic_load(r + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+    }
+    return;
+  }
+  const int off0 = (int)((row - base) * 8);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int q = sub + (k << lg);
+    if (stale_only && (pv[k] & 3) == tag) continue;
+    pv[k] = q < P ? l2_load_off(rs, off0 + q * 8) : tag;
+  }
+}
 
 }  // namespace
 
@@ -104,7 +163,9 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   constexpr int BS = kSplitBS;
   static_assert(RT * 16 <= BS, "16 lanes per owned node");
   constexpr int kPPL = split_max_partials(RT);  // partials summed per lane
-  const SplitTile tl = s.tiles[blockIdx.x];
+  const int tix = s.blk[blockIdx.x];
+  if (tix < 0) return;  // a block on an XCD left without tiles
+  const SplitTile tl = s.tiles[tix];
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
   const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7;
@@ -119,7 +180,8 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const int64_t row0_hint = (int64_t)(n - 1 - tl.p % kHintRows) * Pp;
 
   // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
-  // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag.
+  // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag and
+  // exchange scope.
   auto take = [](uint32_t &off, size_t bytes) {
     const uint32_t o = off;
     off += (uint32_t)((bytes + 15) & ~(size_t)15);
@@ -129,9 +191,9 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const uint32_t ox = take(off, (size_t)(nn + 1) * 8), oJ = take(off, (size_t)BS * BPT * 8),
                  orhs = take(off, RT * 8), oneed = take(off, (size_t)nn * 4), onp = take(off, (RT + 1) * 4),
                  one = take(off, (size_t)tl.ne * 2), orec = take(off, (size_t)tl.nrec * 4),
-                 oab = take(off, 4);
+                 oab = take(off, 8);
   step::Lds<double> x{ox}, J{oJ}, rhs{orhs};
-  step::Lds<int32_t> need{oneed}, nptr{onp}, abort_flag{oab};
+  step::Lds<int32_t> need{oneed}, nptr{onp}, abort_flag{oab};  // [0] abort, [1] XCD-local exchange
   step::Lds<uint16_t> nent{one};
   step::Lds<uint32_t> recl{orec};
   for (int q = threadIdx.x; q < nn; q += BS) need[q] = s.i32[tl.need + q];
@@ -187,9 +249,53 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   double e0 = emf(n0 + 1);
 #pragma unroll
   for (int j = 0; j < BPT; ++j) J[tid0 + j * BS] = g[j] * (j == 0 ? e0 : 0.0) - h[j];
+
+  // Exchange scope. Every tile publishes the XCD it runs on and reads its
+  // component's: when all tiles share one XCD, partials travel through that
+  // XCD's L2 (workgroup-scope atomics, which skip the per-CU L1 but stay in
+  // L2), else through device-coherent memory (agent scope). The tiles read
+  // the same P entries, so they all choose alike. Either way the step tags
+  // decide which values are current; the scope only sets the latency.
+  if (tid0 < 64) {
+    int xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    xcc &= 0xF;
+    if (tid0 == 0) __hip_atomic_store(s.xcc + tix, xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool same = true, quit = false;
+    for (int64_t spins = 0;;) {
+      bool ok = true;
+      same = true;
+      for (int q = tid0; q < P; q += 64) {
+        const int v = __hip_atomic_load(s.xcc + sp.t0 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = ok && v >= 0;
+        same = same && v == xcc;
+      }
+      if (__all(ok)) break;
+      if ((++spins & 255) == 0 &&
+          (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        quit = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    same = __all(same);
+    if (tid0 == 0) {
+      abort_flag[1] = (same && s.allow_local) ? 1 : 0;
+      if (quit) {
+        __hip_atomic_store(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        abort_flag[0] = 1;
+      }
+    }
+  }
   __syncthreads();
+  if (abort_flag[0]) return;
+  const bool xcd_local = abort_flag[1] != 0;
 
   double *xb = s.xbuf + sp.xbuf;
+  // the component's two exchange buffers as one raw buffer resource (no
+  // stride, size in bytes, 32-bit data format) for the XCD-local loads
+  const uint64_t *xbase = reinterpret_cast<const uint64_t *>(xb);
+  const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(xb, 0, 2 * n * Pp * 8, 0x00020000);
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
   for (int64_t m = n0 + 1; m <= n_end; ++m) {
@@ -235,14 +341,12 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
         hint_bits = bits;
         hint_r = r;
       } else if (r < n) {
-        __hip_atomic_store(reinterpret_cast<uint64_t *>(xw) + (int64_t)r * Pp + tl.p, bits, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + (int64_t)r * Pp + tl.p, bits);
       }
     }
     lds_barrier();
     if (hint_r >= 0)
-      __hip_atomic_store(reinterpret_cast<uint64_t *>(xw) + (int64_t)hint_r * Pp + tl.p, hint_bits,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + (int64_t)hint_r * Pp + tl.p, hint_bits);
     // the next step's source EMF does not depend on this step's voltages:
     // computed here, it overlaps the reads below
     const bool last = (m == n_end);
@@ -265,8 +369,9 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
         uint64_t *hint = const_cast<uint64_t *>(xr) + row0_hint;
         for (int64_t spins = 0;;) {
           bool ok = true;
+          asm volatile("" ::: "memory");  // reload every round
           for (int q = tid; q < P; q += 64)
-            ok = ok && (__hip_atomic_load(hint + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 3) == tag;
+            ok = ok && (xget(xcd_local, xrs, xbase, hint + q) & 3) == tag;
           if (__all(ok)) break;
           if ((++spins & 255) == 0 &&
               (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
@@ -282,11 +387,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       for (int slot = tid >> lq_lg; slot < nn; slot += BS >> lq_lg, ++round) {
         uint64_t *row = const_cast<uint64_t *>(xr) + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
         uint64_t pv[kPPL];
-#pragma unroll
-        for (int k = 0; k < kPPL; ++k) {
-          const int q = sub + (k << lq_lg);
-          pv[k] = q < P ? __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
-        }
+        load_partials(xcd_local, xrs, xbase, pv, row, sub, lq_lg, P, tag, false);
         for (int64_t spins = 0;;) {
           bool ok = true;
 #pragma unroll
@@ -298,11 +399,8 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-          for (int k = 0; k < kPPL; ++k) {
-            const int q = sub + (k << lq_lg);
-            if ((pv[k] & 3) != tag) pv[k] = __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          asm volatile("" ::: "memory");  // reload every round
+          load_partials(xcd_local, xrs, xbase, pv, row, sub, lq_lg, P, tag, true);
         }
         double acc = 0.0;
 #pragma unroll
@@ -362,7 +460,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt) {
   auto arr = [](size_t bytes) { return (bytes + 15) & ~(size_t)15; };
   return arr((size_t)(nn + 1) * 8) + arr((size_t)kSplitBS * bpt * 8) + arr((size_t)rt * 8) + arr((size_t)nn * 4) +
-         arr((size_t)(rt + 1) * 4) + arr((size_t)ne * 2) + arr((size_t)nrec * 4) + arr(4);
+         arr((size_t)(rt + 1) * 4) + arr((size_t)ne * 2) + arr((size_t)nrec * 4) + arr(8);
 }
 
 hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *jobs, int n_jobs, size_t lds,
@@ -378,7 +476,7 @@ hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *job
 namespace {
 
 template <int BPT, int RPL, int RT>
-hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_tiles, int64_t n0, int64_t ns, double *rec,
+hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_blocks, int64_t n0, int64_t ns, double *rec,
                         size_t lds, hipStream_t st) {
   auto k = k_split<BPT, RPL, RT>;
   hipError_t e =
@@ -387,7 +485,7 @@ hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_tiles, int64_t
   DevCtx ca = c;
   SplitCtx sa = s;
   void *args[] = {&ca, &sa, &n0, &ns, &rec};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(n_tiles), dim3(kSplitBS), args,
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(n_blocks), dim3(kSplitBS), args,
                                     (unsigned)lds, st);
 }
 
@@ -409,10 +507,10 @@ hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
   X(1, 1, 16) X(1, 2, 16) X(1, 4, 16) X(2, 1, 16) X(2, 2, 16) X(2, 4, 16) X(4, 1, 16) X(4, 2, 16) \
   X(4, 4, 16) X(1, 1, 32) X(1, 2, 32) X(2, 1, 32) X(2, 2, 32) X(4, 1, 32)
 
-hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_tiles, int64_t n0,
+hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_blocks, int64_t n0,
                         int64_t ns, double *rec, size_t lds, hipStream_t st) {
 #define EMT_CASE(B, R, W) \
-  if (bpt == B && rpl == R && rt == W) return split_launch<B, R, W>(c, s, n_tiles, n0, ns, rec, lds, st);
+  if (bpt == B && rpl == R && rt == W) return split_launch<B, R, W>(c, s, n_blocks, n0, ns, rec, lds, st);
   EMT_SPLIT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;

@@ -131,3 +131,45 @@ def test_split_error_paths(torch_cuda):
     with pytest.raises(EMTError) as e:
         Simulator([net], 20e-6, 100, checkpoint_every=10, solver="dense")
     assert e.value.status == EMT_EINVAL and "forward only" in str(e.value)
+
+
+@pytest.mark.parametrize("cols", [16, 32])
+def test_split_xcd_local_equals_device_scope(torch_cuda, oracle_mod, cols):
+    # The exchange through one XCD's L2 (where a component's tiles share an
+    # XCD) and through device-coherent memory move the same tagged values:
+    # the recordings must agree bitwise, and with the oracle.
+    from paper_1903_01081_amd.sim import Simulator
+    net = netgen.small_grid(43, 300, fault_step=120, remove_series=3, remove_step=260, n_mon=60)
+    dt, T = 20e-6, 400
+    recs, local = {}, {}
+    for dev in (False, True):
+        say(f"split {cols} columns, grid300, device scope only = {dev}")
+        sim = Simulator([net], dt, T, solver="dense", split_cols=cols, split_device_scope=dev)
+        sim.factor()
+        assert sim.info()["split_local"] == 0  # no launch yet
+        recs[dev] = sim.step(T).cpu().numpy()[0]
+        local[dev] = sim.info()["split_local"]
+        sim.close()
+    say("components exchanging within one XCD:", local)
+    assert local[True] == 0
+    assert 0 <= local[False] <= 3
+    assert np.array_equal(recs[False], recs[True])
+    assert rel(recs[False], oracle_mod.run(net, dt, T)) < TOL
+
+
+def test_split_grid1000_runs_xcd_local(torch_cuda):
+    # 3 x 1000 nodes in 32-column tiles: 32 workgroups per component, one
+    # XCD's worth of compute units on MI355X, so every component is placed
+    # on an XCD of its own and exchanges through its L2.
+    import torch
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config1(n_steps=50)
+    sim = Simulator(nets, cfg["dt"], 50, solver="dense", split_cols=32)
+    sim.factor()
+    sim.step(50)
+    info = sim.info()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    say("split_local", info["split_local"], "CUs", n_cu)
+    if n_cu < 256:
+        pytest.skip("fewer compute units than MI355X: placement differs")
+    assert info["split_local"] == 3
