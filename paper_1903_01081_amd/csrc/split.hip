@@ -326,10 +326,11 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 #pragma unroll
     for (int rr = 0; rr < RPL; ++rr) {
       const int r = tid + rr * BS;
-      // four independent chains (columns k mod 4), then a fixed pairing
+      // four independent fused multiply-add chains (columns k mod 4), then
+      // a fixed pairing: every tile rounds its partials the same way
       double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < RT; ++k) a[k & 3] = a[k & 3] + w[rr * RT + k] * rv[k];
+      for (int k = 0; k < RT; ++k) a[k & 3] = __builtin_fma(w[rr * RT + k], rv[k], a[k & 3]);
       const double acc = (a[0] + a[1]) + (a[2] + a[3]);
       // tagged, device-coherent 8-byte store: the two lowest mantissa bits
       // carry the step's tag, so readers recognise this step's value. The
@@ -361,11 +362,13 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     {
       const uint64_t *xr = reinterpret_cast<const uint64_t *>(xb) + (int64_t)(m & 1) * n * Pp;
       bool quit = false;
-      // readiness hint: wave 0 polls the P partials of its hint row, among
-      // each tile's final stores (P loads a round, as cheap as arrival
-      // flags), before everyone reads; the tags decide correctness, the
-      // hint only spares memory traffic
-      if (tid < 64) {
+      // readiness hint (device-wide exchange only): wave 0 polls the P
+      // partials of its hint row, among each tile's final stores (P loads a
+      // round, as cheap as arrival flags), before everyone reads, which
+      // spares device memory the polls of every lane; the tags decide
+      // correctness. Through one XCD's L2 polling is cheap and every lane
+      // polls its own partials at once.
+      if (tid < 64 && !xcd_local) {
         uint64_t *hint = const_cast<uint64_t *>(xr) + row0_hint;
         for (int64_t spins = 0;;) {
           bool ok = true;
