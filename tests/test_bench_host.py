@@ -27,3 +27,14 @@ def test_gpus_above_one_exit(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_algorithmic_figures_per_step():
+    # the per-step figures the roofline divides by: sparse sweeps vs the
+    # dense inverse of each component
+    import bench
+    info = {"total_branches": 100, "nnz_L": 40, "total_nodes": 30}
+    assert bench.algorithmic_flops_per_step(info) == 10 * 100 + 4 * 40 + 30
+    assert bench.algorithmic_flops_per_step(info, [10, 20]) == 10 * 100 + 2 * (100 + 400)
+    assert bench.algorithmic_bytes_per_step(info, 5) == 64 * 100 + 8 * 5 + 24 * 40 + 8 * 30
+    assert bench.algorithmic_bytes_per_step(info, 5, [10, 20]) == 64 * 100 + 8 * 5 + 8 * (100 + 400)
