@@ -173,3 +173,39 @@ def test_split_grid1000_runs_xcd_local(torch_cuda):
     if n_cu < 256:
         pytest.skip("fewer compute units than MI355X: placement differs")
     assert info["split_local"] == 3
+
+
+def test_split_components_sharing_xcds(torch_cuda, oracle_mod):
+    # 10 scenarios x 3 components of 200 nodes in 32-column tiles: 30
+    # components of 7 tiles, so each XCD holds several components. Every
+    # scenario against the oracle; XCD-local equal to device-wide bitwise.
+    from paper_1903_01081_amd.sim import Simulator
+    nets = [netgen.small_grid(60 + s, 200, fault_step=50 + 7 * s, n_mon=25) for s in range(10)]
+    dt, T = 20e-6, 160
+    recs, local = {}, {}
+    for dev in (False, True):
+        sim = Simulator(nets, dt, T, solver="dense", split_cols=32, split_device_scope=dev)
+        assert sim.info()["split_tiles"] == 30 * 7
+        sim.factor()
+        recs[dev] = sim.step(T).cpu().numpy()
+        local[dev] = sim.info()["split_local"]
+        sim.close()
+    say("components exchanging within one XCD:", local)
+    assert local[True] == 0
+    assert np.array_equal(recs[False], recs[True])
+    for s, net in enumerate(nets):
+        err = rel(recs[False][s, :, :net.n_rec], oracle_mod.run(net, dt, T))
+        assert err < TOL, (s, err)
+
+
+def test_split_component_too_large_for_one_xcd(torch_cuda, oracle_mod):
+    # 1000-node components in 16-column tiles need 63 workgroups, more than
+    # one XCD's compute units: spread over XCDs, exchanging device-wide.
+    import torch
+    nets, cfg = netgen.config1(n_steps=60, fault_step=30)
+    sim = dense_sim(nets, cfg["dt"], 60, cols=16)
+    rec = sim.step(60).cpu().numpy()[0]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    if n_cu >= 256:
+        assert sim.info()["split_local"] == 0
+    assert rel(rec, oracle_mod.run(nets[0], cfg["dt"], 60)) < TOL
