@@ -74,12 +74,6 @@ __device__ __forceinline__ uint64_t l2_load_off(__amdgpu_buffer_rsrc_t r, int of
   return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 3));
 }
 
-__device__ __forceinline__ uint64_t xget(bool local, __amdgpu_buffer_rsrc_t r, const uint64_t *base,
-                                         const uint64_t *p) {
-  return local ? l2_load_off(r, (int)((p - base) * 8))
-               : __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Loads a lane's share of one node's P partials (q = sub + k * 2^lg): all of
 // them, or (stale_only) those whose tag is not `tag`. Slots past P read as
 // current.
@@ -250,12 +244,12 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
 #pragma unroll
   for (int j = 0; j < BPT; ++j) J[tid0 + j * BS] = g[j] * (j == 0 ? e0 : 0.0) - h[j];
 
-  // Exchange scope. Every tile publishes the XCD it runs on and reads its
-  // component's: when all tiles share one XCD, partials travel through that
-  // XCD's L2 (workgroup-scope atomics, which skip the per-CU L1 but stay in
-  // L2), else through device-coherent memory (agent scope). The tiles read
-  // the same P entries, so they all choose alike. Either way the step tags
-  // decide which values are current; the scope only sets the latency.
+  // Exchange scope. Every tile publishes the XCD it runs on (the XCC_ID
+  // hardware register, id in bits 3:0) and reads its component's: when all
+  // tiles share one XCD, partials travel through that XCD's L2 (xput and
+  // load_partials above), else through device-coherent memory. The tiles
+  // read the same P entries, so they all choose alike. Either way the step
+  // tags decide which values are current; the scope only sets the latency.
   if (tid0 < 64) {
     int xcc;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
@@ -374,7 +368,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
           bool ok = true;
           asm volatile("" ::: "memory");  // reload every round
           for (int q = tid; q < P; q += 64)
-            ok = ok && (xget(xcd_local, xrs, xbase, hint + q) & 3) == tag;
+            ok = ok && (__hip_atomic_load(hint + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 3) == tag;
           if (__all(ok)) break;
           if ((++spins & 255) == 0 &&
               (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {

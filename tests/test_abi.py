@@ -158,7 +158,8 @@ def test_launch_shape_fields_validated(lib):
     net = netgen.small_grid(3, 5)
     assert _analyze_sim(lib, [net])[0] == lib.EMT_OK
     for bad in (dict(block_size=128), dict(block_size=-1), dict(split_cols=8), dict(dense_tail=-2),
-                dict(sweep_from_global=2), dict(serial_adjoint=-1), dict(solver=7)):
+                dict(sweep_from_global=2), dict(serial_adjoint=-1), dict(split_device_scope=2),
+                dict(solver=7)):
         st, _ = _analyze_sim(lib, [net], **bad)
         assert st == lib.EMT_EINVAL, bad
 
