@@ -35,20 +35,28 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / (s if s > 0 else 1.0))
 
 
-@pytest.fixture(scope="module")
-def grid1000_run(torch_cuda):
+# grid1000's two launch shapes: the one the tuner picks on MI355X (the split
+# dense inverse, 32 columns per workgroup) and the one-workgroup sweeps
+GRID1000_SHAPES = [dict(solver="dense", split_cols=32), dict(solver="auto")]
+
+
+@pytest.fixture(scope="module", params=GRID1000_SHAPES, ids=["split32", "auto"])
+def grid1000_run(request, torch_cuda):
     from paper_1903_01081_amd.sim import Simulator
     nets, cfg = netgen.config1()
-    say("grid1000 full horizon: 3000 nodes, 50000 steps")
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    shape = request.param
+    say(f"grid1000 full horizon: 3000 nodes, 50000 steps, {shape}")
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], **shape)
+    if shape["solver"] == "dense":
+        assert sim.info()["split_tiles"] == 96
     sim.factor()
     rec = sim.step(cfg["n_steps"])
     torch_cuda.cuda.synchronize()
-    return nets, cfg, sim, rec
+    return nets, cfg, sim, rec, shape
 
 
 def test_grid1000_prefix_vs_oracle(grid1000_run, oracle_mod):
-    nets, cfg, sim, rec = grid1000_run
+    nets, cfg, sim, rec, _ = grid1000_run
     T0 = 300
     ref = oracle_mod.run(nets[0], cfg["dt"], T0)
     got = rec[0, :T0].cpu().numpy()
@@ -60,7 +68,7 @@ def test_grid1000_prefix_vs_oracle(grid1000_run, oracle_mod):
 def test_grid1000_zero_sequence_whole_horizon(grid1000_run):
     # identical uncoupled phases, balanced sources, symmetric fault: the three
     # phase voltages of every bus sum to zero at every one of the 50,000 steps
-    nets, cfg, sim, rec = grid1000_run
+    nets, cfg, sim, rec, _ = grid1000_run
     r = rec[0]
     zs = r.view(r.shape[0], -1, 3).sum(dim=2).abs().max().item()
     assert zs / r.abs().max().item() < 1e-11
@@ -70,10 +78,10 @@ def test_grid1000_final_state_kcl_and_branch_relations(grid1000_run, torch_cuda)
     # the last step checked from the device state alone: KCL at every node and
     # the trapezoidal relation of every in-service branch between steps T-1, T
     from paper_1903_01081_amd.sim import Simulator
-    nets, cfg, _, _ = grid1000_run
+    nets, cfg, _, _, shape = grid1000_run
     net = nets[0]
     T, dt = cfg["n_steps"], cfg["dt"]
-    sim = Simulator(nets, dt, T)
+    sim = Simulator(nets, dt, T, **shape)
     sim.factor()
     sim.step(T - 1, record=False)
     v0, i0 = sim.get_state(0)
@@ -124,7 +132,8 @@ def test_n1_full_size_sampled_scenarios(torch_cuda, oracle_mod):
     from paper_1903_01081_amd.sim import Simulator
     nets, cfg = netgen.config2()
     say("grid200 N-1 full: 400 scenarios x 600 nodes, 15000 steps")
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    # the launch shape the tuner picks for this batch on MI355X
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], solver="auto", block_size=256)
     sim.factor()
     rec = sim.step(cfg["n_steps"])
     pick = [0, 137, 399]
@@ -140,7 +149,8 @@ def test_uneven_full_size_sampled_instances(torch_cuda, oracle_mod):
     from paper_1903_01081_amd.sim import Simulator
     nets, cfg = netgen.config4()
     say("uneven full: 256 grids of 90-900 nodes, 5000 steps")
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"])
+    # the launch shape the tuner picks for this batch on MI355X
+    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], solver="auto", block_size=512, dense_tail=128)
     sim.factor()
     rec = sim.step(cfg["n_steps"])
     sizes = np.array([n.n_nodes for n in nets])
