@@ -60,6 +60,18 @@ def algorithmic_flops_per_step(info, component_sizes=None):
     return f + 2 * sum(int(n) ** 2 for n in component_sizes)
 
 
+def latency_object(sim, kernel, us_per_step, info):
+    """The step kernel's time per step against its latency floor: the same
+    launch shape running only its barrier-separated phases (and, for the
+    split path, its exchange), measured by emt_latency_floor after the timed
+    region."""
+    kind = "split" if kernel == "k_split" else "one_workgroup"
+    floor = sim.latency_floor(kind, 20000)
+    return {"us_per_time_step": us_per_step, "block_size": info["block_size"],
+            "floor_us_per_time_step": floor, "floor_kind": kind,
+            "floor_over_step": floor / us_per_step}
+
+
 def component_sizes(net):
     """Node counts of the connected components of a network's branch graph."""
     import scipy.sparse as sp
@@ -370,7 +382,7 @@ def main():
                      # the per-step latency chain binds, not HBM or FP64
                      "fp64_flops_per_time_step": per_step_flops, "fp64_tflops": tflops,
                      "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": tflops / FP64_PEAK_TFLOPS},
-        "latency": {"us_per_time_step": kern / T * 1e6, "block_size": info["block_size"]},
+        "latency": latency_object(sim, kernel, kern / T * 1e6, info),
         "build_s": build_s, "tune_s": tune_s,
     }
     sim.close()

@@ -210,6 +210,28 @@ emt_status emt_factor(emt_ctx *ctx, void *stream);
  * Errors: EMT_ESTATE before emt_factor or past n_steps; EMT_EINVAL n < 0. */
 emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
 
+/* Latency floor of a step kernel (a measurement: Sec. IV-B and IV-C judge
+ * a simulator by its average time per integration step, and the time loop
+ * here is bound by its chain of dependent phases, not by bandwidth or
+ * arithmetic). Runs n_steps steps of
+ * a kernel with the step kernel's launch shape but no arithmetic and
+ * returns its time per step in microseconds (HIP events on `stream`, which
+ * the call synchronises):
+ *   EMT_FLOOR_ONE_WORKGROUP: the one-workgroup kernel's grid, workgroup
+ *     size and LDS size, each step emt_info.sweep_levels + 2 phases in which
+ *     every lane reads a value another lane wrote in the previous phase,
+ *     separated by LDS barriers (the gather, the solve passes and the branch
+ *     update of a step).
+ *   EMT_FLOOR_SPLIT: the split components' kernel with the same tiles and
+ *     placement, each step storing its step-tagged partials and reading the
+ *     needed nodes' partials until their tags are current, with the same
+ *     barriers, but no right-hand side, partial products or branch update.
+ * The simulation state and step counter are untouched; a temporary buffer is
+ * allocated for the one-workgroup floor. Errors: EMT_EINVAL (no component
+ * of that kind, n_steps outside 1 .. 2^30, unknown kernel), EMT_EDEVICE. */
+typedef enum { EMT_FLOOR_ONE_WORKGROUP = 0, EMT_FLOOR_SPLIT = 1 } emt_floor_kernel;
+emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, double *us_per_step, void *stream);
+
 /* Return every scenario to step 0 with the zero initial state. */
 emt_status emt_reset(emt_ctx *ctx, void *stream);
 

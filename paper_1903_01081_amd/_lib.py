@@ -21,7 +21,10 @@ STATUS_NAMES = {0: "EMT_OK", 1: "EMT_EINVAL", 2: "EMT_ESINGULAR", 3: "EMT_ENOMEM
 # Exported functions of include/emt.h.
 EXPORTS = ("emt_build", "emt_analyze", "emt_info_get", "emt_set_params", "emt_factor",
            "emt_step", "emt_reset", "emt_adjoint", "emt_branch_adjoints", "emt_get_state",
-           "emt_set_state", "emt_destroy", "emt_last_error")
+           "emt_set_state", "emt_latency_floor", "emt_destroy", "emt_last_error")
+
+# emt_floor_kernel
+FLOOR_KERNELS = {"one_workgroup": 0, "split": 1}
 
 
 class EMTError(RuntimeError):
@@ -96,6 +99,7 @@ def load():
         "emt_branch_adjoints": [vp, i32, vp, vp, vp],
         "emt_get_state": [vp, i32, vp, vp],
         "emt_set_state": [vp, i32, vp, vp],
+        "emt_latency_floor": [vp, i32, i64, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)

@@ -919,7 +919,8 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
 // tag matches neither of the first two steps ((step / 2) mod 4 in the two
 // lowest bits, step parity choosing the buffer), the give-up flag clear and
 // the tiles' XCD record empty.
-static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
+static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st,
+                              bool floor = false) {
   for (const auto &f : c.split_xbuf)
     for (int64_t m = n0 + 1; m <= n0 + 2; ++m) {
       const int64_t stale = (((m >> 1) & 3) + 2) & 3;
@@ -929,8 +930,8 @@ static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, h
   hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
   hip_check(emt::launch_fill_i32(c.sc.xcc, c.n_tiles, -1, st), "split placement record");
   hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.split_grid, n0, ns, rec,
-                              c.split_lds, st),
-            "split forward");
+                              c.split_lds, floor, st),
+            floor ? "split latency floor" : "split forward");
 }
 
 // A split launch whose tiles gave up waiting leaves the error flag set.
@@ -1069,6 +1070,51 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
     if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
     if (ctx->n_tiles > 0) launch_split_step(*ctx, ctx->step, n, rec_dev, st);
     ctx->step += n;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, double *us_per_step, void *stream) {
+  // events and the scratch output are released on every path
+  struct Scratch {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double *out = nullptr;
+    ~Scratch() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (out) (void)hipFree(out);
+    }
+  };
+  return guarded([&]() -> emt_status {
+    if (!ctx || !us_per_step) return set_error(EMT_EINVAL, "ctx and us_per_step are required");
+    if (n_steps <= 0 || n_steps > (int64_t(1) << 30)) return set_error(EMT_EINVAL, "n_steps must be in 1 .. 2^30");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    hip_check(hipEventCreate(&sc.e0), "event");
+    hip_check(hipEventCreate(&sc.e1), "event");
+    if (kernel == EMT_FLOOR_ONE_WORKGROUP) {
+      if (ctx->n_fwd == 0) return set_error(EMT_EINVAL, "no component of this batch runs in one workgroup");
+      hip_check(hipMalloc(reinterpret_cast<void **>(&sc.out), (size_t)ctx->n_fwd * ctx->ks.bs * sizeof(double)),
+                "hipMalloc");
+      hip_check(hipEventRecord(sc.e0, st), "event");
+      hip_check(emt::launch_barrier_floor(ctx->ks.bs, ctx->n_fwd, ctx->sweep_levels + 2, n_steps, ctx->ks.lds_fwd,
+                                          sc.out, st),
+                "barrier floor");
+      hip_check(hipEventRecord(sc.e1, st), "event");
+    } else if (kernel == EMT_FLOOR_SPLIT) {
+      if (ctx->n_tiles == 0) return set_error(EMT_EINVAL, "no split component in this batch");
+      check_split(*ctx);
+      hip_check(hipEventRecord(sc.e0, st), "event");
+      launch_split_step(*ctx, 0, n_steps, nullptr, st, true);
+      hip_check(hipEventRecord(sc.e1, st), "event");
+    } else {
+      return set_error(EMT_EINVAL, "kernel must be EMT_FLOOR_ONE_WORKGROUP or EMT_FLOOR_SPLIT");
+    }
+    hip_check(hipEventSynchronize(sc.e1), "sync");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, sc.e0, sc.e1), "event time");
+    if (kernel == EMT_FLOOR_SPLIT) check_split(*ctx);
+    *us_per_step = (double)ms * 1e3 / (double)n_steps;
     return EMT_OK;
   });
 }

@@ -78,7 +78,11 @@ size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt);
 hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *jobs, int n_jobs, size_t lds,
                           hipStream_t st);
 hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_blocks, int64_t n0,
-                        int64_t ns, double *rec, size_t lds, hipStream_t st);
+                        int64_t ns, double *rec, size_t lds, bool floor, hipStream_t st);
 hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks);
+
+// Latency floors (floor.hip; the split floor is launch_split with floor set).
+hipError_t launch_barrier_floor(int bs, int n_blocks, int phases, int64_t nsteps, size_t lds, double *out,
+                                hipStream_t st);
 
 }  // namespace emt

@@ -150,8 +150,11 @@ __global__ __launch_bounds__(256) void k_inverse(DevCtx c, SplitCtx s, const int
 }
 
 // Forward time loop of the split components: one workgroup per tile, all
-// steps n0+1 .. n0+nsteps.
-template <int BPT, int RPL, int RT>
+// steps n0+1 .. n0+nsteps. FLOOR (a measurement) keeps the placement check,
+// the tagged exchange and the barriers of every step but drops the
+// arithmetic (right-hand side, partial products, branch update) and writes
+// no state or output: its time per step is the floor the exchange sets.
+template <int BPT, int RPL, int RT, bool FLOOR>
 __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_t n0, int64_t nsteps,
                                                    double *rec) {
   constexpr int BS = kSplitBS;
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   for (int64_t m = n0 + 1; m <= n_end; ++m) {
     const int tid = tid_();
     // 1. injections of the owned nodes, 16 lanes per node
-    {
+    if constexpr (!FLOOR) {
       const int node = tid >> 4, sub = tid & 15;
       double acc = 0.0;
       if (node < tl.cnt) {
@@ -323,8 +326,10 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       // four independent fused multiply-add chains (columns k mod 4), then
       // a fixed pairing: every tile rounds its partials the same way
       double a[4] = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (!FLOOR) {
 #pragma unroll
-      for (int k = 0; k < RT; ++k) a[k & 3] = __builtin_fma(w[rr * RT + k], rv[k], a[k & 3]);
+        for (int k = 0; k < RT; ++k) a[k & 3] = __builtin_fma(w[rr * RT + k], rv[k], a[k & 3]);
+      }
       const double acc = (a[0] + a[1]) + (a[2] + a[3]);
       // tagged, device-coherent 8-byte store: the two lowest mantissa bits
       // carry the step's tag, so readers recognise this step's value. The
@@ -415,6 +420,11 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     }
     lds_barrier();
     if (abort_flag[0]) break;
+    if constexpr (FLOOR) {
+      e0 = e_next;
+      lds_barrier();
+      continue;
+    }
     // 4. record, branch update, next injection
     if (rec) {
       double *row = rec + ((int64_t)it.scen * nsteps + (m - n0 - 1)) * R;
@@ -472,10 +482,10 @@ hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *job
 
 namespace {
 
-template <int BPT, int RPL, int RT>
+template <int BPT, int RPL, int RT, bool FLOOR>
 hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_blocks, int64_t n0, int64_t ns, double *rec,
                         size_t lds, hipStream_t st) {
-  auto k = k_split<BPT, RPL, RT>;
+  auto k = k_split<BPT, RPL, RT, FLOOR>;
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -488,7 +498,7 @@ hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_blocks, int64_
 
 template <int BPT, int RPL, int RT>
 hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
-  auto k = k_split<BPT, RPL, RT>;
+  auto k = k_split<BPT, RPL, RT, false>;
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -505,9 +515,11 @@ hipError_t split_occupancy(int *blocks_per_cu, size_t lds) {
   X(4, 4, 16) X(1, 1, 32) X(1, 2, 32) X(2, 1, 32) X(2, 2, 32) X(4, 1, 32)
 
 hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_blocks, int64_t n0,
-                        int64_t ns, double *rec, size_t lds, hipStream_t st) {
-#define EMT_CASE(B, R, W) \
-  if (bpt == B && rpl == R && rt == W) return split_launch<B, R, W>(c, s, n_blocks, n0, ns, rec, lds, st);
+                        int64_t ns, double *rec, size_t lds, bool floor, hipStream_t st) {
+#define EMT_CASE(B, R, W)                                                                               \
+  if (bpt == B && rpl == R && rt == W)                                                                  \
+    return floor ? split_launch<B, R, W, true>(c, s, n_blocks, n0, ns, nullptr, lds, st)               \
+                 : split_launch<B, R, W, false>(c, s, n_blocks, n0, ns, rec, lds, st);
   EMT_SPLIT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;

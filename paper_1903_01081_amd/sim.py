@@ -101,6 +101,14 @@ class Simulator:
     def reset(self):
         check(self.lib.emt_reset(self._ctx, _stream()))
 
+    def latency_floor(self, kernel: str, n_steps: int) -> float:
+        """Microseconds per step of the no-arithmetic floor of a step kernel
+        ("one_workgroup" or "split"), same launch shape; state untouched."""
+        us = C.c_double(0.0)
+        check(self.lib.emt_latency_floor(self._ctx, _lib.FLOOR_KERNELS[kernel], int(n_steps), C.byref(us),
+                                         _stream()))
+        return us.value
+
     def step(self, n: int, rec: Optional[torch.Tensor] = None, record: bool = True):
         """Advance n steps; returns rec [S, n, R] (allocated if not given)."""
         if record and rec is None:
