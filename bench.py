@@ -182,10 +182,11 @@ def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
     sim = Simulator(nets, cfg["dt"], T, **other)
     rec = torch.empty((1, T, sim.R), dtype=torch.float64, device=sim.device)
     wall, kern = time_simulation(torch, sim, rec, 1, 1)
+    floor = sim.latency_floor("split" if sim.info()["split_tiles"] > 0 else "one_workgroup", 20000)
     sim.close()
     return {"tuned_shape": shape, "tuned_node_steps_per_s": N * T / best_run_s,
             "other_shape": other, "other_node_steps_per_s": N * T / wall,
-            "other_us_per_time_step": kern / T * 1e6,
+            "other_us_per_time_step": kern / T * 1e6, "other_floor_us_per_time_step": floor,
             "tuner_trials": [
                 {"shape": t["shape"], "us_per_step": t["s_per_step"] * 1e6, "factor_ms": t["factor_s"] * 1e3}
                 if "s_per_step" in t else {"shape": t["shape"], "rejected": t["rejected"]}
