@@ -355,6 +355,8 @@ def main():
     rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     log(f"built grid1000 in {build_s:.2f} s: {info}")
     wall, kern = time_simulation(torch, sim, rec, args.steps, args.warmup)
+    # split components whose workgroups exchanged through one XCD's L2
+    split_local = sim.info()["split_local"]
     value = N * T * args.steps / wall
     kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
     sizes = component_sizes(net) if kernel == "k_split" else None
@@ -372,7 +374,7 @@ def main():
                    "nodes": N, "branches": int(net.n_branches), "time_steps": T,
                    "bench_step": "emt_factor + emt_step over the whole horizon",
                    "launch_shape": shape, "split_tiles": info["split_tiles"],
-                   "split_cols": info["split_cols"]},
+                   "split_cols": info["split_cols"], "split_components_xcd_local": split_local},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
