@@ -193,20 +193,32 @@ def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
                 for t in tuned["trials"]]}
 
 
-def extras(torch, args):
-    """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
-    uneven batched gradients; each measured once after a warmup."""
+def batched_n1(torch):
+    """The 400-scenario N-1 batch in one launch with its tuned shape: returns
+    (networks, settings, shape, wall s, kernel s)."""
     from paper_1903_01081_amd import netgen
-    from paper_1903_01081_amd.sim import Simulator, theta_matrix
-    out = {}
-    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps;
-    # each side with its own tuned launch shape.
+    from paper_1903_01081_amd.sim import Simulator
     from paper_1903_01081_amd.tune import tune
     nets, cfg = netgen.config2()
     shape_b = tune(nets, cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
     sim = Simulator(nets, cfg["dt"], cfg["n_steps"], **shape_b)
     rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     wall, kern = time_simulation(torch, sim, rec, 1, 1)
+    sim.close()
+    del rec
+    return nets, cfg, shape_b, wall, kern
+
+
+def extras(torch, args):
+    """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
+    uneven batched gradients; each measured once after a warmup."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator, theta_matrix
+    from paper_1903_01081_amd.tune import tune
+    out = {}
+    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps;
+    # each side with its own tuned launch shape.
+    nets, cfg, shape_b, wall, kern = batched_n1(torch)
     N = nets[0].n_nodes
     batched = len(nets) * N * cfg["n_steps"] / wall
     # plain per-scenario loop: a sample of scenarios run one at a time
@@ -224,8 +236,6 @@ def extras(torch, args):
                          "value": batched, "unit": "node-steps/s", "seconds": wall, "launch_shape": shape_b,
                          "plain_loop_value": plain, "plain_loop_sample": f"{n_plain} scenarios run one at a time",
                          "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
-    sim.close()
-    del rec
     # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500 (tuned shape).
     nets, cfg = netgen.config3()
     shape_a = tune(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"],
@@ -314,6 +324,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-n1", action="store_true",
+                    help="run only the batched N-1 workload (one line; for profiling its kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -328,6 +340,13 @@ def main():
     import torch
     if args.calibrate_copy:
         calibrate_copy(torch)
+        return
+    if args.only_n1:
+        nets, cfg, shape, wall, kern = batched_n1(torch)
+        nsteps = len(nets) * nets[0].n_nodes * cfg["n_steps"]
+        print(json.dumps({"metric": "node-steps/s, batched N-1", "value": nsteps / wall, "unit": "node-steps/s",
+                          "workload": "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us",
+                          "launch_shape": shape, "seconds": wall, "kernel_s": kern}), flush=True)
         return
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
