@@ -292,8 +292,8 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
     si.gt = gt_off;
     si.xbuf = xb_off;
     gt_off += (int64_t)sc.n_topo * P * RT * n;
-    c.split_xbuf.emplace_back(xb_off, (int64_t)n * ((P + 7) & ~7));
-    xb_off += 2 * (int64_t)n * ((P + 7) & ~7);
+    c.split_xbuf.emplace_back(xb_off, (int64_t)split_rows_padded(n) * ((P + 7) & ~7));
+    xb_off += 2 * (int64_t)split_rows_padded(n) * ((P + 7) & ~7);
     inv_lds = std::max(inv_lds, (size_t)si.cb * n * sizeof(double));
     for (int t = 0; t < sc.n_topo; ++t)
       for (int j0 = 0; j0 < n; j0 += si.cb) {

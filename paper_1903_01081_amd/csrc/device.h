@@ -66,6 +66,13 @@ constexpr int kSplitBS = 512;
 // 2048 / rt tiles, and the lanes per node are raised until each lane's share
 // fits (smaller for 32-column tiles, whose weight cache fills the registers).
 constexpr int split_max_partials(int rt) { return rt >= 32 ? 8 : 16; }
+// Exchange buffer layout: the partials of kSplitRowBlock consecutive nodes
+// are interleaved per tile ([node / 4][tile][node % 4]), so one wave's
+// stores of consecutive nodes land in 32-byte runs (a quarter of the
+// memory transactions of one node per row) while a node's P partials still
+// span few cache lines. Rows are padded to a multiple of kSplitRowBlock.
+constexpr int kSplitRowBlock = 4;
+constexpr int split_rows_padded(int n) { return (n + kSplitRowBlock - 1) / kSplitRowBlock * kSplitRowBlock; }
 
 struct SplitItem {
   int32_t item, P, cb, rt;   // item, tiles, inverse columns per workgroup of k_inverse, columns per tile
@@ -73,7 +80,8 @@ struct SplitItem {
   int32_t t0;                // index of its first tile (its tiles are t0 .. t0 + P - 1)
   int64_t pos;               // SplitCtx::i32: [n] tile position of each column (tile * rt + k)
   int64_t gt;                // SplitCtx::gt: [n_topo][P][rt][n] inverse columns
-  int64_t xbuf;              // SplitCtx::xbuf: [2][n][Pp] tagged partial voltages (Pp = P rounded up to 8)
+  int64_t xbuf;              // SplitCtx::xbuf: [2][n4 / 4][Pp][4] tagged partial voltages (Pp = P rounded up
+                             // to 8, n4 = n rounded up to 4)
 };
 
 struct SplitTile {

@@ -50,6 +50,14 @@ constexpr int kHintRows = 8;
 
 __device__ __forceinline__ int tid_() { return step::lane_id(); }
 
+// Position of node r's first partial in an exchange buffer (its partials
+// follow at a stride of kSplitRowBlock).
+__device__ __forceinline__ int64_t node_base(int r, int Pp) {
+  static_assert(kSplitRowBlock == 4, "shifts below");
+  const unsigned u = (unsigned)r;  // node ids are >= 0
+  return (int64_t)(((u >> 2) * (unsigned)Pp) << 2) + (u & 3u);
+}
+
 // Accesses to an exchange buffer. Device-wide (the component's tiles span
 // XCDs): 8-byte relaxed atomics at agent scope, served by device-coherent
 // memory. XCD-local (all its tiles on one XCD): stores at workgroup scope,
@@ -87,7 +95,7 @@ __device__ __forceinline__ void load_partials(bool local, __amdgpu_buffer_rsrc_t
     for (int k = 0; k < K; ++k) {
       const int q = sub + (k << lg);
       if (stale_only && (pv[k] & 3) == tag) continue;
-      pv[k] = q < P ? __hip_atomic_load(r + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+      pv[k] = q < P ? __hip_atomic_load(r + q * kSplitRowBlock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
     }
     return;
   }
@@ -96,7 +104,7 @@ __device__ __forceinline__ void load_partials(bool local, __amdgpu_buffer_rsrc_t
   for (int k = 0; k < K; ++k) {
     const int q = sub + (k << lg);
     if (stale_only && (pv[k] & 3) == tag) continue;
-    pv[k] = q < P ? l2_load_off(rs, off0 + q * 8) : tag;
+    pv[k] = q < P ? l2_load_off(rs, off0 + q * (8 * kSplitRowBlock)) : tag;
   }
 }
 
@@ -165,16 +173,16 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   const SplitTile tl = s.tiles[tix];
   const SplitItem sp = s.items[tl.sitem];
   const ItemDesc it = c.items[sp.item];
-  const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7;
+  const int n = it.n, nn = tl.nn, P = sp.P, Pp = (P + 7) & ~7, n4 = split_rows_padded(n);
   // lanes that sum one node's partials, chosen per component so that one
   // round covers every tile's nodes
   const int lq_lg = sp.lq_lg;
   const int slot0 = (int)threadIdx.x >> lq_lg;
-  const int64_t row0 = slot0 < nn ? (int64_t)s.i32[tl.need + slot0] * Pp : 0;
+  const int64_t row0 = slot0 < nn ? node_base(s.i32[tl.need + slot0], Pp) : 0;
   // readiness hint: the partials of one of the component's last kHintRows
   // nodes (each tile stores those last), spread over the reading tiles so
   // that no one row draws every tile's polls
-  const int64_t row0_hint = (int64_t)(n - 1 - tl.p % kHintRows) * Pp;
+  const int64_t row0_hint = node_base(n - 1 - tl.p % kHintRows, Pp);
 
   // LDS: x[nn + 1] (x[nn] = 0 for grounded terminals), J[BS * BPT],
   // rhs[RT], need[nn], nptr[RT + 1], nent[ne], rec[nrec], abort flag and
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   // the component's two exchange buffers as one raw buffer resource (no
   // stride, size in bytes, 32-bit data format) for the XCD-local loads
   const uint64_t *xbase = reinterpret_cast<const uint64_t *>(xb);
-  const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(xb, 0, 2 * n * Pp * 8, 0x00020000);
+  const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(xb, 0, 2 * n4 * Pp * 8, 0x00020000);
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
   for (int64_t m = n0 + 1; m <= n_end; ++m) {
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     double rv[RT];
 #pragma unroll
     for (int k = 0; k < RT; ++k) rv[k] = rhs[k];
-    double *xw = xb + (int64_t)(m & 1) * n * Pp;
+    double *xw = xb + (int64_t)(m & 1) * n4 * Pp;
     const uint64_t tag = (uint64_t)((m >> 1) & 3);
     uint64_t hint_bits = 0;
     int hint_r = -1;
@@ -341,12 +349,13 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
         hint_bits = bits;
         hint_r = r;
       } else if (r < n) {
-        xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + (int64_t)r * Pp + tl.p, bits);
+        xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + node_base(r, Pp) + tl.p * kSplitRowBlock, bits);
       }
     }
     lds_barrier();
     if (hint_r >= 0)
-      xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + (int64_t)hint_r * Pp + tl.p, hint_bits);
+      xput(xcd_local, reinterpret_cast<uint64_t *>(xw) + node_base(hint_r, Pp) + tl.p * kSplitRowBlock,
+           hint_bits);
     // the next step's source EMF does not depend on this step's voltages:
     // computed here, it overlaps the reads below
     const bool last = (m == n_end);
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
     // split in every tile of the component, so all tiles round alike). The
     // first round's node offsets sit in a register.
     {
-      const uint64_t *xr = reinterpret_cast<const uint64_t *>(xb) + (int64_t)(m & 1) * n * Pp;
+      const uint64_t *xr = reinterpret_cast<const uint64_t *>(xb) + (int64_t)(m & 1) * n4 * Pp;
       bool quit = false;
       // readiness hint (device-wide exchange only): wave 0 polls the P
       // partials of its hint row, among each tile's final stores (P loads a
@@ -373,7 +382,8 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
           bool ok = true;
           asm volatile("" ::: "memory");  // reload every round
           for (int q = tid; q < P; q += 64)
-            ok = ok && (__hip_atomic_load(hint + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 3) == tag;
+            ok = ok && (__hip_atomic_load(hint + q * kSplitRowBlock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 3) ==
+                           tag;
           if (__all(ok)) break;
           if ((++spins & 255) == 0 &&
               (spins > kSpinLimit || __hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
@@ -387,7 +397,7 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       const int sub = tid & ((1 << lq_lg) - 1);
       int round = 0;
       for (int slot = tid >> lq_lg; slot < nn; slot += BS >> lq_lg, ++round) {
-        uint64_t *row = const_cast<uint64_t *>(xr) + (round == 0 ? row0 : (int64_t)need[slot] * Pp);
+        uint64_t *row = const_cast<uint64_t *>(xr) + (round == 0 ? row0 : node_base(need[slot], Pp));
         uint64_t pv[kPPL];
         load_partials(xcd_local, xrs, xbase, pv, row, sub, lq_lg, P, tag, false);
         for (int64_t spins = 0;;) {
