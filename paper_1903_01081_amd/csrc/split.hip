@@ -7,7 +7,8 @@
 // them. Per step, a tile:
 //   1. sums the injections of its own nodes (fixed CSR order, DPP scan);
 //   2. multiplies them into its columns of G^{-1}: a partial voltage for
-//      every node, written to the component's exchange buffer;
+//      every node, written to the component's exchange buffer (four
+//      consecutive nodes' partials of one tile side by side);
 //   3. reads the P partials of each node its branches touch, polling until
 //      each carries the step's tag, and sums them in tile order, so every
 //      tile obtains bitwise the same voltages;
