@@ -60,11 +60,42 @@ def algorithmic_flops_per_step(info, component_sizes=None):
     return f + 2 * sum(int(n) ** 2 for n in component_sizes)
 
 
+def roofline_object(info, n_rec_total, time_steps, kernel, kernel_s, traffic=None, passes=1.0,
+                    extra_bytes_per_step=0):
+    """The method's roofline for one launch of a step kernel: the bytes the
+    sparse method touches per time step (the figure above without a dense
+    inverse, whichever solver ran: the dense inverse is extra work this
+    library chooses, not work the method needs) times the time steps of
+    the launch (times `passes` for launches that step each time step more
+    than once, e.g. an adjoint's recompute + reverse), over the kernel's
+    time from HIP events on its stream, against the 8 TB/s HBM peak. The
+    step kernels keep their per-step data on chip, so the binding limit is
+    the chain of dependent phases per step (the `latency` object), not
+    HBM; `traffic` is the counter-measured HBM bytes per launch when a
+    profile of the current sources exists."""
+    per_step = algorithmic_bytes_per_step(info, n_rec_total) + extra_bytes_per_step
+    achieved = per_step * time_steps * passes / kernel_s / 1e9
+    flops = algorithmic_flops_per_step(info) * time_steps * passes / kernel_s / 1e12
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+           "limiter": "latency (see the latency object)",
+           "kernel": kernel, "kernel_s": kernel_s, "time_steps": time_steps, "passes": passes,
+           "algorithmic_bytes_per_time_step": per_step,
+           "fp64_flops_per_time_step": algorithmic_flops_per_step(info), "fp64_tflops": flops,
+           "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": flops / FP64_PEAK_TFLOPS}
+    if traffic is not None:
+        out["traffic_gbs"] = traffic / kernel_s / 1e9
+        out["traffic_frac"] = traffic / kernel_s / 1e9 / HBM_PEAK_GBS
+    return out
+
+
 def latency_object(sim, kernel, us_per_step, info):
     """The step kernel's time per step against its latency floor: the same
     launch shape running only its barrier-separated phases (and, for the
     split path, its exchange), measured by emt_latency_floor after the timed
-    region."""
+    region. floor_over_step is the efficiency figure of a latency-bound
+    loop (1 = the step costs no more than its empty phases)."""
     kind = "split" if kernel == "k_split" else "one_workgroup"
     floor = sim.latency_floor(kind, 20000)
     return {"us_per_time_step": us_per_step, "block_size": info["block_size"],
@@ -121,19 +152,19 @@ def measured_traffic(kernel=None):
 def time_simulation(torch, sim, rec, steps, warmup):
     """Warmup, then `steps` full runs (reset + factor + all steps). Returns
     (wall seconds, forward-kernel seconds per run from HIP events on the
-    launch stream)."""
+    launch stream). Every run's device-side status is checked (emt_sync)."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         sim.reset()
         sim.factor()
         sim.step(sim.n_steps, rec=rec)
-        torch.cuda.synchronize()
+        sim.sync()
         log(f"  warmup run done")
     evs = []
     t0 = time.perf_counter()
     for k in range(steps):
         sim.reset()
-        sim.factor()
+        sim.factor()   # synchronises: also reports the previous run's device status
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -141,35 +172,88 @@ def time_simulation(torch, sim, rec, steps, warmup):
         b.record(stream)
         evs.append((a, b))
         if k == 0:
-            torch.cuda.synchronize()
+            sim.sync()
             log(f"  first timed run: {a.elapsed_time(b) / 1e3:.3f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    sim.sync()
     kern = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
     return wall, kern
 
 
-def cpu_baseline_config1(nets, cfg):
-    """The oracle (dense LU, one thread) on a bounded sample of the workload:
-    two short runs (50 and 2550 steps) give the factorisation and per-step
-    costs, extrapolated to the full horizon with its two factorisations."""
-    from oracle import oracle as O
-    net = nets[0]
-    dt = cfg["dt"]
-    t0 = time.perf_counter()
-    O.run(net, dt, 50)
-    t50 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    O.run(net, dt, 2550)
-    t_long = time.perf_counter() - t0
-    per_step = max((t_long - t50) / 2500.0, 1e-12)
-    factor = max(t50 - 50 * per_step, 0.0)
-    T = cfg["n_steps"]
-    total = 2 * factor + T * per_step
-    return {"value": net.n_nodes * T / total, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle runs of 50 and 2550 steps of the same 3000-node grid "
-                      f"({t50 + t_long:.1f} s of CPU); per-step {per_step * 1e3:.2f} ms and "
-                      f"factorisation {factor:.2f} s extrapolated to 50,000 steps and 2 factorisations"}
+def median_time(fn, repeats=3):
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), ts
+
+
+# --------------------------------------------------------------------------
+# CPU baselines: the oracle (plain dense LU, test infrastructure) compiled
+# with -O3 -march=native on the host that runs the bench, timed on bounded
+# samples of the same workloads.
+# --------------------------------------------------------------------------
+
+CPU_THREADS = 8
+
+
+def cpu_baselines(O):
+    """Returns (headline cpu_baseline, {"n1": ..., "uneven": ...})."""
+    import concurrent.futures as cf
+    from paper_1903_01081_amd import netgen
+    O.use_native_build()
+    out = {}
+    # grid1000, one thread: median of 3 runs of a 500-step prefix (one
+    # factorisation each)
+    nets, cfg = netgen.config1()
+    net, k = nets[0], 500
+    med, ts = median_time(lambda: O.run(net, cfg["dt"], k))
+    head = {"value": net.n_nodes * k / med, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (g++ -O3 -march=native, 1 thread) on the first {k} of the 50,000 steps of the "
+                      f"same 3000-node grid, factorisation included; median of 3 runs "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    # grid200 N-1, 8 threads over scenarios: 16 of the 400 scenarios (every
+    # 25th) over a 3000-step prefix that includes the event at step 2500
+    nets, cfg = netgen.config2()
+    sample = nets[::25]
+    k = 3000
+    med, ts = median_time(lambda: O.run_batch(sample, cfg["dt"], k, n_threads=CPU_THREADS))
+    out["n1"] = {"value": len(sample) * nets[0].n_nodes * k / med, "unit": "node-steps/s",
+                 "cores": CPU_THREADS, "kind": "oracle",
+                 "sample": f"{len(sample)} of the 400 scenarios (every 25th), first {k} of 15,000 steps "
+                           f"(the event at step 2500 included), OpenMP over scenarios on {CPU_THREADS} threads; "
+                           f"median of 3 runs ({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    # uneven batch, 8 threads over instances: forward + adjoint of 8
+    # instances spread over the size range; the full batch's time is
+    # predicted from a fit t = a + b n^2 (dense LU work per step) over the
+    # sample
+    nets, cfg = netgen.config4()
+    sizes = np.array([n.n_nodes for n in nets])
+    order = np.argsort(sizes, kind="stable")
+    pick = [int(order[int(round(q * (len(nets) - 1)))]) for q in np.linspace(0, 1, CPU_THREADS)]
+
+    def one(j):
+        net = nets[j]
+        cot = np.random.default_rng(100 + j).standard_normal((cfg["n_steps"], len(net.rec_nodes)))
+        t0 = time.perf_counter()
+        O.adjoint(net, cfg["dt"], cfg["n_steps"], cot)
+        return time.perf_counter() - t0
+
+    with cf.ThreadPoolExecutor(CPU_THREADS) as ex:
+        t_one = np.array(list(ex.map(one, pick)))
+    n2 = sizes[pick].astype(float) ** 2
+    A = np.stack([np.ones_like(n2), n2], 1)
+    coef, *_ = np.linalg.lstsq(A, t_one, rcond=None)
+    total_1thread = float(np.sum(coef[0] + coef[1] * sizes.astype(float) ** 2))
+    out["uneven"] = {"value": len(nets) / (total_1thread / CPU_THREADS), "unit": "gradients/s",
+                     "cores": CPU_THREADS, "kind": "oracle",
+                     "sample": f"forward + adjoint (oracle_adjoint, 5000 steps) of {len(pick)} instances spread "
+                               f"over the size range ({', '.join(str(int(sizes[j])) for j in pick)} nodes), one per "
+                               f"thread on {CPU_THREADS} threads ({', '.join(f'{t:.1f}' for t in t_one)} s); "
+                               f"all 256 predicted by a fit t = a + b n^2, spread over {CPU_THREADS} threads"}
+    return head, out
 
 
 def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
@@ -193,114 +277,188 @@ def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
                 for t in tuned["trials"]]}
 
 
+N1_WORKLOAD = "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us"
+
+
 def batched_n1(torch):
-    """The 400-scenario N-1 batch in one launch with its tuned shape: returns
-    (networks, settings, shape, wall s, kernel s)."""
+    """The 400-scenario N-1 batch in one launch with its tuned shape:
+    returns (networks, settings, shape, wall s, kernel s, roofline, latency)."""
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
     from paper_1903_01081_amd.tune import tune
     nets, cfg = netgen.config2()
     shape_b = tune(nets, cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
     sim = Simulator(nets, cfg["dt"], cfg["n_steps"], **shape_b)
+    info = sim.info()
     rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     wall, kern = time_simulation(torch, sim, rec, 1, 1)
+    kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
+    T = cfg["n_steps"]
+    roof = roofline_object(info, sum(n.n_rec for n in nets), T, kernel, kern)
+    lat = latency_object(sim, kernel, kern / T * 1e6, info)
     sim.close()
     del rec
-    return nets, cfg, shape_b, wall, kern
+    return nets, cfg, shape_b, wall, kern, roof, lat
 
 
 def extras(torch, args):
     """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
-    uneven batched gradients; each measured once after a warmup."""
+    uneven batched gradients vs the per-instance loop; every side with its
+    own tuned launch shape, medians of repeated timings."""
+    out = extras_n1(torch)
+    out.update(extras_adjoint(torch))
+    return out
+
+
+def extras_n1(torch):
+    from paper_1903_01081_amd.sim import Simulator
+    from paper_1903_01081_amd.tune import tune
+    out = {}
+    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps.
+    nets, cfg, shape_b, wall, kern, roof, lat = batched_n1(torch)
+    N, T = nets[0].n_nodes, cfg["n_steps"]
+    batched = len(nets) * N * T / wall
+    # plain per-scenario loop: every 50th scenario run alone (all scenarios
+    # have the same size), median of 3 runs each, its own tuned shape
+    shape_1 = tune(nets[:1], cfg["dt"], T, probe_steps=300)["shape"]
+    plain_t = []
+    for s in range(0, len(nets), 50):
+        one = Simulator([nets[s]], cfg["dt"], T, **shape_1)
+        r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
+        ts = [time_simulation(torch, one, r1, 1, 1 if k == 0 else 0)[0] for k in range(3)]
+        plain_t.append(float(np.median(ts)))
+        one.close()
+        del r1
+    plain = N * T / float(np.mean(plain_t))
+    out["batched_n1"] = {"workload": N1_WORKLOAD, "value": batched, "unit": "node-steps/s", "seconds": wall,
+                         "launch_shape": shape_b, "roofline": roof, "latency": lat,
+                         "plain_loop_value": plain,
+                         "plain_loop_sample": f"{len(plain_t)} scenarios (every 50th) run one at a time, "
+                                              f"median of 3 runs each",
+                         "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
+    return out
+
+
+def extras_adjoint(torch):
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator, theta_matrix
     from paper_1903_01081_amd.tune import tune
     out = {}
-    # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps;
-    # each side with its own tuned launch shape.
-    nets, cfg, shape_b, wall, kern = batched_n1(torch)
-    N = nets[0].n_nodes
-    batched = len(nets) * N * cfg["n_steps"] / wall
-    # plain per-scenario loop: a sample of scenarios run one at a time
-    shape_1 = tune(nets[:1], cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
-    n_plain = 8
-    plain_t = []
-    for s in range(n_plain):
-        one = Simulator([nets[s]], cfg["dt"], cfg["n_steps"], **shape_1)
-        r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
-        w1, _ = time_simulation(torch, one, r1, 1, 1 if s == 0 else 0)
-        plain_t.append(w1)
-        one.close()
-    plain = N * cfg["n_steps"] / float(np.mean(plain_t))
-    out["batched_n1"] = {"workload": "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us",
-                         "value": batched, "unit": "node-steps/s", "seconds": wall, "launch_shape": shape_b,
-                         "plain_loop_value": plain, "plain_loop_sample": f"{n_plain} scenarios run one at a time",
-                         "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
-    # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500 (tuned shape).
+    # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500 (tuned shape),
+    # for the pipelined kernel and the serial one; medians of 5.
     nets, cfg = netgen.config3()
-    shape_a = tune(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"],
-                   probe_steps=300)["shape"]
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"], **shape_a)
-    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
-    cot = torch.randn((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
-    for _ in range(2):
-        sim.reset()
-        sim.factor()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(sim.n_steps, rec=rec)
-        torch.cuda.synchronize()
-        t_fwd = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        sim.adjoint(cot)
-        torch.cuda.synchronize()
-        t_adj = time.perf_counter() - t0
-    out["adjoint"] = {"workload": "grid100: 300 nodes, 10,000 steps at 50 us, 450 parameters, checkpoint every 500",
-                      "launch_shape": shape_a, "pipelined": bool(sim.info()["adjoint_pipelined"]),
-                      "forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_over_forward": t_adj / t_fwd}
-    sim.close()
-    # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint (tuned
-    # shape for the batch; the per-instance loop keeps the library default).
+    T, K = cfg["n_steps"], cfg["checkpoint_every"]
+    shape_a = tune(nets, cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
+    adj = {"workload": "grid100: 300 nodes, 10,000 steps at 50 us, 450 parameters, checkpoint every 500",
+           "launch_shape": shape_a}
+    for serial in (False, True):
+        sim = Simulator(nets, cfg["dt"], T, checkpoint_every=K, **dict(shape_a, serial_adjoint=serial))
+        info = sim.info()
+        rec = torch.empty((1, T, sim.R), dtype=torch.float64, device=sim.device)
+        cot = torch.randn((1, T, sim.R), dtype=torch.float64, device=sim.device,
+                          generator=torch.Generator(device=sim.device).manual_seed(3))
+        stream = torch.cuda.current_stream()
+        t_f, t_a, k_a = [], [], []
+        for _ in range(6):
+            sim.reset()
+            sim.factor()
+            t0 = time.perf_counter()
+            sim.step(T, rec=rec)
+            sim.sync()
+            t1 = time.perf_counter()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sim.adjoint(cot)
+            b.record(stream)
+            sim.sync()
+            t_f.append(t1 - t0)
+            t_a.append(time.perf_counter() - t1)
+            k_a.append(a.elapsed_time(b) / 1e3)
+        t_f, t_a, k_a = t_f[1:], t_a[1:], k_a[1:]   # the first is a warmup
+        kname = "k_adjoint" if serial else ("k_adjoint_pipe" if info["adjoint_pipelined"] else "k_adjoint")
+        n_br = info["total_branches"]
+        # recompute + reverse each step; segment buffer written and read
+        # (i, u per branch: 16 B per branch, twice)
+        roof = roofline_object(info, 0, T, kname, float(np.median(k_a)), passes=2.0,
+                               extra_bytes_per_step=32 * n_br)
+        lat = latency_object(sim, "k_forward", float(np.median(k_a)) / T * 1e6, info)
+        key = "serial" if serial else "default"
+        adj[key] = {"pipelined": bool(info["adjoint_pipelined"]), "kernel": kname,
+                    "forward_s": float(np.median(t_f)), "adjoint_s": float(np.median(t_a)),
+                    "adjoint_over_forward": float(np.median(t_a)) / float(np.median(t_f)),
+                    "timings": "median of 5 after one warmup", "roofline": roof, "latency": lat}
+        sim.close()
+        del rec, cot
+    adj["adjoint_over_forward"] = adj["default"]["adjoint_over_forward"]
+    out["adjoint"] = adj
+    # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint, tuned
+    # shape; median of 3.
     nets, cfg = netgen.config4()
-    shape_u = tune(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"],
-                   probe_steps=300)["shape"]
-    sim = Simulator(nets, cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"], **shape_u)
+    T, K = cfg["n_steps"], cfg["checkpoint_every"]
+    shape_u = tune(nets, cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
+    sim = Simulator(nets, cfg["dt"], T, checkpoint_every=K, **shape_u)
+    info = sim.info()
     theta = theta_matrix(nets, device=sim.device)
-    rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
-    cot = torch.randn_like(rec)
-    for _ in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+    rec = torch.empty((sim.S, T, sim.R), dtype=torch.float64, device=sim.device)
+    cot = torch.randn((sim.S, T, sim.R), dtype=torch.float64, device=sim.device,
+                      generator=torch.Generator(device=sim.device).manual_seed(4))
+
+    def run_batch():
         sim.set_params(theta)
         sim.factor()
-        sim.step(sim.n_steps, rec=rec)
+        sim.step(T, rec=rec)
         sim.adjoint(cot)
-        torch.cuda.synchronize()
-        t_b = time.perf_counter() - t0
-    n_loop = 8
-    loop_t = []
-    for j in range(n_loop):
-        one = Simulator([nets[j]], cfg["dt"], cfg["n_steps"], checkpoint_every=cfg["checkpoint_every"])
+        sim.sync()
+
+    run_batch()
+    t_b, ts_b = median_time(run_batch)
+    kname = "k_adjoint_pipe" if info["adjoint_pipelined"] else "k_adjoint"
+    roof = roofline_object(info, sum(n.n_rec for n in nets), T, f"k_forward + {kname}", t_b, passes=3.0,
+                           extra_bytes_per_step=32 * info["total_branches"])
+    lat = latency_object(sim, "k_forward", t_b / (3 * T) * 1e6, info)
+    sim.close()
+    del rec, cot, theta
+    # per-instance loop: 8 instances spread over the size range, each with
+    # its own tuned shape, median of 3; the loop over all 256 is predicted
+    # from a fit t = a + b n over the sample
+    sizes = np.array([n.n_nodes for n in nets])
+    order = np.argsort(sizes, kind="stable")
+    pick = [int(order[int(round(q * (len(nets) - 1)))]) for q in np.linspace(0, 1, 8)]
+    loop_t, loop_shapes = [], []
+    for j in pick:
+        sh = tune([nets[j]], cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
+        one = Simulator([nets[j]], cfg["dt"], T, checkpoint_every=K, **sh)
         th1 = theta_matrix([nets[j]], device=one.device)
-        r1 = torch.empty((1, one.n_steps, one.R), dtype=torch.float64, device=one.device)
-        c1 = torch.randn_like(r1)
-        for _ in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+        r1 = torch.empty((1, T, one.R), dtype=torch.float64, device=one.device)
+        c1 = torch.randn((1, T, one.R), dtype=torch.float64, device=one.device,
+                         generator=torch.Generator(device=one.device).manual_seed(j))
+
+        def run_one():
             one.set_params(th1)
             one.factor()
-            one.step(one.n_steps, rec=r1)
+            one.step(T, rec=r1)
             one.adjoint(c1)
-            torch.cuda.synchronize()
-            tj = time.perf_counter() - t0
-        loop_t.append(tj)
+            one.sync()
+
+        run_one()
+        loop_t.append(median_time(run_one)[0])
+        loop_shapes.append(sh)
         one.close()
-    out["uneven_gradients"] = {"workload": "256 grids of 90-900 nodes, 5000 steps at 50 us, forward + adjoint",
-                               "launch_shape": shape_u, "pipelined": bool(sim.info()["adjoint_pipelined"]),
-                               "gradients_per_s": len(nets) / t_b, "seconds": t_b,
-                               "per_instance_loop_gradients_per_s": 1.0 / float(np.mean(loop_t)),
-                               "loop_sample": f"{n_loop} instances run one at a time"}
-    sim.close()
+        del r1, c1, th1
+    A = np.stack([np.ones(len(pick)), sizes[pick].astype(float)], 1)
+    coef, *_ = np.linalg.lstsq(A, np.array(loop_t), rcond=None)
+    loop_total = float(np.sum(coef[0] + coef[1] * sizes.astype(float)))
+    out["uneven_gradients"] = {
+        "workload": "256 grids of 90-900 nodes, 5000 steps at 50 us, forward + adjoint",
+        "launch_shape": shape_u, "pipelined": bool(info["adjoint_pipelined"]), "adjoint_kernel": kname,
+        "gradients_per_s": len(nets) / t_b, "seconds": t_b, "timings": ts_b, "roofline": roof, "latency": lat,
+        "per_instance_loop_gradients_per_s": len(nets) / loop_total,
+        "loop_sample": f"{len(pick)} instances spread over the size range "
+                       f"({', '.join(str(int(sizes[j])) for j in pick)} nodes), each with its own tuned shape, "
+                       f"median of 3 runs each ({', '.join(f'{t * 1e3:.1f}' for t in loop_t)} ms); the loop "
+                       f"over all 256 predicted by a fit t = a + b n",
+        "loop_shapes": loop_shapes, "speedup_vs_per_instance_loop": loop_total / t_b}
     return out
 
 
@@ -326,6 +484,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-n1", action="store_true",
                     help="run only the batched N-1 workload (one line; for profiling its kernel)")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run only the adjoint workloads (one line; for profiling the adjoint kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -337,17 +497,30 @@ def main():
               "no exchange during the loop). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    import gc
     import torch
-    if args.calibrate_copy:
-        calibrate_copy(torch)
-        return
-    if args.only_n1:
-        nets, cfg, shape, wall, kern = batched_n1(torch)
-        nsteps = len(nets) * nets[0].n_nodes * cfg["n_steps"]
-        print(json.dumps({"metric": "node-steps/s, batched N-1", "value": nsteps / wall, "unit": "node-steps/s",
-                          "workload": "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us",
-                          "launch_shape": shape, "seconds": wall, "kernel_s": kern}), flush=True)
-        return
+    try:
+        if args.calibrate_copy:
+            calibrate_copy(torch)
+        elif args.only_n1:
+            nets, cfg, shape, wall, kern, roof, lat = batched_n1(torch)
+            nsteps = len(nets) * nets[0].n_nodes * cfg["n_steps"]
+            print(json.dumps({"metric": "node-steps/s, batched N-1", "value": nsteps / wall, "unit": "node-steps/s",
+                              "workload": N1_WORKLOAD, "launch_shape": shape, "seconds": wall, "kernel_s": kern,
+                              "roofline": roof, "latency": lat}), flush=True)
+        elif args.only_adjoint:
+            print(json.dumps(extras_adjoint(torch)), flush=True)
+        else:
+            headline(torch, args)
+    finally:
+        # every context is closed by now; leave no device work or library
+        # object for the interpreter's (or a profiler's) exit handlers
+        gc.collect()
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+
+
+def headline(torch, args):
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
     from paper_1903_01081_amd.tune import tune
@@ -379,10 +552,14 @@ def main():
     value = N * T * args.steps / wall
     kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
     sizes = component_sizes(net) if kernel == "k_split" else None
-    per_step_bytes = algorithmic_bytes_per_step(info, net.n_rec, sizes)
-    achieved = per_step_bytes * T / kern / 1e9
-    per_step_flops = algorithmic_flops_per_step(info, sizes)
-    tflops = per_step_flops * T / kern / 1e12
+    lat = latency_object(sim, kernel, kern / T * 1e6, info)
+    roof = roofline_object(info, net.n_rec, T, kernel, kern, traffic=measured_traffic(kernel))
+    # the work the launch actually does with the dense inverse (8 n^2 B and
+    # 2 n^2 flops per component per step, on chip)
+    roof["dense_inverse_bytes_per_time_step"] = algorithmic_bytes_per_step(info, net.n_rec, sizes) \
+        if sizes is not None else None
+    roof["dense_inverse_fp64_tflops"] = (algorithmic_flops_per_step(info, sizes) * T / kern / 1e12
+                                         if sizes is not None else None)
     line = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -394,17 +571,9 @@ def main():
                    "bench_step": "emt_factor + emt_step over the whole horizon",
                    "launch_shape": shape, "split_tiles": info["split_tiles"],
                    "split_cols": info["split_cols"], "split_components_xcd_local": split_local},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": kernel, "kernel_s": kern,
-                     "algorithmic_bytes_per_time_step": per_step_bytes,
-                     # the same kernel against the FP64 vector peak: both
-                     # paths keep their solve data on chip (LDS, VGPRs), so
-                     # the per-step latency chain binds, not HBM or FP64
-                     "fp64_flops_per_time_step": per_step_flops, "fp64_tflops": tflops,
-                     "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": tflops / FP64_PEAK_TFLOPS},
-        "latency": latency_object(sim, kernel, kern / T * 1e6, info),
+        "roofline": roof,
+        "latency": lat,
+        "efficiency": {"figure": "latency.floor_over_step", "value": lat["floor_over_step"]},
         "build_s": build_s, "tune_s": tune_s,
     }
     sim.close()
@@ -413,7 +582,10 @@ def main():
         line["solver_comparison"] = solver_comparison(torch, nets, cfg, tuned, shape, wall / args.steps)
         line.update(extras(torch, args))
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_config1(nets, cfg)
+        from oracle import oracle as O
+        head, others = cpu_baselines(O)
+        line["cpu_baseline"] = head
+        line["cpu_baseline_other"] = others
     print(json.dumps(line), flush=True)
 
 

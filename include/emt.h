@@ -35,10 +35,22 @@
  * only and copied. Device buffers (`*_dev`) belong to the caller, must be
  * device memory of the current HIP device, and must stay valid until the
  * work queued on `stream` has finished. `stream` is a hipStream_t (NULL =
- * the default stream). Calls are stream-ordered; a context is not
- * thread-safe. Every call returns a status; on a non-OK status nothing was
- * queued and emt_last_error() describes the cause. No C++ exception crosses
- * this interface.
+ * the default stream); the calls of one run go to one stream. Calls are
+ * stream-ordered: emt_set_params, emt_reset and emt_step only queue work and
+ * return without waiting for the device; the calls documented as
+ * synchronising (emt_factor, emt_sync, emt_get_state, emt_set_state,
+ * emt_branch_adjoints, emt_latency_floor, emt_destroy, emt_build, the
+ * pipelined emt_adjoint, emt_info_get with split components) wait. Errors
+ * found by the device during queued work (a split launch whose workgroups
+ * gave up waiting for each other) are reported by the next synchronising
+ * call of the same run. A context is not thread-safe. Every call returns a
+ * status; on a non-OK status returned before any work was queued, nothing
+ * was queued, and emt_last_error() describes the cause. No C++ exception
+ * crosses this interface.
+ *
+ * Sources: each declaration below names the passage of the paper that
+ * defines what it computes ("Sec." = a section of arXiv 1903.01081); calls
+ * that are not in the paper say so.
  */
 #ifndef EMT_H
 #define EMT_H
@@ -177,20 +189,33 @@ typedef struct {
                             (0 before the first step; synchronises the device) */
 } emt_info;
 
-/* Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and
+/* Source: Sec. II-A and II-B (a simulation task is a model of connected
+ * components plus the task's configuration, here: time step, horizon,
+ * switching events, recorded outputs), Sec. III-A (the task is turned into
+ * the per-step computations of the four basic processes, ordered in layers)
+ * and Sec. III-B (scenarios of one topology run side by side; here also
+ * networks of different sizes).
+ * Validate, analyse (components, ordering, symbolic LDL^T, sweep levels) and
  * upload n_scen networks; allocates the context on the current HIP device.
  * Companion coefficients are computed from the branch values (no theta).
  * Errors: EMT_EINVAL (any invalid field), EMT_ESINGULAR (a node without a
  * conductive path to ground in some topology), EMT_ENOMEM, EMT_EDEVICE. */
 emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_ctx **out);
 
-/* Host-only: the validation and analysis of emt_build without any device
- * work (same errors except EMT_ENOMEM/EMT_EDEVICE); fills *info. */
+/* Source: Sec. III-A (the task parser and the layering of the basic
+ * processes), without the upload. Host-only: the validation and analysis of
+ * emt_build without any device work (same errors except
+ * EMT_ENOMEM/EMT_EDEVICE); fills *info. */
 emt_status emt_analyze(const emt_net *nets, int32_t n_scen, const emt_sim *sim, emt_info *info);
 
+/* Not in the paper: sizes and launch shape of a built context (fills *info;
+ * EMT_EINVAL on NULL). Synchronises the device when the context has split
+ * components (to read where their last launch ran). */
 emt_status emt_info_get(const emt_ctx *ctx, emt_info *info);
 
-/* Replace the line parameters of every scenario: theta_dev is device memory
+/* Source: Sec. III-A, first basic process (each component's Norton
+ * equivalent conductance and history coefficients, from its parameters).
+ * Replace the line parameters of every scenario: theta_dev is device memory
  * [S][P] (P = info.param_stride; entries past a scenario's n_params are
  * ignored). Recomputes the companion coefficients of all topologies on the
  * device, rewinds to step 0 and marks the factors stale (emt_factor next).
@@ -198,23 +223,39 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info);
  * checked on the device; a bad value shows up as EMT_ESINGULAR or NaN). */
 emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream);
 
-/* Numerically factorise G of every topology of every scenario (LDL^T on the
- * shared symbolic pattern). Synchronises `stream` to check the pivots:
- * EMT_ESINGULAR if any pivot is non-positive or not finite. */
+/* Source: Sec. III-A, third basic process (factorising the system
+ * conductance matrix), done here once per topology that the switching
+ * events produce, before the time loop.
+ * Numerically factorise G of every topology of every scenario (LDL^T on the
+ * shared symbolic pattern). Starts a run (clears the device error flag) and
+ * synchronises `stream` to check the pivots: EMT_ESINGULAR if any pivot is
+ * non-positive or not finite. */
 emt_status emt_factor(emt_ctx *ctx, void *stream);
 
-/* Advance every scenario by n steps from the current step, writing the
- * recorded node voltages to rec_dev [S][n][R] (row j = step current+1+j;
- * columns past a scenario's n_rec are left untouched; rec_dev may be NULL to
- * record nothing). Writes checkpoints when checkpoint_every > 0.
+/* Source: Sec. III-A, the four basic processes per time step (Norton
+ * equivalents, nodal injections, and the forward/back substitution through
+ * the prefactored matrix), the layers run in order; Sec. III-B, all
+ * scenarios at once. Advance every scenario by n steps from the current
+ * step, writing the recorded node voltages to rec_dev [S][n][R] (row j =
+ * step current+1+j; columns past a scenario's n_rec are left untouched;
+ * rec_dev may be NULL to record nothing). Writes checkpoints when
+ * checkpoint_every > 0. Queues the launches on `stream` and returns without
+ * waiting for them; a split launch that gave up (EMT_EDEVICE) is reported
+ * by the next synchronising call, e.g. emt_sync.
  * Errors: EMT_ESTATE before emt_factor or past n_steps; EMT_EINVAL n < 0. */
 emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
 
-/* Latency floor of a step kernel (a measurement: Sec. IV-B and IV-C judge
- * a simulator by its average time per integration step, and the time loop
- * here is bound by its chain of dependent phases, not by bandwidth or
- * arithmetic). Runs n_steps steps of
- * a kernel with the step kernel's launch shape but no arithmetic and
+/* Not in the paper: waits for the work queued on `stream` and reports
+ * device-side failures of the current run: EMT_EDEVICE if a split launch
+ * since the last emt_factor / emt_reset / emt_set_params gave up waiting for
+ * its workgroups (its recorded outputs are then not valid). */
+emt_status emt_sync(emt_ctx *ctx, void *stream);
+
+/* Source: Sec. IV-B and IV-C (a simulator is judged by its average time per
+ * integration step). Latency floor of a step kernel, a measurement: the time
+ * loop here is bound by its chain of dependent phases, not by bandwidth or
+ * arithmetic. Runs n_steps steps of a kernel with the step kernel's launch
+ * shape but no arithmetic and
  * returns its time per step in microseconds (HIP events on `stream`, which
  * the call synchronises):
  *   EMT_FLOOR_ONE_WORKGROUP: the one-workgroup kernel's grid, workgroup
@@ -232,10 +273,16 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
 typedef enum { EMT_FLOOR_ONE_WORKGROUP = 0, EMT_FLOOR_SPLIT = 1 } emt_floor_kernel;
 emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, double *us_per_step, void *stream);
 
-/* Return every scenario to step 0 with the zero initial state. */
+/* Not in the paper (its runs start from rest): return every scenario to
+ * step 0 with the zero initial state; starts a run (clears the device error
+ * flag, discarding a give-up not yet reported). Stream-ordered. */
 emt_status emt_reset(emt_ctx *ctx, void *stream);
 
-/* Reverse-time adjoint (vector-Jacobian product) of the whole recorded
+/* Not in the paper, which has no gradients: an extension that
+ * differentiates the paper's time loop (Sec. III-A) exactly. It is the
+ * discrete adjoint of the recursion at the top of this header, with the
+ * transposed solves through the factors of emt_factor.
+ * Reverse-time adjoint (vector-Jacobian product) of the whole recorded
  * waveform: given dJ_drec_dev [S][T][R] returns grad_dev [S][P] = dJ/dtheta
  * (entries past a scenario's n_params are set to 0). Recomputes each
  * checkpoint segment, then runs transposed solves through the same factors
@@ -249,25 +296,32 @@ emt_status emt_reset(emt_ctx *ctx, void *stream);
  * Leaves the forward state at step n_steps. */
 emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream);
 
-/* Per-branch adjoints of the companion coefficients from the last
+/* Not in the paper (part of the adjoint extension above).
+ * Per-branch adjoints of the companion coefficients from the last
  * emt_adjoint, in the scenario's original branch order (host arrays of
  * n_branches, any may be NULL). Synchronises the device. */
 emt_status emt_branch_adjoints(emt_ctx *ctx, int32_t scen, double *gbar, double *betabar,
                                double *gammabar);
 
-/* Copy one scenario's current state to host: v [n_nodes], i [n_branches]
- * (original branch order; out-of-service branches read 0); either may be
- * NULL. Synchronises the device. */
+/* Source: Sec. III-A (the node voltages of the fourth basic process and the
+ * branch currents of the first). Copy one scenario's current state to
+ * host: v [n_nodes], i [n_branches] (original branch order; out-of-service
+ * branches read 0); either may be NULL. Synchronises the device;
+ * EMT_EDEVICE if a split launch of this run gave up. */
 emt_status emt_get_state(emt_ctx *ctx, int32_t scen, double *v_host, double *i_host);
 
-/* Overwrite one scenario's state at the current step from host v and i
- * (u is recomputed as A^T v - e at the current step). Synchronises. */
+/* Not in the paper (its runs start from rest; used for initial states such
+ * as a charged lossless L-C tank). Overwrite one scenario's state at the
+ * current step from host v and i (u is recomputed as A^T v - e at the
+ * current step). Synchronises. */
 emt_status emt_set_state(emt_ctx *ctx, int32_t scen, const double *v_host, const double *i_host);
 
-/* Free everything the context owns (NULL-safe). Synchronises the device. */
+/* Not in the paper: free everything the context owns (NULL-safe).
+ * Synchronises the device. */
 void emt_destroy(emt_ctx *ctx);
 
-/* Message for the last non-OK status returned on this thread. */
+/* Not in the paper: message for the last non-OK status returned on this
+ * thread. */
 const char *emt_last_error(void);
 
 #ifdef __cplusplus

@@ -45,12 +45,32 @@ class _Net(C.Structure):
 _lib = None
 
 
-def _load():
+def use_native_build() -> str:
+    """For timing the oracle on the machine it runs on: compile the same
+    source with -O3 -march=native into liboracle_native.so and route every
+    later call of this process through it. The compiler may fuse
+    multiply-adds there, so results can differ from the test build in the
+    last bits: timing only. Must come before the first oracle call."""
+    global _lib
+    if _lib is not None:
+        raise RuntimeError("use_native_build() must come before the first oracle call")
+    path = os.path.join(_HERE, "liboracle_native.so")
+    tmp = path + ".tmp"
+    subprocess.check_call(["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp",
+                           "-shared", "-fPIC", "-o", tmp, _SRC])
+    os.replace(tmp, path)
+    _load(path)
+    return path
+
+
+def _load(path=None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = C.CDLL(_LIB)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = C.CDLL(path)
         vp, i64, f64, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int32
         lib.oracle_run.argtypes = [vp, vp, f64, i64, vp, vp, vp, vp, vp, vp]
         lib.oracle_loss_complex.argtypes = [vp, vp, vp, f64, i64, vp, vp, vp]

@@ -87,6 +87,9 @@ struct emt_ctx {
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
   std::vector<std::pair<int64_t, int64_t>> split_xbuf;  // (offset, doubles per step parity) per split item
+  // give-up flag of the split launches, copied after each launch on its
+  // stream into pinned host memory and read at the synchronising calls
+  int32_t *h_err = nullptr;
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -108,6 +111,7 @@ struct emt_ctx {
   }
   ~emt_ctx() {
     for (void *p : allocs) (void)hipFree(p);
+    if (h_err) (void)hipHostFree(h_err);
   }
 };
 
@@ -917,30 +921,43 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
 
 // The split components' launch: both exchange buffers hold values whose
 // tag matches neither of the first two steps ((step / 2) mod 4 in the two
-// lowest bits, step parity choosing the buffer), the give-up flag clear and
-// the tiles' XCD record empty.
-static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st,
-                              bool floor = false) {
+// lowest bits, step parity choosing the buffer) and the tiles' XCD record is
+// empty. The give-up flag is not cleared here: it stays set from the launch
+// that gave up until the next run starts (arm_split_flag), and its copy into
+// pinned host memory follows every launch on the same stream.
+static void launch_split_with(emt_ctx &c, const emt::SplitCtx &sc, int64_t n0, int64_t ns, double *rec,
+                              hipStream_t st, bool floor) {
   for (const auto &f : c.split_xbuf)
     for (int64_t m = n0 + 1; m <= n0 + 2; ++m) {
       const int64_t stale = (((m >> 1) & 3) + 2) & 3;
-      int64_t *buf = reinterpret_cast<int64_t *>(c.sc.xbuf + f.first + (m & 1) * f.second);
+      int64_t *buf = reinterpret_cast<int64_t *>(sc.xbuf + f.first + (m & 1) * f.second);
       hip_check(emt::launch_fill_i64(buf, f.second, stale, st), "split exchange buffer");
     }
-  hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
-  hip_check(emt::launch_fill_i32(c.sc.xcc, c.n_tiles, -1, st), "split placement record");
-  hip_check(emt::launch_split(c.dc, c.sc, c.split_bpt, c.split_rpl, c.split_rt, c.split_grid, n0, ns, rec,
+  hip_check(emt::launch_fill_i32(sc.xcc, c.n_tiles, -1, st), "split placement record");
+  hip_check(emt::launch_split(c.dc, sc, c.split_bpt, c.split_rpl, c.split_rt, c.split_grid, n0, ns, rec,
                               c.split_lds, floor, st),
             floor ? "split latency floor" : "split forward");
 }
 
-// A split launch whose tiles gave up waiting leaves the error flag set.
-static void check_split(emt_ctx &c) {
+static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st,
+                              bool floor = false) {
+  launch_split_with(c, c.sc, n0, ns, rec, st, floor);
+  hip_check(hipMemcpyAsync(c.h_err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "split error flag");
+}
+
+// Clears the split give-up flag at the start of a run (factor, reset,
+// set_params), in stream order, and its pinned host copy after it.
+static void arm_split_flag(emt_ctx &c, hipStream_t st) {
   if (c.n_tiles == 0) return;
-  int32_t err = 0;
-  hip_check(hipDeviceSynchronize(), "sync");
-  hip_check(hipMemcpy(&err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost), "split error flag");
-  if (err) throw emt::Error{EMT_EDEVICE, "a split-component launch gave up waiting for its workgroups"};
+  hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
+  hip_check(hipMemcpyAsync(c.h_err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "split error flag");
+}
+
+// After a synchronisation: a split launch of this run gave up waiting for
+// its workgroups (its outputs are not valid).
+static void report_split(const emt_ctx &c) {
+  if (c.n_tiles > 0 && c.h_err && *reinterpret_cast<volatile int32_t *>(c.h_err) != 0)
+    throw emt::Error{EMT_EDEVICE, "a split-component launch gave up waiting for its workgroups"};
 }
 
 static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
@@ -979,6 +996,9 @@ emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, em
     c->sim = *sim;
     hip_check(hipGetDevice(&c->device), "hipGetDevice");
     upload_all(*c, nets);
+    hip_check(hipHostMalloc(reinterpret_cast<void **>(&c->h_err), sizeof(int32_t), hipHostMallocDefault),
+              "hipHostMalloc");
+    *c->h_err = 0;
     hip_check(emt::launch_companions(c->dc, c->ca, nullptr), "companions");
     hip_check(emt::launch_reset(c->dc, c->d_bitem, c->d_blocal, c->nbr_total, c->nodes_total, nullptr), "reset");
     hip_check(hipDeviceSynchronize(), "build");
@@ -1030,6 +1050,7 @@ emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream) {
     hip_check(emt::launch_companions(ctx->dc, ctx->ca, st), "companions");
     hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
               "reset");
+    arm_split_flag(*ctx, st);
     ctx->step = 0;
     ctx->factored = false;
     ctx->clean = true;
@@ -1042,6 +1063,7 @@ emt_status emt_factor(emt_ctx *ctx, void *stream) {
     if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hip_check(emt::launch_fill_i32(ctx->dc.flags, 1, 0, st), "clear flags");
+    arm_split_flag(*ctx, st);
     hip_check(emt::launch_factor(ctx->dc, ctx->d_pairs, ctx->n_pairs, ctx->max_tail, st), "factor");
     if (ctx->n_tiles > 0)
       hip_check(emt::launch_inverse(ctx->dc, ctx->sc, ctx->d_inv_jobs, ctx->n_inv_jobs, ctx->inverse_lds, st),
@@ -1066,10 +1088,18 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
     if (ctx->step + n > ctx->sim.n_steps) return set_error(EMT_ESTATE, "stepping past n_steps");
     if (n == 0) return EMT_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    check_split(*ctx);
     if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
     if (ctx->n_tiles > 0) launch_split_step(*ctx, ctx->step, n, rec_dev, st);
     ctx->step += n;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_sync(emt_ctx *ctx, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    hip_check(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sync");
+    report_split(*ctx);
     return EMT_OK;
   });
 }
@@ -1103,7 +1133,9 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
       hip_check(hipEventRecord(sc.e1, st), "event");
     } else if (kernel == EMT_FLOOR_SPLIT) {
       if (ctx->n_tiles == 0) return set_error(EMT_EINVAL, "no split component in this batch");
-      check_split(*ctx);
+      hip_check(hipStreamSynchronize(st), "sync");
+      report_split(*ctx);
+      arm_split_flag(*ctx, st);
       hip_check(hipEventRecord(sc.e0, st), "event");
       launch_split_step(*ctx, 0, n_steps, nullptr, st, true);
       hip_check(hipEventRecord(sc.e1, st), "event");
@@ -1113,7 +1145,7 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
     hip_check(hipEventSynchronize(sc.e1), "sync");
     float ms = 0.0f;
     hip_check(hipEventElapsedTime(&ms, sc.e0, sc.e1), "event time");
-    if (kernel == EMT_FLOOR_SPLIT) check_split(*ctx);
+    if (kernel == EMT_FLOOR_SPLIT) report_split(*ctx);
     *us_per_step = (double)ms * 1e3 / (double)n_steps;
     return EMT_OK;
   });
@@ -1125,6 +1157,7 @@ emt_status emt_reset(emt_ctx *ctx, void *stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
               "reset");
+    arm_split_flag(*ctx, st);
     ctx->step = 0;
     ctx->clean = true;
     return EMT_OK;
@@ -1190,7 +1223,7 @@ emt_status emt_get_state(emt_ctx *ctx, int32_t scen, double *v_host, double *i_h
   return guarded([&]() -> emt_status {
     if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size()) return set_error(EMT_EINVAL, "bad scenario");
     hip_check(hipDeviceSynchronize(), "sync");
-    check_split(*ctx);
+    report_split(*ctx);
     const emt::Scenario &sc = ctx->A.scens[scen];
     if (v_host) {
       std::vector<double> sv(ctx->nodes_total);

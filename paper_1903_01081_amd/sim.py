@@ -109,8 +109,14 @@ class Simulator:
                                          _stream()))
         return us.value
 
+    def sync(self):
+        """Wait for the queued work of this run and raise EMTError if the
+        device reported a failure (a split launch that gave up)."""
+        check(self.lib.emt_sync(self._ctx, _stream()))
+
     def step(self, n: int, rec: Optional[torch.Tensor] = None, record: bool = True):
-        """Advance n steps; returns rec [S, n, R] (allocated if not given)."""
+        """Advance n steps; returns rec [S, n, R] (allocated if not given).
+        Queues the work and returns; sync() waits and reports device errors."""
         if record and rec is None:
             rec = torch.zeros((self.S, n, self.R), dtype=torch.float64, device=self.device)
         ptr = _dev_ptr(rec, (self.S, n, self.R), "rec") if record else None

@@ -40,6 +40,19 @@ def test_library_exports_every_header_symbol(lib):
     assert set(lib.EXPORTS) == set(header_functions())
 
 
+def test_every_declaration_names_its_source():
+    """Each function of the boundary carries, in the comment just above it,
+    the passage of the paper it follows ("Source: Sec. ...") or says that it
+    is not in the paper."""
+    text = open(os.path.join(ROOT, "include", "emt.h")).read()
+    body = text[text.index("#ifdef __cplusplus"):]
+    for name in header_functions():
+        m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*(?:typedef[^;]*;\s*)?(?:#define[^\n]*\n\s*)?[a-z_ *]+\b" + name + r"\s*\(", body, flags=re.S)
+        assert m is not None, f"{name} has no comment"
+        comment = m.group(1)
+        assert re.search(r"Source: Sec\. [IV]+", comment) or "Not in the paper" in comment, name
+
+
 def test_destroy_null_is_safe(lib):
     lib.load().emt_destroy(None)
 

@@ -38,3 +38,19 @@ def test_algorithmic_figures_per_step():
     assert bench.algorithmic_flops_per_step(info, [10, 20]) == 10 * 100 + 2 * (100 + 400)
     assert bench.algorithmic_bytes_per_step(info, 5) == 64 * 100 + 8 * 5 + 24 * 40 + 8 * 30
     assert bench.algorithmic_bytes_per_step(info, 5, [10, 20]) == 64 * 100 + 8 * 5 + 8 * (100 + 400)
+
+
+def test_roofline_object_prices_the_method_bytes():
+    # frac = the sparse method's bytes per time step x time steps (x passes)
+    # / kernel seconds / 8 TB/s, whichever solver ran
+    info = {"total_branches": 100, "nnz_L": 40, "total_nodes": 30}
+    r = bench.roofline_object(info, 5, 1000, "k_split", 1e-3)
+    per_step = 64 * 100 + 8 * 5 + 24 * 40 + 8 * 30
+    assert r["algorithmic_bytes_per_time_step"] == per_step
+    assert abs(r["achieved"] - per_step * 1000 / 1e-3 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["traffic"] is None
+    r2 = bench.roofline_object(info, 5, 1000, "k_adjoint", 1e-3, passes=2.0, extra_bytes_per_step=32)
+    assert abs(r2["achieved"] - (per_step + 32) * 2000 / 1e-3 / 1e9) < 1e-9
+    r3 = bench.roofline_object(info, 5, 1000, "k_split", 1e-3, traffic=4e6)
+    assert abs(r3["traffic_gbs"] - 4.0) < 1e-12

@@ -51,7 +51,7 @@ def grid1000_run(request, torch_cuda):
         assert sim.info()["split_tiles"] == 96
     sim.factor()
     rec = sim.step(cfg["n_steps"])
-    torch_cuda.cuda.synchronize()
+    sim.sync()
     return nets, cfg, sim, rec, shape
 
 
@@ -160,4 +160,30 @@ def test_uneven_full_size_sampled_instances(torch_cuda, oracle_mod):
     refs = oracle_mod.run_batch([nets[s] for s in pick], cfg["dt"], cfg["n_steps"], n_threads=3)
     errs = [rel(got[q][:, :nets[s].n_rec], refs[q]) for q, s in enumerate(pick)]
     say("uneven sampled rel errs", errs, "sizes", sizes[pick])
+    assert max(errs) < TOL
+
+
+def test_grid1000_whole_horizon_vs_oracle_samples(grid1000_run):
+    """All 50,000 steps in the benchmarked launch, checked element by element
+    at the samples the oracle wrote over its own full run
+    (tests/golden/make_goldens.py): every 100th step at 64 nodes, every
+    node at steps 24,999-25,003 (the fault) and at step 50,000; error
+    relative to the largest |v| of the whole oracle trajectory."""
+    import os
+    nets, cfg, sim, rec, shape = grid1000_run
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "grid1000_samples.npz"))
+    assert int(g["n_steps"]) == cfg["n_steps"] and float(g["dt"]) == cfg["dt"]
+    r = rec[0]
+    import torch
+    steps = torch.as_tensor(g["steps"] - 1, device=r.device)
+    nodes = torch.as_tensor(g["nodes"], device=r.device)
+    got = r.index_select(0, steps).index_select(1, nodes).cpu().numpy()
+    fault = r.index_select(0, torch.as_tensor(g["fault_steps"] - 1, device=r.device)).cpu().numpy()
+    last = r[-1].cpu().numpy()
+    vmax = float(g["vmax"])
+    errs = [float(np.max(np.abs(got - g["v_steps_nodes"]))) / vmax,
+            float(np.max(np.abs(fault - g["v_fault"]))) / vmax,
+            float(np.max(np.abs(last - g["v_last"]))) / vmax]
+    say(f"grid1000 {shape} whole-horizon sampled rel errs (every 100th step x 64 nodes, fault steps, last step)",
+        errs)
     assert max(errs) < TOL

@@ -209,3 +209,25 @@ def test_split_component_too_large_for_one_xcd(torch_cuda, oracle_mod):
     if n_cu >= 256:
         assert sim.info()["split_local"] == 0
     assert rel(rec, oracle_mod.run(nets[0], cfg["dt"], 60)) < TOL
+
+
+def test_step_queues_without_host_sync(torch_cuda):
+    """emt_step on a split context only queues its launches: right after two
+    calls the stream still has work pending (host calls take microseconds,
+    the 2 x 10,000 steps take tens of milliseconds), and emt_sync then waits
+    and reports no device error."""
+    torch = torch_cuda
+    net = netgen.small_grid(43, 150, fault_step=7000, n_mon=30)
+    say("split: 3 x 150 nodes, two emt_step calls of 10,000 steps without a host sync")
+    sim = dense_sim([net], 20e-6, 20000, 32)
+    assert sim.info()["split_tiles"] > 0
+    rec = torch.empty((1, 20000, sim.R), dtype=torch.float64, device=sim.device)
+    torch.cuda.synchronize()
+    sim.step(10000, rec=rec[:, :10000])
+    sim.step(10000, rec=rec[:, 10000:])
+    pending = not torch.cuda.current_stream().query()
+    sim.sync()
+    assert pending, "emt_step waited for the device"
+    assert torch.cuda.current_stream().query()
+    assert np.all(np.isfinite(rec.cpu().numpy()))
+    sim.close()
