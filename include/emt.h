@@ -36,14 +36,15 @@
  * device memory of the current HIP device, and must stay valid until the
  * work queued on `stream` has finished. `stream` is a hipStream_t (NULL =
  * the default stream); the calls of one run go to one stream. Calls are
- * stream-ordered: emt_set_params, emt_reset and emt_step only queue work and
- * return without waiting for the device; the calls documented as
- * synchronising (emt_factor, emt_sync, emt_get_state, emt_set_state,
- * emt_branch_adjoints, emt_latency_floor, emt_destroy, emt_build, the
- * pipelined emt_adjoint, emt_info_get with split components) wait. Errors
- * found by the device during queued work (a split launch whose workgroups
- * gave up waiting for each other) are reported by the next synchronising
- * call of the same run. A context is not thread-safe. Every call returns a
+ * stream-ordered: emt_set_params, emt_factor_async, emt_reset, emt_step,
+ * emt_adjoint and emt_mismatch only queue work and return without waiting
+ * for the device (so a caller can record them into a HIP graph); the calls
+ * documented as synchronising (emt_factor, emt_sync, emt_get_state,
+ * emt_set_state, emt_branch_adjoints, emt_latency_floor, emt_destroy,
+ * emt_build, emt_info_get with split components) wait. Errors found by the
+ * device during queued work (non-positive pivots of emt_factor_async, a
+ * split launch or the pipelined adjoint whose workgroups gave up waiting for
+ * each other) are reported by emt_sync. A context is not thread-safe. Every call returns a
  * status; on a non-OK status returned before any work was queued, nothing
  * was queued, and emt_last_error() describes the cause. No C++ exception
  * crosses this interface.
@@ -232,6 +233,13 @@ emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream);
  * non-positive or not finite. */
 emt_status emt_factor(emt_ctx *ctx, void *stream);
 
+/* Source: Sec. III-A, third basic process, as emt_factor: the same
+ * factorisation, queued without waiting:
+ * the pivot check is reported by the next emt_sync (EMT_ESINGULAR; the
+ * factors are then stale again). For callers that record a whole run
+ * (parameters, factorisation, forward, adjoint) into one HIP graph. */
+emt_status emt_factor_async(emt_ctx *ctx, void *stream);
+
 /* Source: Sec. III-A, the four basic processes per time step (Norton
  * equivalents, nodal injections, and the forward/back substitution through
  * the prefactored matrix), the layers run in order; Sec. III-B, all
@@ -246,9 +254,11 @@ emt_status emt_factor(emt_ctx *ctx, void *stream);
 emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
 
 /* Not in the paper: waits for the work queued on `stream` and reports
- * device-side failures of the current run: EMT_EDEVICE if a split launch
- * since the last emt_factor / emt_reset / emt_set_params gave up waiting for
- * its workgroups (its recorded outputs are then not valid). */
+ * device-side failures of the queued work: EMT_ESINGULAR for non-positive
+ * pivots of an emt_factor_async; EMT_EDEVICE if a split launch since the
+ * last emt_factor / emt_reset / emt_set_params gave up waiting for its
+ * workgroups (its recorded outputs are then not valid) or a pipelined
+ * emt_adjoint did (its gradient is then not valid). */
 emt_status emt_sync(emt_ctx *ctx, void *stream);
 
 /* Source: Sec. IV-B and IV-C (a simulator is judged by its average time per
@@ -288,13 +298,24 @@ emt_status emt_reset(emt_ctx *ctx, void *stream);
  * checkpoint segment, then runs transposed solves through the same factors
  * backwards in time; where both fit on the device at once, a second
  * workgroup per component recomputes segment s-1 while segment s is
- * reversed (emt_info.adjoint_pipelined; the call then synchronises `stream`
- * and returns EMT_EDEVICE if a workgroup gave up waiting). dJ_drec_dev may be
+ * reversed (emt_info.adjoint_pipelined; a give-up of those workgroups is
+ * reported by emt_sync as EMT_EDEVICE; while `stream` is being captured
+ * into a HIP graph the one-workgroup kernel runs instead). Stream-ordered;
+ * bitwise the same gradient either way. dJ_drec_dev may be
  * NULL when no node is recorded (R = 0). Requires checkpoint_every > 0 and a
  * forward run of all n_steps since the last emt_set_params/emt_factor/
  * emt_reset (else EMT_ESTATE); EMT_EINVAL with split dense components.
  * Leaves the forward state at step n_steps. */
 emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev, void *stream);
+
+/* Not in the paper (part of the adjoint extension above): the waveform
+ * mismatch of a parameter-identification run. For rec_dev and target_dev
+ * [S][T][R] (device), writes dJ_drec_dev [S][T][R] = 2 (rec - target) on
+ * each scenario's n_rec recorded columns (0 on the others) and loss_dev [S]
+ * = sum over steps and recorded columns of (rec - target)^2, in a fixed
+ * order (deterministic). Stream-ordered; rec and dJ_drec may not overlap. */
+emt_status emt_mismatch(emt_ctx *ctx, const double *rec_dev, const double *target_dev, double *dJ_drec_dev,
+                        double *loss_dev, void *stream);
 
 /* Not in the paper (part of the adjoint extension above).
  * Per-branch adjoints of the companion coefficients from the last

@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "EMT_OK", 1: "EMT_EINVAL", 2: "EMT_ESINGULAR", 3: "EMT_ENOMEM
                 4: "EMT_EDEVICE", 5: "EMT_ESTATE"}
 
 # Exported functions of include/emt.h.
-EXPORTS = ("emt_build", "emt_analyze", "emt_info_get", "emt_set_params", "emt_factor",
+EXPORTS = ("emt_build", "emt_analyze", "emt_info_get", "emt_set_params", "emt_factor", "emt_factor_async",
+           "emt_mismatch",
            "emt_step", "emt_sync", "emt_reset", "emt_adjoint", "emt_branch_adjoints", "emt_get_state",
            "emt_set_state", "emt_latency_floor", "emt_destroy", "emt_last_error")
 
@@ -93,6 +94,8 @@ def load():
         "emt_info_get": [vp, vp],
         "emt_set_params": [vp, vp, vp],
         "emt_factor": [vp, vp],
+        "emt_factor_async": [vp, vp],
+        "emt_mismatch": [vp, vp, vp, vp, vp, vp],
         "emt_step": [vp, i64, vp, vp],
         "emt_sync": [vp, vp],
         "emt_reset": [vp, vp],

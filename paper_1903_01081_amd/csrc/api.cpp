@@ -64,6 +64,7 @@ struct emt_ctx {
   int64_t *d_br_ids = nullptr;
   std::vector<int64_t> scen_br_off;  // into d_br_ids
   int32_t *d_lptr = nullptr, *d_line_scen = nullptr, *d_line_id = nullptr;
+  int32_t *d_nrec = nullptr;  // recorded nodes per scenario
   int64_t *d_lent = nullptr;
   int n_lines_total = 0;
   double *d_stage = nullptr;  // staging for set_state currents
@@ -87,9 +88,11 @@ struct emt_ctx {
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
   std::vector<std::pair<int64_t, int64_t>> split_xbuf;  // (offset, doubles per step parity) per split item
-  // give-up flag of the split launches, copied after each launch on its
-  // stream into pinned host memory and read at the synchronising calls
-  int32_t *h_err = nullptr;
+  // device-side status words of queued work, read by the synchronising
+  // calls after their wait: the split give-up flag (sc.err, sticky for the
+  // run), the pivot count of an emt_factor_async (dc.flags[0]) and the
+  // pipelined adjoint's give-up flag (dc.flags[2])
+  bool pivots_pending = false, adjoint_pending = false;
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -111,7 +114,6 @@ struct emt_ctx {
   }
   ~emt_ctx() {
     for (void *p : allocs) (void)hipFree(p);
-    if (h_err) (void)hipHostFree(h_err);
   }
 };
 
@@ -897,6 +899,11 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   c.d_lent = c.upload(lent);
   c.d_line_scen = c.upload(line_scen);
   c.d_line_id = c.upload(line_id);
+  {
+    std::vector<int32_t> nrec(A.scens.size());
+    for (size_t q = 0; q < A.scens.size(); ++q) nrec[q] = A.scens[q].n_rec;
+    c.d_nrec = c.upload(nrec);
+  }
   int64_t max_scen_br = 0;
   for (size_t s = 0; s + 1 < c.scen_br_off.size(); ++s)
     max_scen_br = std::max(max_scen_br, c.scen_br_off[s + 1] - c.scen_br_off[s]);
@@ -923,8 +930,8 @@ static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec
 // tag matches neither of the first two steps ((step / 2) mod 4 in the two
 // lowest bits, step parity choosing the buffer) and the tiles' XCD record is
 // empty. The give-up flag is not cleared here: it stays set from the launch
-// that gave up until the next run starts (arm_split_flag), and its copy into
-// pinned host memory follows every launch on the same stream.
+// that gave up until the next run starts (arm_split_flag) and is read by the
+// synchronising calls.
 static void launch_split_with(emt_ctx &c, const emt::SplitCtx &sc, int64_t n0, int64_t ns, double *rec,
                               hipStream_t st, bool floor) {
   for (const auto &f : c.split_xbuf)
@@ -942,22 +949,46 @@ static void launch_split_with(emt_ctx &c, const emt::SplitCtx &sc, int64_t n0, i
 static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st,
                               bool floor = false) {
   launch_split_with(c, c.sc, n0, ns, rec, st, floor);
-  hip_check(hipMemcpyAsync(c.h_err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "split error flag");
 }
 
 // Clears the split give-up flag at the start of a run (factor, reset,
-// set_params), in stream order, and its pinned host copy after it.
+// set_params), in stream order.
 static void arm_split_flag(emt_ctx &c, hipStream_t st) {
   if (c.n_tiles == 0) return;
   hip_check(emt::launch_fill_i32(c.sc.err, 1, 0, st), "split error flag");
-  hip_check(hipMemcpyAsync(c.h_err, c.sc.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "split error flag");
 }
 
-// After a synchronisation: a split launch of this run gave up waiting for
-// its workgroups (its outputs are not valid).
+static int32_t read_flag(const int32_t *dev) {
+  int32_t v = 0;
+  hip_check(hipMemcpy(&v, dev, sizeof(int32_t), hipMemcpyDeviceToHost), "status flag");
+  return v;
+}
+
+// After the work of this run has finished: a split launch gave up waiting
+// for its workgroups (its outputs are not valid).
 static void report_split(const emt_ctx &c) {
-  if (c.n_tiles > 0 && c.h_err && *reinterpret_cast<volatile int32_t *>(c.h_err) != 0)
+  if (c.n_tiles > 0 && read_flag(c.sc.err) != 0)
     throw emt::Error{EMT_EDEVICE, "a split-component launch gave up waiting for its workgroups"};
+}
+
+// After the queued work has finished: every status word it may have set
+// (split give-up, pivots of an asynchronous factorisation, pipelined
+// adjoint give-up).
+static void report_all(emt_ctx &c) {
+  report_split(c);
+  if (c.pivots_pending) {
+    c.pivots_pending = false;
+    const int32_t bad = read_flag(c.dc.flags);
+    if (bad != 0) {
+      c.factored = false;
+      throw emt::Error{EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots"};
+    }
+  }
+  if (c.adjoint_pending) {
+    c.adjoint_pending = false;
+    if (read_flag(c.dc.flags + 2) != 0)
+      throw emt::Error{EMT_EDEVICE, "the pipelined adjoint gave up waiting for its recompute workgroups"};
+  }
 }
 
 static hipError_t launch_adjoint(emt_ctx &c, const double *dJ, hipStream_t st) {
@@ -996,9 +1027,6 @@ emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, em
     c->sim = *sim;
     hip_check(hipGetDevice(&c->device), "hipGetDevice");
     upload_all(*c, nets);
-    hip_check(hipHostMalloc(reinterpret_cast<void **>(&c->h_err), sizeof(int32_t), hipHostMallocDefault),
-              "hipHostMalloc");
-    *c->h_err = 0;
     hip_check(emt::launch_companions(c->dc, c->ca, nullptr), "companions");
     hip_check(emt::launch_reset(c->dc, c->d_bitem, c->d_blocal, c->nbr_total, c->nodes_total, nullptr), "reset");
     hip_check(hipDeviceSynchronize(), "build");
@@ -1071,11 +1099,28 @@ emt_status emt_factor(emt_ctx *ctx, void *stream) {
     int32_t bad = 0;
     hip_check(hipMemcpyAsync(&bad, ctx->dc.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag");
     hip_check(hipStreamSynchronize(st), "factor sync");
+    ctx->pivots_pending = false;
     if (bad) {
       ctx->factored = false;
       return set_error(EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots");
     }
     ctx->factored = true;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_factor_async(emt_ctx *ctx, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(emt::launch_fill_i32(ctx->dc.flags, 1, 0, st), "clear flags");
+    arm_split_flag(*ctx, st);
+    hip_check(emt::launch_factor(ctx->dc, ctx->d_pairs, ctx->n_pairs, ctx->max_tail, st), "factor");
+    if (ctx->n_tiles > 0)
+      hip_check(emt::launch_inverse(ctx->dc, ctx->sc, ctx->d_inv_jobs, ctx->n_inv_jobs, ctx->inverse_lds, st),
+                "inverse");
+    ctx->factored = true;
+    ctx->pivots_pending = true;
     return EMT_OK;
   });
 }
@@ -1095,11 +1140,24 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
   });
 }
 
+emt_status emt_mismatch(emt_ctx *ctx, const double *rec_dev, const double *target_dev, double *dJ_drec_dev,
+                        double *loss_dev, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx || !rec_dev || !target_dev || !dJ_drec_dev || !loss_dev)
+      return set_error(EMT_EINVAL, "ctx, rec, target, dJ_drec and loss are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(emt::launch_mismatch(rec_dev, target_dev, dJ_drec_dev, loss_dev, ctx->d_nrec, (int)ctx->A.scens.size(),
+                                   ctx->sim.n_steps, ctx->A.rec_stride, st),
+              "mismatch");
+    return EMT_OK;
+  });
+}
+
 emt_status emt_sync(emt_ctx *ctx, void *stream) {
   return guarded([&]() -> emt_status {
     if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
     hip_check(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sync");
-    report_split(*ctx);
+    report_all(*ctx);
     return EMT_OK;
   });
 }
@@ -1174,7 +1232,10 @@ emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (!ctx->ks_adj_ok) return set_error(EMT_EINVAL, "a connected component is too large for the adjoint kernel");
     if (ctx->n_tiles > 0) return set_error(EMT_EINVAL, "the split dense solver runs forward only");
-    if (ctx->adj_pipe) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cap), "capture status");
+    // the pipelined kernel is a cooperative launch: not recorded into graphs
+    if (ctx->adj_pipe && cap == hipStreamCaptureStatusNone) {
       emt::KernelShape ks = ctx->ks;
       ks.sm = ctx->sm_adj;
       if (!ks.sm) ks.bpt = ctx->bpt_global;
@@ -1186,10 +1247,7 @@ emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev
                     ? emt::launch_adjoint_pipe_bs256(ctx->dc, ks, ctx->d_order, n, dJ_drec_dev, ctx->d_pipe, st)
                     : emt::launch_adjoint_pipe_bs512(ctx->dc, ks, ctx->d_order, n, dJ_drec_dev, ctx->d_pipe, st),
                 "adjoint");
-      int32_t err = 0;
-      hip_check(hipStreamSynchronize(st), "adjoint sync");
-      hip_check(hipMemcpy(&err, ctx->dc.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost), "pipe error flag");
-      if (err) return set_error(EMT_EDEVICE, "the pipelined adjoint gave up waiting for its recompute workgroups");
+      ctx->adjoint_pending = true;
     } else {
       hip_check(launch_adjoint(*ctx, dJ_drec_dev, st), "adjoint");
     }

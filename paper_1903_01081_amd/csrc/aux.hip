@@ -242,6 +242,31 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   if (q < n) p[q] = v;
 }
 
+// Waveform mismatch of scenario blockIdx.x over its recorded columns:
+// dJ = 2 (rec - target) and loss = sum (rec - target)^2, summed by each
+// lane over a fixed stride and then by a fixed tree, so every run rounds
+// identically. Columns past the scenario's n_rec get dJ = 0.
+__global__ __launch_bounds__(256) void k_mismatch(const double *rec, const double *target, double *dJ, double *loss,
+                                                  const int32_t *nrec, int64_t T, int R) {
+  __shared__ double part[256];
+  const int s = blockIdx.x, nr = nrec[s];
+  const int64_t base = (int64_t)s * T * R, cnt = T * R;
+  double acc = 0.0;
+  for (int64_t q = threadIdx.x; q < cnt; q += 256) {
+    const int col = (int)(q % R);
+    const double d = col < nr ? rec[base + q] - target[base + q] : 0.0;
+    dJ[base + q] = 2.0 * d;
+    acc = acc + d * d;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[s] = part[0];
+}
+
 // State at step n from node voltages (already in c.sv_state) and branch
 // currents: u = A^T v - e(n) and i on in-service branches, 0 elsewhere.
 __global__ void k_set_state(DevCtx c, const int32_t *bitem, const int32_t *blocal, const int64_t *br_ids,
@@ -367,6 +392,13 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st) {
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_mismatch(const double *rec, const double *target, double *dJ, double *loss, const int32_t *nrec,
+                           int n_scen, int64_t T, int R, hipStream_t st) {
+  if (n_scen == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mismatch, dim3(n_scen), dim3(256), 0, st, rec, target, dJ, loss, nrec, T, R);
   return hipGetLastError();
 }
 

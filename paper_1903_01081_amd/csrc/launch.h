@@ -71,6 +71,8 @@ hipError_t launch_grad(const DevCtx &c, const int32_t *lptr, const int64_t *lent
                        const int32_t *line_id, int n_lines_total, double *grad, int P, int64_t grad_len,
                        hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_mismatch(const double *rec, const double *target, double *dJ, double *loss, const int32_t *nrec,
+                           int n_scen, int64_t T, int R, hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
 
 // Split dense components (split.hip).

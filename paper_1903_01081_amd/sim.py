@@ -98,8 +98,21 @@ class Simulator:
     def factor(self):
         check(self.lib.emt_factor(self._ctx, _stream()))
 
+    def factor_async(self):
+        """emt_factor without waiting: pivots are checked by sync()."""
+        check(self.lib.emt_factor_async(self._ctx, _stream()))
+
     def reset(self):
         check(self.lib.emt_reset(self._ctx, _stream()))
+
+    def mismatch(self, rec: torch.Tensor, target: torch.Tensor, dJ: torch.Tensor, loss: torch.Tensor):
+        """dJ = 2 (rec - target) on the recorded columns, loss[s] = sum of
+        squares (emt_mismatch); all device tensors, queued."""
+        T = self.n_steps
+        check(self.lib.emt_mismatch(self._ctx, _dev_ptr(rec, (self.S, T, self.R), "rec"),
+                                    _dev_ptr(target, (self.S, T, self.R), "target"),
+                                    _dev_ptr(dJ, (self.S, T, self.R), "dJ"),
+                                    _dev_ptr(loss, (self.S,), "loss"), _stream()))
 
     def latency_floor(self, kernel: str, n_steps: int) -> float:
         """Microseconds per step of the no-arithmetic floor of a step kernel
@@ -157,6 +170,61 @@ class Simulator:
         check(self.lib.emt_set_state(self._ctx, int(scen), v.ctypes.data, i.ctypes.data))
 
 
+class IdentificationGraph:
+    """One parameter-identification iteration of a batch recorded into a HIP
+    graph: set the line parameters, factorise (pivots checked at sync()),
+    run forward over the horizon, form the waveform mismatch against the
+    target and run the adjoint. replay() launches the whole iteration as one
+    graph; `theta` (input), `loss` [S] and `grad` [S, P] are fixed device
+    tensors the caller writes and reads between replays.
+
+    Every call in the iteration only queues kernels (no host wait, no
+    allocation, no memset nodes), which is what lets the stream be captured;
+    the pipelined adjoint is a cooperative launch and is replaced by the
+    one-workgroup adjoint inside the graph (bitwise the same gradient).
+    """
+
+    def __init__(self, sim: Simulator, target: torch.Tensor, theta: Optional[torch.Tensor] = None):
+        if sim.checkpoint_every <= 0:
+            raise ValueError("the simulator needs checkpoints for the adjoint")
+        dev = sim.device
+        T = sim.n_steps
+        self.sim = sim
+        self.theta = (theta_matrix(sim.nets, device=dev) if theta is None else theta).clone()
+        self.target = target.contiguous().clone()
+        # untouched rec columns (past a scenario's n_rec) stay zero
+        self.rec = torch.zeros((sim.S, T, sim.R), dtype=torch.float64, device=dev)
+        self.dJ = torch.zeros_like(self.rec)
+        self.loss = torch.zeros((sim.S,), dtype=torch.float64, device=dev)
+        self.grad = torch.zeros((sim.S, sim.P), dtype=torch.float64, device=dev)
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            self._iteration()          # eager, once: kernels loaded, attributes set
+            sim.sync()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        with torch.cuda.graph(self.graph, capture_error_mode="relaxed"):
+            self._iteration()
+        torch.cuda.current_stream(dev).synchronize()
+
+    def _iteration(self):
+        sim = self.sim
+        sim.set_params(self.theta)
+        sim.factor_async()
+        sim.step(sim.n_steps, rec=self.rec)
+        sim.mismatch(self.rec, self.target, self.dJ, self.loss)
+        sim.adjoint(self.dJ, grad=self.grad)
+
+    def replay(self, check_status: bool = True):
+        """Runs the iteration; with check_status, waits and raises EMTError
+        on a device-side failure (e.g. EMT_ESINGULAR)."""
+        self.graph.replay()
+        if check_status:
+            self.sim.sync()
+        return self.loss, self.grad
+
+
 def theta_matrix(nets, thetas=None, device=None) -> torch.Tensor:
     """Stacks per-scenario parameter vectors (default: nominal) into [S, P]."""
     P = max(3 * int(n.n_lines) for n in nets)
@@ -167,4 +235,4 @@ def theta_matrix(nets, thetas=None, device=None) -> torch.Tensor:
     return torch.tensor(out, dtype=torch.float64, device=device)
 
 
-__all__ = ["Simulator", "EMTError", "theta_matrix", "SOLVERS"]
+__all__ = ["Simulator", "IdentificationGraph", "EMTError", "theta_matrix", "SOLVERS"]
