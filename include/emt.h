@@ -253,6 +253,28 @@ emt_status emt_factor_async(emt_ctx *ctx, void *stream);
  * Errors: EMT_ESTATE before emt_factor or past n_steps; EMT_EINVAL n < 0. */
 emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
 
+/* Not in the paper. For callers that cannot allocate device memory while
+ * they step (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): emt_step with the split components' per-step
+ * exchange (partial voltages, give-up flag, XCD record) in the library's
+ * static exchange space, a file-scope device array of 2 MiB
+ * (EMT_STATIC_SCRATCH_BYTES) that each device holds until the process ends,
+ * instead of the context's own exchange buffer. Same arguments, results
+ * (bitwise) and stream order as emt_step; it calls no allocating routine.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other contexts, other threads) race and must
+ * be serialised by the caller. The array keeps the last call's contents;
+ * each call re-initialises what it reads (exchange tags, flag, record).
+ * The array's device address is looked up once per device, at the first
+ * call on that device, which must have the context's device current
+ * (EMT_EDEVICE otherwise).
+ * Errors: those of emt_step, and EMT_EINVAL if the context's split
+ * components need more than EMT_STATIC_SCRATCH_BYTES (e.g. one 1000-node
+ * component x 3 phases in 32-column tiles needs 1.5 MB; in 16-column tiles
+ * 3 MB). emt_info.split_local does not report calls of this entry point. */
+#define EMT_STATIC_SCRATCH_BYTES (2 * 1024 * 1024)
+emt_status emt_step_noalloc(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream);
+
 /* Not in the paper: waits for the work queued on `stream` and reports
  * device-side failures of the queued work: EMT_ESINGULAR for non-positive
  * pivots of an emt_factor_async; EMT_EDEVICE if a split launch since the

@@ -88,6 +88,7 @@ struct emt_ctx {
   int32_t *d_inv_jobs = nullptr;
   int n_inv_jobs = 0;
   std::vector<std::pair<int64_t, int64_t>> split_xbuf;  // (offset, doubles per step parity) per split item
+  int64_t xbuf_doubles = 0;                             // both parities of every split item
   // device-side status words of queued work, read by the synchronising
   // calls after their wait: the split give-up flag (sc.err, sticky for the
   // run), the pivot count of an emt_factor_async (dc.flags[0]) and the
@@ -483,6 +484,7 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   c.sc.gt = c.alloc<double>(gt_off);
   hip_check(hipMemset(c.sc.gt, 0, (size_t)gt_off * sizeof(double)), "clear inverse");
   c.sc.xbuf = c.alloc<double>(xb_off);
+  c.xbuf_doubles = xb_off;
   c.sc.err = c.dc.flags + 1;
   c.d_inv_jobs = c.upload(jobs);
   c.n_inv_jobs = (int)jobs.size() / 3;
@@ -951,6 +953,16 @@ static void launch_split_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, h
   launch_split_with(c, c.sc, n0, ns, rec, st, floor);
 }
 
+// Layout of the static exchange space for this context's split components:
+// partials at offset 0, then the give-up flag, then the XCD record (256-byte
+// aligned parts). Returns the bytes needed.
+static int64_t static_layout(const emt_ctx &c, int64_t *err_off, int64_t *xcc_off) {
+  auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+  *err_off = up(c.xbuf_doubles * 8);
+  *xcc_off = *err_off + 256;
+  return *xcc_off + up((int64_t)c.n_tiles * 4);
+}
+
 // Clears the split give-up flag at the start of a run (factor, reset,
 // set_params), in stream order.
 static void arm_split_flag(emt_ctx &c, hipStream_t st) {
@@ -1135,6 +1147,39 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
     if (ctx->n_tiles > 0) launch_split_step(*ctx, ctx->step, n, rec_dev, st);
+    ctx->step += n;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_step_noalloc(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    if (n < 0) return set_error(EMT_EINVAL, "n must be >= 0");
+    if (!ctx->factored) return set_error(EMT_ESTATE, "emt_factor has not succeeded since the last change");
+    if (ctx->step + n > ctx->sim.n_steps) return set_error(EMT_ESTATE, "stepping past n_steps");
+    int64_t err_off = 0, xcc_off = 0;
+    const int64_t need = ctx->n_tiles > 0 ? static_layout(*ctx, &err_off, &xcc_off) : 0;
+    if (need > emt::kStaticScratchBytes)
+      return set_error(EMT_EINVAL, "the split components' exchange needs " + std::to_string(need) +
+                                       " bytes; the static exchange space holds " +
+                                       std::to_string(emt::kStaticScratchBytes));
+    if (n == 0) return EMT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    if (ctx->n_tiles > 0) {
+      void *base = nullptr;
+      hip_check(emt::static_scratch_ptr(ctx->device, &base), "static scratch address");
+      char *b = static_cast<char *>(base);
+      emt::SplitCtx sc = ctx->sc;
+      sc.xbuf = reinterpret_cast<double *>(b);
+      sc.err = reinterpret_cast<int32_t *>(b + err_off);
+      sc.xcc = reinterpret_cast<int32_t *>(b + xcc_off);
+      hip_check(emt::launch_fill_i32(sc.err, 1, 0, st), "split error flag");
+      launch_split_with(*ctx, sc, ctx->step, n, rec_dev, st, false);
+      // a give-up joins the run's sticky flag
+      hip_check(emt::launch_or_flag(ctx->sc.err, sc.err, st), "split error flag");
+    }
     ctx->step += n;
     return EMT_OK;
   });

@@ -267,6 +267,10 @@ __global__ __launch_bounds__(256) void k_mismatch(const double *rec, const doubl
   if (threadIdx.x == 0) loss[s] = part[0];
 }
 
+__global__ void k_or_flag(int32_t *dst, const int32_t *src) {
+  if (threadIdx.x == 0 && src[0] != 0) dst[0] = 1;
+}
+
 // State at step n from node voltages (already in c.sv_state) and branch
 // currents: u = A^T v - e(n) and i on in-service branches, 0 elsewhere.
 __global__ void k_set_state(DevCtx c, const int32_t *bitem, const int32_t *blocal, const int64_t *br_ids,
@@ -399,6 +403,11 @@ hipError_t launch_mismatch(const double *rec, const double *target, double *dJ, 
                            int n_scen, int64_t T, int R, hipStream_t st) {
   if (n_scen == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mismatch, dim3(n_scen), dim3(256), 0, st, rec, target, dJ, loss, nrec, T, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_flag(int32_t *dst, const int32_t *src, hipStream_t st) {
+  hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, st, dst, src);
   return hipGetLastError();
 }
 

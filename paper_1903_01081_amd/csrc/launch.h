@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "device.h"
+#include "emt.h"
 
 namespace emt {
 
@@ -82,6 +83,14 @@ hipError_t launch_inverse(const DevCtx &c, const SplitCtx &s, const int32_t *job
 hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, int rt, int n_blocks, int64_t n0,
                         int64_t ns, double *rec, size_t lds, bool floor, hipStream_t st);
 hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks);
+
+// The library's static exchange space (split.hip, used by emt_step_noalloc):
+// its size and its device address on `device`, which must be the current
+// device (read once per device, then cached).
+constexpr int64_t kStaticScratchBytes = EMT_STATIC_SCRATCH_BYTES;
+hipError_t static_scratch_ptr(int device, void **ptr);
+// dst[0] = 1 if src[0] != 0 (one lane; stream-ordered)
+hipError_t launch_or_flag(int32_t *dst, const int32_t *src, hipStream_t st);
 
 // Latency floors (floor.hip; the split floor is launch_split with floor set).
 hipError_t launch_barrier_floor(int bs, int n_blocks, int phases, int64_t nsteps, size_t lds, double *out,

@@ -31,6 +31,9 @@
 // flag and ends every tile's loop instead of hanging.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "device.h"
 #include "launch.h"
 #include "step.h"
@@ -473,6 +476,36 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
       for (int q = tid; q < tl.cnt; q += BS) c.sv_state[it.node + need[q]] = x[q];
     lds_barrier();
   }
+}
+
+// Exchange space of emt_step_noalloc: the split components' partial
+// voltages, the give-up flag and the XCD record, in one file-scope device
+// array instead of the context's allocations. Each device that runs the
+// library holds its own copy until the process ends; its device address is
+// read once per device (static_scratch_ptr) and only that address is handed
+// to kernels and fills.
+__device__ __align__(256) static unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_ptr(int device, void **ptr) {
+  static std::mutex mu;
+  static std::vector<void *> ptrs;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= ptrs.size()) ptrs.resize((size_t)device + 1, nullptr);
+  if (!ptrs[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    // the host-side stand-in is not a device address: never hand it out
+    if (p == nullptr || p == static_cast<void *>(scratch)) return hipErrorInvalidSymbol;
+    ptrs[device] = p;
+  }
+  *ptr = ptrs[device];
+  return hipSuccess;
 }
 
 size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt) {
