@@ -204,6 +204,7 @@ def cpu_baselines(O):
     import concurrent.futures as cf
     from paper_1903_01081_amd import netgen
     O.use_native_build()
+    log("cpu baseline: grid1000 prefix, 1 thread")
     out = {}
     # grid1000, one thread: median of 3 runs of a 500-step prefix (one
     # factorisation each)
@@ -214,6 +215,7 @@ def cpu_baselines(O):
             "sample": f"oracle (g++ -O3 -march=native, 1 thread) on the first {k} of the 50,000 steps of the "
                       f"same 3000-node grid, factorisation included; median of 3 runs "
                       f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    log("cpu baseline: grid200 N-1 sample, 8 threads")
     # grid200 N-1, 8 threads over scenarios: 16 of the 400 scenarios (every
     # 25th) over a 3000-step prefix that includes the event at step 2500
     nets, cfg = netgen.config2()
@@ -225,6 +227,7 @@ def cpu_baselines(O):
                  "sample": f"{len(sample)} of the 400 scenarios (every 25th), first {k} of 15,000 steps "
                            f"(the event at step 2500 included), OpenMP over scenarios on {CPU_THREADS} threads; "
                            f"median of 3 runs ({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    log("cpu baseline: uneven forward + adjoint sample, 8 threads")
     # uneven batch, 8 threads over instances: forward + adjoint of 8
     # instances spread over the size range; the full batch's time is
     # predicted from a fit t = a + b n^2 (dense LU work per step) over the
@@ -315,11 +318,13 @@ def extras_n1(torch):
     from paper_1903_01081_amd.tune import tune
     out = {}
     # Batched N-1 contingencies: 400 scenarios x 600 nodes, 15,000 steps.
+    log("extras: batched N-1")
     nets, cfg, shape_b, wall, kern, roof, lat = batched_n1(torch)
     N, T = nets[0].n_nodes, cfg["n_steps"]
     batched = len(nets) * N * T / wall
     # plain per-scenario loop: every 50th scenario run alone (all scenarios
     # have the same size), median of 3 runs each, its own tuned shape
+    log("extras: per-scenario loop")
     shape_1 = tune(nets[:1], cfg["dt"], T, probe_steps=300)["shape"]
     plain_t = []
     for s in range(0, len(nets), 50):
@@ -346,6 +351,7 @@ def extras_adjoint(torch):
     out = {}
     # Adjoint: 300 nodes, 10,000 steps, checkpoint every 500 (tuned shape),
     # for the pipelined kernel and the serial one; medians of 5.
+    log("extras: adjoint")
     nets, cfg = netgen.config3()
     T, K = cfg["n_steps"], cfg["checkpoint_every"]
     shape_a = tune(nets, cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
@@ -394,6 +400,7 @@ def extras_adjoint(torch):
     out["adjoint"] = adj
     # Uneven batch: 256 networks of 90-900 nodes, forward + adjoint, tuned
     # shape; median of 3.
+    log("extras: uneven batch")
     nets, cfg = netgen.config4()
     T, K = cfg["n_steps"], cfg["checkpoint_every"]
     shape_u = tune(nets, cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
@@ -426,6 +433,7 @@ def extras_adjoint(torch):
     order = np.argsort(sizes, kind="stable")
     pick = [int(order[int(round(q * (len(nets) - 1)))]) for q in np.linspace(0, 1, 8)]
     loop_t, loop_shapes = [], []
+    log("extras: per-instance loop")
     for j in pick:
         sh = tune([nets[j]], cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
         one = Simulator([nets[j]], cfg["dt"], T, checkpoint_every=K, **sh)

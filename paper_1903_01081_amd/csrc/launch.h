@@ -47,7 +47,7 @@ hipError_t launch_adjoint_bs256(const DevCtx &, const KernelShape &, const int32
 hipError_t launch_adjoint_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                 hipStream_t);
 
-// Pipelined adjoint (two workgroups per item, cooperative launch) and its
+// Pipelined adjoint (two workgroups per item, all resident at once) and its
 // resident workgroups per compute unit.
 hipError_t launch_adjoint_pipe_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                     int32_t *, hipStream_t);

@@ -26,9 +26,10 @@
 // The host places each component's tiles on one XCD where they fit (one
 // L2 per XCD); the tiles confirm it at the start of the launch and then
 // exchange through that L2, else through device-coherent memory.
-// All tiles of a launch must be resident together: the launch is
-// cooperative, and a poll that outlasts kSpinLimit rounds sets an error
-// flag and ends every tile's loop instead of hanging.
+// All tiles of a launch must be resident together: emt_build checks that
+// the kernel's occupancy holds the whole grid at once, and a poll that
+// outlasts kSpinLimit rounds sets an error flag and ends every tile's loop
+// instead of hanging.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -533,11 +534,12 @@ hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_blocks, int64_
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  DevCtx ca = c;
-  SplitCtx sa = s;
-  void *args[] = {&ca, &sa, &n0, &ns, &rec};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(n_blocks), dim3(kSplitBS), args,
-                                    (unsigned)lds, st);
+  // an ordinary launch: emt_build has checked that the occupancy holds every
+  // workgroup at once, so on a device running nothing else they are all
+  // resident together; work of other streams that keeps one out makes the
+  // others give up after their bounded waits (error flag), never hang
+  hipLaunchKernelGGL(k, dim3(n_blocks), dim3(kSplitBS), lds, st, c, s, n0, ns, rec);
+  return hipGetLastError();
 }
 
 template <int BPT, int RPL, int RT>
