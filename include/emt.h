@@ -321,8 +321,9 @@ emt_status emt_reset(emt_ctx *ctx, void *stream);
  * backwards in time; where both fit on the device at once, a second
  * workgroup per component recomputes segment s-1 while segment s is
  * reversed (emt_info.adjoint_pipelined; a give-up of those workgroups is
- * reported by emt_sync as EMT_EDEVICE). Stream-ordered; bitwise the same
- * gradient either way. dJ_drec_dev may be
+ * reported by emt_sync as EMT_EDEVICE; while `stream` is being captured
+ * into a HIP graph the one-workgroup kernel runs instead). Stream-ordered;
+ * bitwise the same gradient either way. dJ_drec_dev may be
  * NULL when no node is recorded (R = 0). Requires checkpoint_every > 0 and a
  * forward run of all n_steps since the last emt_set_params/emt_factor/
  * emt_reset (else EMT_ESTATE); EMT_EINVAL with split dense components.

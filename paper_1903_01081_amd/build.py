@@ -26,6 +26,7 @@ SOURCES = [
     ("step.hip", "step256", ["-DEMT_BS=256"]),
     ("step.hip", "step512", ["-DEMT_BS=512"]),
     ("split.hip", "split", []),
+    ("scratch.hip", "scratch", []),
     ("floor.hip", "floor", []),
 ]
 

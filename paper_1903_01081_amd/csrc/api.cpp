@@ -629,7 +629,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   if (f_gl > (size_t)max_lds) throw Error{EMT_EINVAL, "a connected component needs more LDS than a workgroup has"};
   c.ks_adj_ok = a_gl <= (size_t)max_lds;
   // Pipelined adjoint where both workgroups of every item fit on the device
-  // at once (by the kernel's occupancy) and it was not turned off.
+  // at once (cooperative launch) and it was not turned off.
   c.adj_pipe = false;
   if (K > 0 && c.ks_adj_ok && !sim.serial_adjoint) {
     KernelShape ks = c.ks;
@@ -1277,7 +1277,10 @@ emt_status emt_adjoint(emt_ctx *ctx, const double *dJ_drec_dev, double *grad_dev
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (!ctx->ks_adj_ok) return set_error(EMT_EINVAL, "a connected component is too large for the adjoint kernel");
     if (ctx->n_tiles > 0) return set_error(EMT_EINVAL, "the split dense solver runs forward only");
-    if (ctx->adj_pipe) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cap), "capture status");
+    // the pipelined kernel is a cooperative launch: not recorded into graphs
+    if (ctx->adj_pipe && cap == hipStreamCaptureStatusNone) {
       emt::KernelShape ks = ctx->ks;
       ks.sm = ctx->sm_adj;
       if (!ks.sm) ks.bpt = ctx->bpt_global;

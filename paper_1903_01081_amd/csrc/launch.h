@@ -47,7 +47,7 @@ hipError_t launch_adjoint_bs256(const DevCtx &, const KernelShape &, const int32
 hipError_t launch_adjoint_bs512(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                 hipStream_t);
 
-// Pipelined adjoint (two workgroups per item, all resident at once) and its
+// Pipelined adjoint (two workgroups per item, cooperative launch) and its
 // resident workgroups per compute unit.
 hipError_t launch_adjoint_pipe_bs64(const DevCtx &, const KernelShape &, const int32_t *, int, const double *,
                                     int32_t *, hipStream_t);
@@ -84,7 +84,7 @@ hipError_t launch_split(const DevCtx &c, const SplitCtx &s, int bpt, int rpl, in
                         int64_t ns, double *rec, size_t lds, bool floor, hipStream_t st);
 hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks);
 
-// The library's static exchange space (split.hip, used by emt_step_noalloc):
+// The library's static exchange space (scratch.hip, used by emt_step_noalloc):
 // its size and its device address on `device`, which must be the current
 // device (read once per device, then cached).
 constexpr int64_t kStaticScratchBytes = EMT_STATIC_SCRATCH_BYTES;

@@ -26,14 +26,10 @@
 // The host places each component's tiles on one XCD where they fit (one
 // L2 per XCD); the tiles confirm it at the start of the launch and then
 // exchange through that L2, else through device-coherent memory.
-// All tiles of a launch must be resident together: emt_build checks that
-// the kernel's occupancy holds the whole grid at once, and a poll that
-// outlasts kSpinLimit rounds sets an error flag and ends every tile's loop
-// instead of hanging.
+// All tiles of a launch must be resident together: the launch is
+// cooperative, and a poll that outlasts kSpinLimit rounds sets an error
+// flag and ends every tile's loop instead of hanging.
 #include <hip/hip_runtime.h>
-
-#include <mutex>
-#include <vector>
 
 #include "device.h"
 #include "launch.h"
@@ -479,36 +475,6 @@ __global__ __launch_bounds__(kSplitBS) void k_split(DevCtx c, SplitCtx s, int64_
   }
 }
 
-// Exchange space of emt_step_noalloc: the split components' partial
-// voltages, the give-up flag and the XCD record, in one file-scope device
-// array instead of the context's allocations. Each device that runs the
-// library holds its own copy until the process ends; its device address is
-// read once per device (static_scratch_ptr) and only that address is handed
-// to kernels and fills.
-__device__ __align__(256) static unsigned char scratch[kStaticScratchBytes];
-
-hipError_t static_scratch_ptr(int device, void **ptr) {
-  static std::mutex mu;
-  static std::vector<void *> ptrs;
-  std::lock_guard<std::mutex> lock(mu);
-  if (device < 0) return hipErrorInvalidDevice;
-  if ((size_t)device >= ptrs.size()) ptrs.resize((size_t)device + 1, nullptr);
-  if (!ptrs[device]) {
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return e;
-    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
-    void *p = nullptr;
-    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-    if (e != hipSuccess) return e;
-    // the host-side stand-in is not a device address: never hand it out
-    if (p == nullptr || p == static_cast<void *>(scratch)) return hipErrorInvalidSymbol;
-    ptrs[device] = p;
-  }
-  *ptr = ptrs[device];
-  return hipSuccess;
-}
-
 size_t split_lds_bytes(int nn, int bpt, int ne, int nrec, int rt) {
   auto arr = [](size_t bytes) { return (bytes + 15) & ~(size_t)15; };
   return arr((size_t)(nn + 1) * 8) + arr((size_t)kSplitBS * bpt * 8) + arr((size_t)rt * 8) + arr((size_t)nn * 4) +
@@ -534,12 +500,11 @@ hipError_t split_launch(const DevCtx &c, const SplitCtx &s, int n_blocks, int64_
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  // an ordinary launch: emt_build has checked that the occupancy holds every
-  // workgroup at once, so on a device running nothing else they are all
-  // resident together; work of other streams that keeps one out makes the
-  // others give up after their bounded waits (error flag), never hang
-  hipLaunchKernelGGL(k, dim3(n_blocks), dim3(kSplitBS), lds, st, c, s, n0, ns, rec);
-  return hipGetLastError();
+  DevCtx ca = c;
+  SplitCtx sa = s;
+  void *args[] = {&ca, &sa, &n0, &ns, &rec};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(n_blocks), dim3(kSplitBS), args,
+                                    (unsigned)lds, st);
 }
 
 template <int BPT, int RPL, int RT>

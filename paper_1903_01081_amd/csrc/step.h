@@ -778,8 +778,7 @@ __device__ __forceinline__ void publish_flag(int32_t *flag, int32_t value) {
 }
 
 // Pipelined adjoint: two workgroups per item, resident together
-// (the occupancy holds the whole grid at once; every wait is bounded).
-// Workgroup n_items + i recomputes the segments of
+// (cooperative launch). Workgroup n_items + i recomputes the segments of
 // item order[i], last first, into two alternating segment buffers;
 // workgroup i reverses each segment as soon as it is recomputed, so the
 // recompute of segment s-1 overlaps the reversal of segment s. Per item,

@@ -42,10 +42,14 @@ hipError_t adj_pipe(const DevCtx &c, const int32_t *order, int n_items, const do
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  // an ordinary launch: the occupancy holds both workgroups of every item at
-  // once (checked by emt_build); every wait between them is bounded
-  hipLaunchKernelGGL(k, dim3(2 * n_items), dim3(EMT_BS), lds, st, c, order, n_items, dJ, pipe);
-  return hipGetLastError();
+  DevCtx ca = c;
+  const int32_t *oa = order;
+  int na = n_items;
+  const double *da = dJ;
+  int32_t *pa = pipe;
+  void *args[] = {&ca, &oa, &na, &da, &pa};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k), dim3(2 * n_items), dim3(EMT_BS), args,
+                                    (unsigned)lds, st);
 }
 
 template <int BPT, int WPT, bool SM>

@@ -179,7 +179,9 @@ class IdentificationGraph:
     tensors the caller writes and reads between replays.
 
     Every call in the iteration only queues kernels (no host wait, no
-    allocation, no memset nodes), which is what lets the stream be captured.
+    allocation, no memset nodes), which is what lets the stream be captured;
+    the pipelined adjoint is a cooperative launch and is replaced by the
+    one-workgroup adjoint inside the graph (bitwise the same gradient).
     """
 
     def __init__(self, sim: Simulator, target: torch.Tensor, theta: Optional[torch.Tensor] = None):
