@@ -470,6 +470,47 @@ def extras_adjoint(torch):
     return out
 
 
+def profile_adjoint(torch, which):
+    """The adjoint workloads in the launch shapes the tuner picks for them on
+    MI355X, without the tuner, two runs each, for a rocprofv3 kernel trace:
+    "pipelined": grid100 forward + pipelined adjoint (k_adjoint_pipe);
+    "serial": grid100 forward + one-workgroup adjoint and the uneven batch
+    forward + adjoint (k_adjoint)."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator, theta_matrix
+    out = {}
+    if which == "pipelined":
+        runs = [("grid100_pipelined", netgen.config3, dict(solver="auto", block_size=512))]
+    else:
+        runs = [("grid100_serial", netgen.config3, dict(solver="auto", block_size=512, serial_adjoint=True)),
+                ("uneven_serial", netgen.config4, dict(solver="auto", block_size=256, dense_tail=64))]
+    for name, make, shape in runs:
+        nets, cfg = make()
+        T, K = cfg["n_steps"], cfg["checkpoint_every"]
+        sim = Simulator(nets, cfg["dt"], T, checkpoint_every=K, **shape)
+        theta = theta_matrix(nets, device=sim.device)
+        rec = torch.empty((sim.S, T, sim.R), dtype=torch.float64, device=sim.device)
+        cot = torch.randn((sim.S, T, sim.R), dtype=torch.float64, device=sim.device,
+                          generator=torch.Generator(device=sim.device).manual_seed(5))
+        ts = []
+        for _ in range(2):
+            sim.set_params(theta)
+            sim.factor()
+            t0 = time.perf_counter()
+            sim.step(T, rec=rec)
+            sim.sync()
+            t1 = time.perf_counter()
+            sim.adjoint(cot)
+            sim.sync()
+            ts.append((t1 - t0, time.perf_counter() - t1))
+        out[name] = {"shape": shape, "pipelined": bool(sim.info()["adjoint_pipelined"]),
+                     "forward_s": ts[-1][0], "adjoint_s": ts[-1][1]}
+        log(name, out[name])
+        sim.close()
+        del rec, cot, theta
+    return out
+
+
 def calibrate_copy(torch, gib=1):
     """A plain device-to-device copy of a known size, run under the same
     rocprofv3 --pmc counters as the step kernel: FETCH_SIZE and WRITE_SIZE
@@ -494,6 +535,9 @@ def main():
                     help="run only the batched N-1 workload (one line; for profiling its kernel)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the adjoint workloads (one line; for profiling the adjoint kernels)")
+    ap.add_argument("--profile-adjoint", choices=["serial", "pipelined"],
+                    help="only the adjoint kernels in fixed launch shapes, two runs each (for rocprofv3): "
+                         "the one-workgroup adjoint (grid100 and the uneven batch) or the pipelined one (grid100)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -518,6 +562,8 @@ def main():
                               "roofline": roof, "latency": lat}), flush=True)
         elif args.only_adjoint:
             print(json.dumps(extras_adjoint(torch)), flush=True)
+        elif args.profile_adjoint is not None:
+            print(json.dumps(profile_adjoint(torch, args.profile_adjoint)), flush=True)
         else:
             headline(torch, args)
     finally:
