@@ -717,9 +717,13 @@ __device__ __forceinline__ void store_branch_adjoints(const DevCtx &c, const Ite
 }
 
 // Serial adjoint: one workgroup per item recomputes and reverses each
-// segment in turn, last segment first.
+// segment in turn, last segment first. With 256 lanes the register budget
+// is held to two waves per SIMD (two workgroups per compute unit), so a
+// batch of many components runs in fewer rounds than at the one wave per
+// SIMD that its largest branch-slot counts would otherwise take.
 template <int BS, int BPT, int WPT, bool SM>
-__global__ __launch_bounds__(BS) void k_adjoint(DevCtx c, const int32_t *order, const double *dJ) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS == 256 ? 2 : 1))) void k_adjoint(
+    DevCtx c, const int32_t *order, const double *dJ) {
   const ItemDesc it = c.items[order[blockIdx.x]];
   View<SM> v = make_view<BS, SM>(c, it, true);
   const int64_t nseg = (c.T + c.K - 1) / c.K;
