@@ -39,6 +39,19 @@
 //     gbar += hbar_n u_n, betabar += hbar_n i_{n-1}, gammabar += hbar_n u_{n-1}
 //   then the chain rule to the per-line parameters (R_l, L_l, C_l).
 //
+// Distributed-parameter (travelling-wave, Bergeron) lines, kind 5, between
+// nodes k and m with surge impedance Z (field R) and travel time tau (field
+// L, tau >= dt): the lossless line of the EMTP method (the paper's reference
+// [2]). Each end is a Norton equivalent to ground, g = 1/Z, whose history
+// current is the wave that left the other end tau earlier:
+//     i_k(n) = g v_k(n) + h_k(n),   h_k(n) = -w_m(t_n - tau),
+//     w_m(n) = g v_m(n) + i_m(n)    (and the same with k and m swapped),
+// i_k the current from node k into the line. t_n - tau falls between steps:
+// with tau / dt = D0 + f (0 <= f < 1), w(t_n - tau) = (1 - f) w(n - D0) +
+// f w(n - D0 - 1), and w = 0 before step 1 (the line starts at rest). The
+// branch current i of a line is i_k; its u is v_k. Lines run forward only
+// (the adjoint rejects them), take no events and no initial state.
+//
 // Everything is plain loops over dense arrays in the scalar type T (double,
 // or std::complex<double> for complex-step differentiation; pivots are chosen
 // by |Re| so that the complex run stays analytic).
@@ -56,7 +69,7 @@
 
 namespace {
 
-enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4 };
+enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4, K_LINE = 5 };
 
 }  // namespace
 
@@ -138,7 +151,7 @@ void companions(const OracleNet &net, const T *theta, double dt,
         c.gamma[b] = -g;
         break;
       }
-      default: {  // resistor or closed switch
+      default: {  // resistor, closed switch, or a line end's 1/Z
         c.g[b] = T(1) / R;
         break;
       }
@@ -228,6 +241,7 @@ void assemble(const OracleNet &net, const Companions<T> &c, std::vector<T> &G) {
     const T g = c.g[b];
     if (k >= 0) G[(size_t)k * N + k] += g;
     if (m >= 0) G[(size_t)m * N + m] += g;
+    if (net.kind[b] == K_LINE) continue;  // two Norton equivalents to ground
     if (k >= 0 && m >= 0) {
       G[(size_t)k * N + m] -= g;
       G[(size_t)m * N + k] -= g;
@@ -247,11 +261,15 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
     const int k = net.k[b], m = net.m[b];
     if (k < -1 || k >= net.n_nodes || m < -1 || m >= net.n_nodes) return false;
     if (k < 0 && m < 0) return false;
-    if (net.kind[b] < 0 || net.kind[b] > 4) return false;
+    if (net.kind[b] < 0 || net.kind[b] > 5) return false;
+    if (net.kind[b] == K_LINE &&
+        (k < 0 || m < 0 || k == m || !(net.R[b] > 0) || !(net.L[b] >= dt) || net.C[b] != 0.0 || net.line[b] >= 0))
+      return false;
   }
   for (int j = 0; j < net.n_events; ++j) {
     if (net.ev_step[j] < 1) return false;
     if (net.ev_branch[j] < 0 || net.ev_branch[j] >= net.n_branches) return false;
+    if (net.kind[net.ev_branch[j]] == K_LINE) return false;
   }
   for (int r = 0; r < net.n_rec; ++r)
     if (net.rec_nodes && (net.rec_nodes[r] < 0 || net.rec_nodes[r] >= net.n_nodes)) return false;
@@ -259,6 +277,35 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
 }
 
 inline int rec_node(const OracleNet &net, int r) { return net.rec_nodes ? net.rec_nodes[r] : r; }
+
+bool has_lines(const OracleNet &net) {
+  for (int b = 0; b < net.n_branches; ++b)
+    if (net.kind[b] == K_LINE) return true;
+  return false;
+}
+
+// The travelling waves of the lines: w[end][step] for every line, end 0 = k,
+// end 1 = m; step 0 and earlier read 0 (the line at rest).
+template <class T>
+struct Waves {
+  std::vector<int> lines;                 // branch ids of the lines
+  std::vector<std::vector<T>> w[2];       // [end][line][step]
+  double dt = 0;
+  void init(const OracleNet &net, double dt_, int64_t Tn) {
+    dt = dt_;
+    for (int b = 0; b < net.n_branches; ++b)
+      if (net.kind[b] == K_LINE) lines.push_back(b);
+    for (int e = 0; e < 2; ++e) w[e].assign(lines.size(), std::vector<T>(Tn + 1, T(0)));
+  }
+  T at(int e, size_t q, int64_t j) const { return j <= 0 ? T(0) : w[e][q][j]; }
+  // w of end e of line q at t_n - tau (linear interpolation between steps)
+  T delayed(const OracleNet &net, int e, size_t q, int64_t n) const {
+    const double D = net.L[lines[q]] / dt;
+    const int64_t D0 = (int64_t)std::floor(D);
+    const double f = D - (double)D0;
+    return (1.0 - f) * at(e, q, n - D0) + f * at(e, q, n - D0 - 1);
+  }
+};
 
 // One forward run. Optional outputs may be null. Trajectories have T+1 rows
 // (row 0 = initial state). Returns 0 on success, 1 on bad input, 2 on a
@@ -269,6 +316,7 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
             std::vector<int> *topo_of_step, std::vector<Companions<T>> *topos,
             std::vector<DenseLU<T>> *lus) {
   if (!valid(net, dt, Tn)) return 1;
+  if (has_lines(net) && (v0 || i0)) return 1;
   const int N = net.n_nodes, B = net.n_branches;
   std::vector<uint8_t> ins(B);
   for (int b = 0; b < B; ++b)
@@ -305,6 +353,9 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
   if (i_traj) std::copy(i.begin(), i.end(), i_traj);
   if (u_traj) std::copy(u.begin(), u.end(), u_traj);
 
+  Waves<T> waves;
+  waves.init(net, dt, Tn);
+
   // Events sorted by step (stable order within a step).
   std::vector<int> ev(net.n_events);
   for (int j = 0; j < net.n_events; ++j) ev[j] = j;
@@ -337,9 +388,20 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
     }
     std::fill(x.begin(), x.end(), T(0));
     for (int b = 0; b < B; ++b) {
+      if (net.kind[b] == K_LINE) continue;
       const T j = c.g[b] * e[b] - h[b];
       if (net.k[b] >= 0) x[net.k[b]] += j;
       if (net.m[b] >= 0) x[net.m[b]] -= j;
+    }
+    // lines: each end injects minus its history current (the wave that left
+    // the other end tau earlier)
+    std::vector<T> hk(waves.lines.size()), hm(waves.lines.size());
+    for (size_t q = 0; q < waves.lines.size(); ++q) {
+      const int b = waves.lines[q];
+      hk[q] = -waves.delayed(net, 1, q, n);
+      hm[q] = -waves.delayed(net, 0, q, n);
+      x[net.k[b]] -= hk[q];
+      x[net.m[b]] -= hm[q];
     }
     lu.solve(x);
     v = x;
@@ -349,10 +411,20 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
         i[b] = T(0);
         continue;
       }
+      if (net.kind[b] == K_LINE) continue;
       T vk = net.k[b] >= 0 ? v[net.k[b]] : T(0);
       T vm = net.m[b] >= 0 ? v[net.m[b]] : T(0);
       u[b] = vk - vm - e[b];
       i[b] = c.g[b] * u[b] + h[b];
+    }
+    for (size_t q = 0; q < waves.lines.size(); ++q) {
+      const int b = waves.lines[q];
+      const T g = c.g[b], vk = v[net.k[b]], vm = v[net.m[b]];
+      const T ik = g * vk + hk[q], im = g * vm + hm[q];
+      waves.w[0][q][n] = g * vk + ik;
+      waves.w[1][q][n] = g * vm + im;
+      u[b] = vk;
+      i[b] = ik;
     }
     if (rec)
       for (int r = 0; r < net.n_rec; ++r) rec[(size_t)(n - 1) * net.n_rec + r] = v[rec_node(net, r)];
@@ -403,6 +475,7 @@ int oracle_loss_complex(const OracleNet *net, const double *theta_re, const doub
 int oracle_adjoint(const OracleNet *net, const double *theta, double dt, int64_t T,
                    const double *dJ_drec, double *grad, double *gbar_out,
                    double *betabar_out, double *gammabar_out) {
+  if (has_lines(*net)) return 1;  // lines run forward only
   const int N = net->n_nodes, B = net->n_branches;
   std::vector<double> i_traj((size_t)(T + 1) * B), u_traj((size_t)(T + 1) * B);
   std::vector<int> topo_of_step;

@@ -35,8 +35,10 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-# Branch kinds; the integer codes are part of the C interface.
-RL, CAP, RES, SWITCH, SRC = 0, 1, 2, 3, 4
+# Branch kinds; the integer codes are part of the C interface. LINE is a
+# distributed-parameter (travelling-wave) line: R = surge impedance Z,
+# L = travel time tau.
+RL, CAP, RES, SWITCH, SRC, LINE = 0, 1, 2, 3, 4, 5
 
 F_HZ = 60.0
 R_SRC = 0.5          # Thevenin source resistance per phase [ohm]
@@ -169,12 +171,19 @@ def random_lines(rng: np.random.Generator, n_bus: int, n_lines: int) -> np.ndarr
 
 def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
                      n_gen: int, n_load: int, *, fault_bus: Optional[int] = None,
-                     fault_step: int = 0, rec_nodes=None, with_fault_switch=True):
+                     fault_step: int = 0, rec_nodes=None, with_fault_switch=True,
+                     travelling_wave_dt: Optional[float] = None):
     """Draw one grid. Returns (builder, bookkeeping) so callers can add events.
 
     Branch order: for each line its 3 series R-L branches, then the 3 shunt
     capacitors at its first bus, then the 3 at its second bus; then 3 source
     branches per generator, 3 load branches per load, 3 fault switches.
+
+    travelling_wave_dt: if given, every line whose travel time
+    tau = sqrt(L C) is at least this time step is drawn the same way but
+    entered as three lossless distributed-parameter lines (one per phase,
+    kind LINE, Z = sqrt(L / C), series resistance dropped) instead of
+    pi-sections; it is then not part of the parameter vector.
     """
     edges = random_lines(rng, n_bus, n_lines)
     n_nodes = 3 * n_bus
@@ -185,6 +194,11 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
         R = rng.uniform(0.01, 0.05) * km              # ohm
         L = rng.uniform(0.05, 0.2) * 1e-3 * km        # H
         C = rng.uniform(8.0, 12.0) * 1e-9 * km        # F
+        tau = math.sqrt(L * C)
+        if travelling_wave_dt is not None and tau >= travelling_wave_dt:
+            for p in range(3):
+                series[l, p] = bld.add(3 * a + p, 3 * b + p, LINE, R=math.sqrt(L / C), L=tau)
+            continue
         for p in range(3):
             series[l, p] = bld.add(3 * a + p, 3 * b + p, RL, R=R, L=L, line=l)
         for p in range(3):
@@ -338,7 +352,8 @@ def config4(seed: int = 4, n_inst: int = 256, n_steps: int = 5000,
 
 def small_grid(seed: int, n_bus: int, *, n_lines=None, n_gen=None, n_load=None,
                fault_step: Optional[int] = None, n_mon: Optional[int] = None,
-               remove_series: Optional[int] = None, remove_step: Optional[int] = None):
+               remove_series: Optional[int] = None, remove_step: Optional[int] = None,
+               travelling_wave_dt: Optional[float] = None):
     """A grid of the same recipe at an arbitrary size, for tests."""
     rng = np.random.default_rng(seed)
     if n_lines is None:
@@ -346,7 +361,8 @@ def small_grid(seed: int, n_bus: int, *, n_lines=None, n_gen=None, n_load=None,
     n_gen = max(1, int(round(0.2 * n_bus))) if n_gen is None else n_gen
     n_load = int(round(0.6 * n_bus)) if n_load is None else n_load
     bld, info = three_phase_grid(rng, n_bus, n_lines, n_gen, n_load,
-                                 with_fault_switch=fault_step is not None)
+                                 with_fault_switch=fault_step is not None,
+                                 travelling_wave_dt=travelling_wave_dt)
     events = [] if fault_step is None else _fault_events(info, fault_step)
     if remove_series is not None:
         l, p = divmod(int(remove_series), 3)

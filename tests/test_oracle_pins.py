@@ -472,3 +472,135 @@ def test_adjoint_vjp_linear_in_cotangent(oracle_mod):
     g2 = oracle_mod.adjoint(net, dt, T, d2)
     g12 = oracle_mod.adjoint(net, dt, T, 3 * d1 - d2)
     assert rel_err(g12, 3 * g1 - g2) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Distributed-parameter (travelling-wave) lines: lossless line of surge
+# impedance Z and travel time tau, each end a Norton equivalent 1/Z whose
+# history is the wave that left the other end tau earlier.
+# ---------------------------------------------------------------------------
+
+from paper_1903_01081_amd.netgen import LINE  # noqa: E402
+
+
+def _delayed(x, D):
+    """x at t_n - D dt with linear interpolation, x = 0 before step 1
+    (x[0] is step 1)."""
+    D0 = int(math.floor(D))
+    f = D - D0
+    T = x.shape[0]
+    out = np.zeros(T)
+    for n in range(1, T + 1):
+        a = x[n - D0 - 1] if n - D0 >= 1 else 0.0
+        b = x[n - D0 - 2] if n - D0 - 1 >= 1 else 0.0
+        out[n - 1] = (1 - f) * a + f * b
+    return out
+
+
+@pytest.mark.parametrize("D", [5.0, 4.3, 1.0])
+def test_line_matched_load_is_a_pure_delay(oracle_mod, D):
+    """A line terminated in its surge impedance reflects nothing: the far-end
+    voltage is the near-end voltage tau later (interpolated between steps),
+    and the near end sees a resistor Z, so its current is the R-L step of
+    the source into R_s + Z (discrete closed form)."""
+    E, Rs, Ls, Z = 1.5, 0.5, 10e-3, 80.0
+    dt, T = 20e-6, 1500
+    net = netgen.circuit(2, [
+        dict(k=0, m=-1, kind=SRC, R=Rs, L=Ls, E=E, omega=0.0, phase=0.0),
+        dict(k=0, m=1, kind=LINE, R=Z, L=D * dt),
+        dict(k=1, m=-1, kind=RES, R=Z),
+    ])
+    rec = oracle_mod.run(net, dt, T)
+    v0, v1 = rec[:, 0], rec[:, 1]
+    assert rel_err(v1, _delayed(v0, D)) < 1e-13
+    Rt = Rs + Z
+    a = dt * Rt / (2 * Ls)
+    rho = (1 - a) / (1 + a)
+    n = np.arange(1, T + 1)
+    assert rel_err(v0, Z * (E / Rt) * (1 - rho ** n)) < 1e-12
+
+
+@pytest.mark.parametrize("D", [7.0, 6.6])
+def test_line_causality_and_dc_steady_state(oracle_mod, D):
+    """Nothing reaches the far end before tau: its voltage is exactly zero
+    for the first floor(tau / dt) steps. After the waves have died out the
+    lossless line is a short circuit for DC: both ends settle at the divider
+    voltage E R_load / (R_s + R_load) (the trapezoidal rule keeps DC exact)."""
+    E, Rs, Ls, Z, Rl = 1.0, 20.0, 2e-3, 100.0, 40.0
+    dt, T = 20e-6, 20000
+    net = netgen.circuit(2, [
+        dict(k=0, m=-1, kind=SRC, R=Rs, L=Ls, E=E, omega=0.0, phase=0.0),
+        dict(k=0, m=1, kind=LINE, R=Z, L=D * dt),
+        dict(k=1, m=-1, kind=RES, R=Rl),
+    ])
+    rec = oracle_mod.run(net, dt, T)
+    D0 = int(math.floor(D))
+    assert np.all(rec[:D0, 1] == 0.0)
+    assert np.all(rec[D0:D0 + 5, 1] != 0.0)
+    assert np.all(rec[:, 0][:3] != 0.0)
+    v_dc = E * Rl / (Rs + Rl)
+    assert abs(rec[-1, 0] - v_dc) < 1e-12 * v_dc
+    assert abs(rec[-1, 1] - v_dc) < 1e-12 * v_dc
+
+
+def test_line_open_end_doubles_the_wave(oracle_mod):
+    """An open far end (only the line's own Norton equivalent there) reflects
+    the incident wave with coefficient +1: at the first arrival the far-end
+    voltage is twice the near-end voltage one travel time earlier."""
+    E, Rs, Ls, Z = 1.0, 0.5, 1e-3, 120.0
+    dt, D, T = 20e-6, 12.0, 40
+    net = netgen.circuit(2, [
+        dict(k=0, m=-1, kind=SRC, R=Rs, L=Ls, E=E, omega=0.0, phase=0.0),
+        dict(k=0, m=1, kind=LINE, R=Z, L=D * dt),
+    ])
+    rec = oracle_mod.run(net, dt, T)
+    v0, v1 = rec[:, 0], rec[:, 1]
+    n = np.arange(12, 24)  # first arrival, before the reflection gets back to the near end
+    assert rel_err(v1[n], 2.0 * v0[n - 12]) < 1e-13
+
+
+def test_line_converges_to_a_fine_pi_cascade(oracle_mod):
+    """The lossless line against the same line lumped into pi-sections (a
+    different discretisation of the same telegrapher's equations), driven by
+    a sinusoid whose wavelength is eight travel times, from zero: as the
+    cascade is refined (sections and its time step together, so that every
+    section's own travel time spans four of its steps) its far-end voltage
+    approaches the line's, about halving the difference each time."""
+    Lp, Cp, length = 1e-3, 11e-9, 60.0           # per km
+    Lt, Ct = Lp * length, Cp * length
+    Z, tau = math.sqrt(Lt / Ct), math.sqrt(Lt * Ct)
+    w = 2 * math.pi / (8 * tau)
+    E, Rs, Ls, Rl = 1.0, 30.0, 1e-4, 300.0
+    dt, T = tau / 40, 3200
+    src = dict(k=0, m=-1, kind=SRC, R=Rs, L=Ls, E=E, omega=w, phase=-math.pi / 2)
+    line = netgen.circuit(2, [src, dict(k=0, m=1, kind=LINE, R=Z, L=tau), dict(k=1, m=-1, kind=RES, R=Rl)])
+    ref = oracle_mod.run(line, dt, T)[:, 1]
+    errs = []
+    for ns in (10, 20, 40):
+        M = ns // 10
+        br = [src]
+        for s in range(ns):
+            br.append(dict(k=s, m=s + 1, kind=RL, R=0.0, L=Lt / ns))
+            br.append(dict(k=s, m=-1, kind=CAP, C=Ct / ns / 2))
+            br.append(dict(k=s + 1, m=-1, kind=CAP, C=Ct / ns / 2))
+        br.append(dict(k=ns, m=-1, kind=RES, R=Rl))
+        far = oracle_mod.run(netgen.circuit(ns + 1, br, rec_nodes=[ns]), dt / M, T * M)[M - 1::M, 0]
+        errs.append(np.sqrt(np.mean((far - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    assert errs[0] < 3e-3 and errs[2] < 6e-4, errs
+    assert 1.6 < errs[0] / errs[1] < 4.5 and 1.6 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_line_rejections(oracle_mod):
+    """Lines run forward only, from rest, with tau >= dt and no events."""
+    net = netgen.circuit(2, [
+        dict(k=0, m=-1, kind=SRC, R=1.0, L=1e-3, E=1.0, omega=0.0, phase=0.0),
+        dict(k=0, m=1, kind=LINE, R=50.0, L=3 * 20e-6),
+        dict(k=1, m=-1, kind=RES, R=50.0),
+    ])
+    oracle_mod.run(net, 20e-6, 10)
+    with pytest.raises(ValueError):
+        oracle_mod.run(net, 100e-6, 10)                       # tau < dt
+    with pytest.raises(ValueError):
+        oracle_mod.adjoint(net, 20e-6, 10, np.zeros((10, 2)))
+    with pytest.raises(ValueError):
+        oracle_mod.run(net, 20e-6, 10, v0=np.zeros(2), i0=np.zeros(3))
