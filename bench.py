@@ -305,12 +305,61 @@ def batched_n1(torch):
 
 
 def extras(torch, args):
-    """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, and
-    uneven batched gradients vs the per-instance loop; every side with its
-    own tuned launch shape, medians of repeated timings."""
+    """Batched N-1 vs the per-scenario loop, adjoint/forward ratio, uneven
+    batched gradients vs the per-instance loop, and the grid with
+    travelling-wave lines; every side with its own tuned launch shape,
+    medians of repeated timings."""
     out = extras_n1(torch)
     out.update(extras_adjoint(torch))
+    out.update(extras_lines(torch, with_cpu=not args.no_cpu))
     return out
+
+
+# per distributed-parameter line and time step: the two new waves written,
+# the four delayed ones read (the interpolation's two per end)
+LINE_BYTES_PER_STEP = 48
+LINES_WORKLOAD = ("grid1000-tw: the grid1000 draw with its 1354 lines of travel time >= one step as "
+                  "distributed-parameter lines (4062 line phases), 3000 nodes, 50000 steps at 20 us, "
+                  "three-phase fault at step 25000, all nodes recorded")
+
+
+def extras_lines(torch, with_cpu=True):
+    """The 1000-bus grid with travelling-wave lines: forward node-steps/s in
+    its tuned launch shape, roofline, latency and the oracle's rate."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator
+    from paper_1903_01081_amd.tune import tune
+    log("extras: travelling-wave lines")
+    nets, cfg = netgen.config1(travelling_wave=True)
+    net = nets[0]
+    N, T = net.n_nodes, cfg["n_steps"]
+    n_line = int(np.sum(net.kind == netgen.LINE))
+    shape = tune(nets, cfg["dt"], T, probe_steps=400)["shape"]
+    sim = Simulator(nets, cfg["dt"], T, **shape)
+    info = sim.info()
+    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    runs = [time_simulation(torch, sim, rec, 1, 1 if k == 0 else 0) for k in range(3)]
+    wall, kern = sorted(runs)[1]
+    kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
+    roof = roofline_object(info, net.n_rec, T, kernel, kern,
+                           extra_bytes_per_step=LINE_BYTES_PER_STEP * n_line)
+    lat = latency_object(sim, kernel, kern / T * 1e6, info)
+    sim.close()
+    del rec
+    out = {"workload": LINES_WORKLOAD, "value": N * T / wall, "unit": "node-steps/s", "seconds": wall,
+           "kernel_s": kern, "launch_shape": shape, "line_phases": n_line, "components": info["n_items"],
+           "nnz_L": info["nnz_L"], "roofline": roof, "latency": lat}
+    if with_cpu:
+        from oracle import oracle as O
+        O.use_native_build()
+        k = 500
+        med, ts = median_time(lambda: O.run(net, cfg["dt"], k))
+        out["cpu_baseline"] = {
+            "value": N * k / med, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (g++ -O3 -march=native, 1 thread) on the first {k} of the 50,000 steps of the "
+                      f"same grid, factorisation included; median of 3 runs "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    return {"travelling_wave_lines": out}
 
 
 def extras_n1(torch):
@@ -538,6 +587,8 @@ def main():
     ap.add_argument("--profile-adjoint", choices=["serial", "pipelined"],
                     help="only the adjoint kernels in fixed launch shapes, two runs each (for rocprofv3): "
                          "the one-workgroup adjoint (grid100 and the uneven batch) or the pipelined one (grid100)")
+    ap.add_argument("--only-lines", action="store_true",
+                    help="run only the grid with travelling-wave lines (one line; for profiling its kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -560,6 +611,8 @@ def main():
             print(json.dumps({"metric": "node-steps/s, batched N-1", "value": nsteps / wall, "unit": "node-steps/s",
                               "workload": N1_WORKLOAD, "launch_shape": shape, "seconds": wall, "kernel_s": kern,
                               "roofline": roof, "latency": lat}), flush=True)
+        elif args.only_lines:
+            print(json.dumps(extras_lines(torch, with_cpu=not args.no_cpu)), flush=True)
         elif args.only_adjoint:
             print(json.dumps(extras_adjoint(torch)), flush=True)
         elif args.profile_adjoint is not None:

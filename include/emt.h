@@ -73,7 +73,7 @@ typedef enum {
   EMT_ESTATE = 5      /* call out of order (see each call) */
 } emt_status;
 
-typedef enum { EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4 } emt_kind;
+typedef enum { EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5 } emt_kind;
 
 typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 } emt_solver;
 
@@ -82,6 +82,18 @@ typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 
  *   k, m       terminals (-1 = ground; not both -1), kind = emt_kind.
  *   R, L, C    RL: R >= 0, L > 0 (source: internal R, L); C: C > 0;
  *              R and SWITCH: R > 0 (SWITCH: closed resistance).
+ *              LINE (a lossless distributed-parameter line between two
+ *              nodes, the travelling-wave line model of the EMTP method the
+ *              paper cites as its reference [2]): R = surge impedance Z > 0,
+ *              L = travel time tau >= dt, C = 0. Each end is a Norton
+ *              equivalent 1/Z to ground whose history current is the wave
+ *              that left the other end tau earlier (linear interpolation
+ *              between steps; the line starts at rest). The branch current
+ *              is the current from node k into the line. Lines take no
+ *              events and belong to no pi-section (line = -1); a batch with
+ *              lines runs forward only (EMT_EINVAL with checkpoint_every >
+ *              0 or with components split over workgroups) and takes no
+ *              emt_set_state.
  *   E, omega, phase  source EMF E cos(omega t + phase); read for EMT_SRC only.
  *   line       pi-section line index l of the branch, or -1. Line parameters
  *              theta[3l + {0,1,2}] = (R_l, L_l, C_l) are the series R and L

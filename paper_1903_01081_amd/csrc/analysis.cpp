@@ -41,7 +41,7 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (k < -1 || k >= n.n_nodes || m < -1 || m >= n.n_nodes)
       fail(EMT_EINVAL, where(s, "branch terminal out of range", b));
     if (k == m) fail(EMT_EINVAL, where(s, "branch with both terminals equal (or both ground)", b));
-    if (kd < EMT_RL || kd > EMT_SRC) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
+    if (kd < EMT_RL || kd > EMT_LINE) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
     const double R = n.R[b], L = n.L[b], C = n.C[b];
     switch (kd) {
       case EMT_RL:
@@ -57,6 +57,13 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
       case EMT_C:
         if (!finite(C) || !(C > 0)) fail(EMT_EINVAL, where(s, "capacitor needs C > 0", b));
         break;
+      case EMT_LINE:
+        if (k < 0 || m < 0) fail(EMT_EINVAL, where(s, "a line joins two nodes (neither end at ground)", b));
+        if (!finite(R) || !(R > 0)) fail(EMT_EINVAL, where(s, "a line needs its surge impedance R > 0", b));
+        if (!finite(L) || !(L >= sim.dt))
+          fail(EMT_EINVAL, where(s, "a line needs its travel time L >= dt", b));
+        if (C != 0.0) fail(EMT_EINVAL, where(s, "a line's C must be 0 (lossless)", b));
+        break;
       default:
         if (!finite(R) || !(R > 0)) fail(EMT_EINVAL, where(s, "resistor/switch needs R > 0", b));
     }
@@ -65,6 +72,8 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (l >= 0 && kd == EMT_SRC) fail(EMT_EINVAL, where(s, "a source cannot belong to a line", b));
     if (l >= 0 && kd != EMT_RL && kd != EMT_C)
       fail(EMT_EINVAL, where(s, "only R-L and C branches can belong to a line", b));
+    if (kd == EMT_LINE && sim.checkpoint_every > 0)
+      fail(EMT_EINVAL, where(s, "distributed-parameter lines run forward only (no checkpoints)", b));
   }
   if (n.n_events < 0) fail(EMT_EINVAL, where(s, "n_events < 0"));
   if (n.n_events > 0 && (!n.ev_step || !n.ev_branch || !n.ev_in_service))
@@ -74,6 +83,8 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (n.ev_branch[j] < 0 || n.ev_branch[j] >= n.n_branches)
       fail(EMT_EINVAL, where(s, "event branch out of range", j));
     if (n.ev_in_service[j] > 1) fail(EMT_EINVAL, where(s, "ev_in_service must be 0 or 1", j));
+    if (n.kind[n.ev_branch[j]] == EMT_LINE)
+      fail(EMT_EINVAL, where(s, "distributed-parameter lines take no switching events", j));
   }
   if (n.rec_nodes) {
     if (n.n_rec < 0) fail(EMT_EINVAL, where(s, "n_rec < 0"));
@@ -83,7 +94,6 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
   } else if (n.n_rec != 0 && n.n_rec != n.n_nodes) {
     fail(EMT_EINVAL, where(s, "rec_nodes == NULL requires n_rec == n_nodes (or 0)"));
   }
-  (void)sim;
 }
 
 struct DSU {
@@ -400,6 +410,11 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       for (int b = 0; b < B; ++b) {
         if (!sc.ins[t][b]) continue;
         const int k = net.k[b] < 0 ? N : net.k[b], m = net.m[b] < 0 ? N : net.m[b];
+        if (net.kind[b] == EMT_LINE) {  // each end a Norton equivalent to ground
+          d.join(k, N);
+          d.join(m, N);
+          continue;
+        }
         d.join(k, m);
       }
       for (int v = 0; v < N; ++v)
@@ -434,7 +449,7 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       for (int v : nodes) key.push_back(v);
       std::vector<std::pair<int, int>> edges;
       for (int b = 0; b < B; ++b) {
-        if (!ever[b] || net.k[b] < 0 || net.m[b] < 0) continue;
+        if (!ever[b] || net.k[b] < 0 || net.m[b] < 0 || net.kind[b] == EMT_LINE) continue;
         if (d.find(net.k[b]) != kv.first) continue;
         int a = canon[net.k[b]], c = canon[net.m[b]];
         if (a > c) std::swap(a, c);
@@ -485,7 +500,17 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       }
       it_.n_src = (int)srcs.size();
       it_.br = srcs;
-      it_.br.insert(it_.br.end(), rest.begin(), rest.end());
+      // a line is two local branches: its k end, then its m end
+      std::vector<int> line_end;  // per local branch: 0, 1 = k end, 2 = m end
+      line_end.assign(srcs.size(), 0);
+      for (int b : rest) {
+        it_.br.push_back(b);
+        line_end.push_back(net.kind[b] == EMT_LINE ? 1 : 0);
+        if (net.kind[b] == EMT_LINE) {
+          it_.br.push_back(b);
+          line_end.push_back(2);
+        }
+      }
       it_.n_br = (int)it_.br.size();
       it_.n_br_real = it_.n_br;
       it_.bk.resize(it_.n_br);
@@ -493,6 +518,24 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       it_.gpos.assign(it_.n_br, -1);
       for (int j = 0; j < it_.n_br; ++j) {
         const int b = it_.br[j];
+        if (line_end[j]) {
+          const int node = line_end[j] == 1 ? net.k[b] : net.m[b];
+          it_.bk[j] = sc.node_local[node];
+          it_.bm[j] = -1;
+          if (line_end[j] == 1) {
+            sc.br_item[b] = item_id;
+            sc.br_local[b] = j;
+            const double D = net.L[b] / sim.dt;
+            const int D0 = (int)std::floor(D);
+            it_.line_bk.push_back(j);
+            it_.line_bm.push_back(j + 1);
+            it_.line_nk.push_back(sc.node_local[net.k[b]]);
+            it_.line_nm.push_back(sc.node_local[net.m[b]]);
+            it_.line_d0.push_back(D0);
+            it_.line_f.push_back(D - (double)D0);
+          }
+          continue;
+        }
         it_.bk[j] = net.k[b] >= 0 ? sc.node_local[net.k[b]] : -1;
         it_.bm[j] = net.m[b] >= 0 ? sc.node_local[net.m[b]] : -1;
         sc.br_item[b] = item_id;

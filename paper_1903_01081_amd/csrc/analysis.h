@@ -77,6 +77,12 @@ struct Item {
   std::vector<int> nptr, nent;  // node CSR of incident branch ends: (local branch << 1) | (end is m)
   std::vector<int> gpos;    // per local branch: CSR entry of L for its off-diagonal, -1 if none
   std::vector<int> rec_node, rec_col;  // recorded local node and its output column
+  // distributed-parameter lines: each is two local branches (its k end and
+  // its m end, Norton equivalents to ground) whose histories come from each
+  // other's travelling waves; per line its two local branches and nodes and
+  // its delay tau / dt = D0 + f
+  std::vector<int> line_bk, line_bm, line_nk, line_nm, line_d0;
+  std::vector<double> line_f;
 };
 
 struct Scenario {

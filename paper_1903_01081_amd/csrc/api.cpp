@@ -94,6 +94,7 @@ struct emt_ctx {
   // run), the pivot count of an emt_factor_async (dc.flags[0]) and the
   // pipelined adjoint's give-up flag (dc.flags[2])
   bool pivots_pending = false, adjoint_pending = false;
+  int64_t ring_doubles = 0;  // wave rings of the distributed-parameter lines
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -171,8 +172,10 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
       // ground terminals point at the node slot n, which holds 0
       const uint32_t k = it.bk[j] >= 0 ? (uint32_t)it.bk[j] : (uint32_t)it.n;
       const uint32_t m = it.bm[j] >= 0 ? (uint32_t)it.bm[j] : (uint32_t)it.n;
-      const uint32_t cls = (kind == EMT_RL || kind == EMT_SRC) ? emt::GAMMA_PLUS_G
-                           : (kind == EMT_C ? emt::GAMMA_MINUS_G : emt::GAMMA_ZERO);
+      const uint32_t cls = (kind == EMT_RL || kind == EMT_SRC)
+                               ? emt::GAMMA_PLUS_G
+                               : (kind == EMT_C ? emt::GAMMA_MINUS_G
+                                                : (kind == EMT_LINE ? emt::GAMMA_LINE : emt::GAMMA_ZERO));
       bpack.push_back(k | (m << 15) | (cls << 30));
     }
   }
@@ -513,6 +516,9 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
       throw Error{EMT_EINVAL, "a connected component has more than 32766 nodes"};
     if (it.n_br > 32767) throw Error{EMT_EINVAL, "a connected component has more than 32767 branches"};
     if (sim.solver == EMT_SOLVER_DENSE && it.n > tail_max(512)) {
+      if (!it.line_bk.empty())
+        throw Error{EMT_EINVAL, "components with distributed-parameter lines run in one workgroup; the dense "
+                                "solver would split one of " + std::to_string(it.n) + " nodes"};
       c.is_split[q] = 1;
       continue;
     }
@@ -720,6 +726,9 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<int32_t> bk, bm, bgpos, bscen, bitem, blocal, nptr, rptr;
   std::vector<uint16_t> nent, rnode, rcolumn;
   int64_t coef_off = 0, fac_off = 0, dfac_off = 0, sv_off = 0, w_off = 0, ck_off = 0, seg_off = 0, node_off = 0;
+  std::vector<LineDesc> line_tab;
+  std::vector<double> line_gf;
+  int64_t ring_off = 0;
   std::vector<int64_t> ca_coef, ca_br;
   std::vector<int32_t> ca_nbr, ca_prefix;
   int64_t work = 0;
@@ -752,6 +761,25 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.topo = scen_topo_off[it.scen];
     d.ck = ck_off;
     d.seg = seg_off;
+    d.n_lines = (int32_t)it.line_bk.size();
+    d.lines = (int64_t)line_tab.size();
+    for (size_t l = 0; l < it.line_bk.size(); ++l) {
+      const int b = it.br[it.line_bk[l]];
+      LineDesc ld{};
+      ld.bk = it.line_bk[l];
+      ld.bm = it.line_bm[l];
+      ld.nk = it.line_nk[l];
+      ld.nm = it.line_nm[l];
+      ld.d0 = it.line_d0[l];
+      int32_t len = 1;  // ring length: a power of two holding steps n - D0 - 1 .. n
+      while (len < ld.d0 + 2) len *= 2;
+      ld.mask = len - 1;
+      ld.ring = ring_off;
+      ring_off += 2 * (int64_t)len;
+      line_tab.push_back(ld);
+      line_gf.push_back(1.0 / nets[it.scen].R[b]);
+      line_gf.push_back(it.line_f[l]);
+    }
     c.items[q] = d;
     coef_off += (int64_t)sc.n_topo * it.n_br;
     fac_off += (int64_t)sc.n_topo * S.nnz();
@@ -879,6 +907,10 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.seg_i = K > 0 ? c.alloc<double>(seg_off) : nullptr;
   dc.seg_u = K > 0 ? c.alloc<double>(seg_off) : nullptr;
   if (c.adj_pipe) c.d_pipe = c.alloc<int32_t>(2 * (size_t)NI);
+  dc.line_tab = line_tab.empty() ? nullptr : c.upload(line_tab);
+  dc.line_gf = line_gf.empty() ? nullptr : c.upload(line_gf);
+  dc.ring = ring_off > 0 ? c.alloc<double>(ring_off) : nullptr;
+  c.ring_doubles = ring_off;
   dc.flags = c.alloc<int32_t>(4);
   hip_check(launch_fill_i32(dc.flags, 4, 0, nullptr), "clear flags");
   dc.dt = sim.dt;
@@ -1040,7 +1072,7 @@ emt_status emt_build(const emt_net *nets, int32_t n_scen, const emt_sim *sim, em
     hip_check(hipGetDevice(&c->device), "hipGetDevice");
     upload_all(*c, nets);
     hip_check(emt::launch_companions(c->dc, c->ca, nullptr), "companions");
-    hip_check(emt::launch_reset(c->dc, c->d_bitem, c->d_blocal, c->nbr_total, c->nodes_total, nullptr), "reset");
+    hip_check(emt::launch_reset(c->dc, c->d_bitem, c->d_blocal, c->nbr_total, c->nodes_total, c->ring_doubles, nullptr), "reset");
     hip_check(hipDeviceSynchronize(), "build");
     *out = c.release();
     return EMT_OK;
@@ -1088,7 +1120,7 @@ emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream) {
     hip_check(emt::launch_set_params(ctx->dc, theta_dev, ctx->A.param_stride, ctx->d_bscen, ctx->nbr_total, st),
               "set_params");
     hip_check(emt::launch_companions(ctx->dc, ctx->ca, st), "companions");
-    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
+    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, ctx->ring_doubles, st),
               "reset");
     arm_split_flag(*ctx, st);
     ctx->step = 0;
@@ -1258,7 +1290,7 @@ emt_status emt_reset(emt_ctx *ctx, void *stream) {
   return guarded([&]() -> emt_status {
     if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, st),
+    hip_check(emt::launch_reset(ctx->dc, ctx->d_bitem, ctx->d_blocal, ctx->nbr_total, ctx->nodes_total, ctx->ring_doubles, st),
               "reset");
     arm_split_flag(*ctx, st);
     ctx->step = 0;
@@ -1349,6 +1381,9 @@ emt_status emt_set_state(emt_ctx *ctx, int32_t scen, const double *v_host, const
     if (!ctx || scen < 0 || scen >= (int)ctx->A.scens.size() || !v_host || !i_host)
       return set_error(EMT_EINVAL, "bad arguments");
     const emt::Scenario &sc = ctx->A.scens[scen];
+    for (int q : sc.items)
+      if (!ctx->A.items[q].line_bk.empty())
+        return set_error(EMT_EINVAL, "a scenario with distributed-parameter lines starts from rest (no set_state)");
     for (int a = 0; a < sc.n_nodes; ++a)
       if (!std::isfinite(v_host[a])) return set_error(EMT_EINVAL, "non-finite voltage");
     for (int b = 0; b < sc.n_branches; ++b)

@@ -363,10 +363,13 @@ hipError_t launch_set_params(const DevCtx &c, const double *theta, int P, const 
 }
 
 hipError_t launch_reset(const DevCtx &c, const int32_t *bitem, const int32_t *blocal, int64_t nbr_total,
-                        int64_t n_nodes_total, hipStream_t st) {
+                        int64_t n_nodes_total, int64_t ring_doubles, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(blocks(nbr_total, 256)), dim3(256), 0, st, c, bitem, blocal, nbr_total);
   hipLaunchKernelGGL(k_fill_f64, dim3(blocks(n_nodes_total, 256)), dim3(256), 0, st, c.sv_state, n_nodes_total,
                      0.0);
+  // travelling-wave histories: every line starts at rest
+  if (ring_doubles > 0)
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks(ring_doubles, 256)), dim3(256), 0, st, c.ring, ring_doubles, 0.0);
   return hipGetLastError();
 }
 

@@ -8,15 +8,17 @@
 
 namespace emt {
 
-enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4 };
+enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4, KIND_LINE = 5 };
 
 // Packed branch descriptor for the step kernels: local terminals in 15 bits
 // each (a grounded terminal holds the node count n: the step kernels keep a
 // zero at x[n]) and the history-coefficient class in 2 bits: gamma = g (R-L
-// and sources), -g (capacitors) or 0 (resistors, switches).
+// and sources), -g (capacitors) or 0 (resistors, switches), or a line end
+// (gamma = beta = 0; its history comes from the other end's travelling wave,
+// written into its injection by the line pass, not by the branch update).
 constexpr uint32_t kTermGround = 0x7FFF;  // mask of one packed terminal
 constexpr int kMaxItemNodes = 0x7FFF;
-enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2 };
+enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2, GAMMA_LINE = 3 };
 
 // Symbolic factor and sweep plan (shared by isomorphic items). Offsets index
 // DevCtx::symi (int32) or DevCtx::symh (uint16).
@@ -38,7 +40,7 @@ struct SymDesc {
 };
 
 struct ItemDesc {
-  int32_t scen, sym, n, n_br, n_src, n_topo, n_rec, pad0;
+  int32_t scen, sym, n, n_br, n_src, n_topo, n_rec, n_lines;
   int64_t br;    // per-branch arrays
   int64_t coef;  // coefficient arrays [n_topo][n_br] (g, beta, in-service)
   int64_t nptr;  // node CSR pointers [n+1] (int32); also recorded-node pointers rptr
@@ -52,6 +54,16 @@ struct ItemDesc {
   int64_t topo;  // scenario topology start steps [n_topo]
   int64_t ck;    // checkpoints (i, u) [n_ck][n_br]
   int64_t seg;   // adjoint segment buffer (i, u) [K+1][n_br]
+  int64_t lines; // distributed-parameter lines: first entry of line_tab / line_gf
+};
+
+// One distributed-parameter line: its two local branches (k end, m end),
+// their local nodes, the integer part D0 of tau / dt and the offset of its
+// two wave rings (k end, then m end) in DevCtx::ring. Each ring holds
+// mask + 1 doubles, a power of two >= D0 + 2; step n's wave sits at n & mask.
+struct LineDesc {
+  int32_t bk, bm, nk, nm, d0, mask;
+  int64_t ring;
 };
 
 // Components too large for one workgroup's dense tail, solved with their
@@ -139,6 +151,11 @@ struct DevCtx {
   int64_t T;
   int32_t K;
   int32_t rec_stride;
+  // distributed-parameter lines (ItemDesc::lines + q): descriptor, (1/Z,
+  // fractional delay f) pairs, and the wave rings
+  const LineDesc *line_tab;
+  const double *line_gf;
+  double *ring;
 };
 
 }  // namespace emt

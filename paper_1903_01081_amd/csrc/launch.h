@@ -64,7 +64,7 @@ hipError_t launch_companions(const DevCtx &c, const CompanionArgs &a, hipStream_
 hipError_t launch_set_params(const DevCtx &c, const double *theta, int P, const int32_t *bscen,
                              int64_t nbr_total, hipStream_t st);
 hipError_t launch_reset(const DevCtx &c, const int32_t *bitem, const int32_t *blocal, int64_t nbr_total,
-                        int64_t n_nodes_total, hipStream_t st);
+                        int64_t n_nodes_total, int64_t ring_doubles, hipStream_t st);
 hipError_t launch_set_state(const DevCtx &c, const int32_t *bitem, const int32_t *blocal,
                             const int64_t *br_ids, int64_t b0, int64_t nb, const double *i_in, int64_t n,
                             hipStream_t st);

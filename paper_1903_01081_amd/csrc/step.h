@@ -487,9 +487,12 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
   for (int j = 0; j < BPT; ++j) {
     const int b = tid + j * BS;
     const uint32_t pk = L.pk[j];
+    // a line end's history is its injection in every slot (no source there),
+    // and the line pass, not this update, writes its next injection
+    const bool line = (pk >> 30) == GAMMA_LINE;
     const double vk = v.x[pk & kTermGround], vm = v.x[(pk >> 15) & kTermGround];
     const double e = j == 0 ? L.e0 : 0.0;
-    const double h = j == 0 ? L.h0 : -v.J[b];
+    const double h = (j == 0 && !line) ? L.h0 : -v.J[b];
     const double u = (L.g[j] != 0.0) ? (vk - vm) - e : 0.0;
     const double i = L.g[j] * u + h;
     if (st_i) {
@@ -507,12 +510,42 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
     const double hn = L.be[j] * i + gamma_of(pk, L.g[j]) * u;
     if (j == 0) {
       L.h0 = hn;
-      if (inj) v.J[b] = L.g[j] * e_next - hn;
-    } else if (inj) {
+      if (inj && !line) v.J[b] = L.g[j] * e_next - hn;
+    } else if (inj && !line) {
       v.J[b] = -hn;
     }
   }
   L.e0 = e_next;
+}
+
+// Distributed-parameter lines, one lane per line. Each end is a Norton
+// equivalent to ground (1/Z) whose history current is the wave that left the
+// other end tau = (D0 + f) dt earlier: h_k(n) = -[(1 - f) w_m(n - D0) +
+// f w_m(n - D0 - 1)], w = g v + i, i = g v + h, w = 0 up to step 0 (the line
+// starts at rest). With advance set, the waves of step n are formed from the
+// solution (v.x) and the ends' injections J = -h of step n, stored, and the
+// injections of step n + 1 written; otherwise only those of step n.
+template <int BS, bool SM>
+__device__ __forceinline__ void line_pass(const DevCtx &c, const ItemDesc &it, const View<SM> &v, int64_t n,
+                                          bool advance) {
+  for (int q = lane_id(); q < it.n_lines; q += BS) {
+    const LineDesc ld = c.line_tab[it.lines + q];
+    const double g = c.line_gf[2 * (it.lines + q)], f = c.line_gf[2 * (it.lines + q) + 1];
+    double *rk = c.ring + ld.ring, *rm = rk + (ld.mask + 1);
+    int64_t m = n;
+    if (advance) {
+      const double vk = v.x[ld.nk], vm = v.x[ld.nm];
+      const double ik = g * vk - v.J[ld.bk], im = g * vm - v.J[ld.bm];
+      rk[n & ld.mask] = g * vk + ik;
+      rm[n & ld.mask] = g * vm + im;
+      m = n + 1;
+    }
+    const int64_t j0 = m - ld.d0, j1 = j0 - 1;
+    const double k0 = j0 > 0 ? rk[j0 & ld.mask] : 0.0, k1 = j1 > 0 ? rk[j1 & ld.mask] : 0.0;
+    const double m0 = j0 > 0 ? rm[j0 & ld.mask] : 0.0, m1 = j1 > 0 ? rm[j1 & ld.mask] : 0.0;
+    v.J[ld.bk] = (1.0 - f) * m0 + f * m1;
+    v.J[ld.bm] = (1.0 - f) * k0 + f * k1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -534,6 +567,11 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   select_factor<BS, WPT, SM>(c, it, v, t, w);
   inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
+  const bool lines = it.n_lines > 0;
+  if (lines) {
+    line_pass<BS, SM>(c, it, v, n0 + 1, false);
+    lds_barrier();
+  }
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
   for (int64_t n = n0 + 1; n <= n_end; ++n) {
@@ -556,6 +594,10 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
     }
     update_inject<BS, BPT, SM>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
                                n < n_end, n);
+    if (lines) {
+      lds_barrier();
+      line_pass<BS, SM>(c, it, v, n, true);
+    }
     if (sw) {
       ++t;
       next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;

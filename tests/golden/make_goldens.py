@@ -5,12 +5,17 @@ method's arithmetic); nothing here runs or reads the HIP library.
 
     python tests/golden/make_goldens.py grid1000   # ~10 min, one core
     python tests/golden/make_goldens.py grid100fd  # ~1 min, one core
+    python tests/golden/make_goldens.py grid1000tw # ~10 min, one core
 
 grid1000_samples.npz: the 1000-bus grid (3000 nodes, 50,000 steps at 20 us,
 three-phase fault at step 25,000, every node recorded) over its whole
 horizon, sampled: every 100th step at 64 seeded nodes, every node at steps
 24,999-25,003 (the fault) and at step 50,000, plus max |v| over all steps
 and nodes (the scale of the relative tolerance).
+
+grid1000_tw_samples.npz: the same grid and samples with every line whose
+travel time is at least one step entered as a distributed-parameter
+(travelling-wave) line.
 
 grid100_fd.npz: central differences of the loss J = sum (v - v_target)^2 of
 the 100-bus adjoint workload (300 nodes, 10,000 steps at 50 us, 30 monitored
@@ -32,8 +37,8 @@ from oracle import oracle as O  # noqa: E402
 from paper_1903_01081_amd import netgen  # noqa: E402
 
 
-def grid1000():
-    nets, cfg = netgen.config1()
+def grid1000(travelling_wave=False):
+    nets, cfg = netgen.config1(travelling_wave=travelling_wave)
     net = nets[0]
     T = cfg["n_steps"]
     rng = np.random.default_rng(12345)
@@ -43,8 +48,9 @@ def grid1000():
     t0 = time.time()
     rec = O.run(net, cfg["dt"], T)                          # [T][n_nodes], row j = step j+1
     print(f"oracle run {time.time() - t0:.0f} s", flush=True)
+    name = "grid1000_tw_samples.npz" if travelling_wave else "grid1000_samples.npz"
     np.savez_compressed(
-        os.path.join(HERE, "grid1000_samples.npz"),
+        os.path.join(HERE, name),
         nodes=nodes, steps=steps, v_steps_nodes=rec[np.ix_(steps - 1, nodes)],
         fault_steps=fault, v_fault=rec[fault - 1], v_last=rec[T - 1],
         vmax=np.array(np.max(np.abs(rec))), dt=np.array(cfg["dt"]), n_steps=np.array(T))
@@ -76,6 +82,7 @@ def grid100fd(h=1e-6):
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["grid1000", "grid100fd"]
+    which = sys.argv[1:] or ["grid1000", "grid100fd", "grid1000tw"]
     for w in which:
-        {"grid1000": grid1000, "grid100fd": grid100fd}[w]()
+        {"grid1000": grid1000, "grid100fd": grid100fd,
+         "grid1000tw": lambda: grid1000(travelling_wave=True)}[w]()
