@@ -558,19 +558,23 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   c.ks.bpt = bpt;
   c.ks.dmax = tail_max(bs);
   // Pad every item's branch list to whole lane slots with inert branches, so
-  // the step kernels need no per-slot bounds; sources must fit slot 0.
-  for (Item &it : A.items) {
-    if (c.is_split[&it - &A.items[0]]) continue;
-    if (it.n_src > bs)
-      throw Error{EMT_EINVAL, "a connected component has more sources (" + std::to_string(it.n_src) +
-                                  ") than lanes (" + std::to_string(bs) + ")"};
-    const int pad = bs * bpt;
-    it.br.resize(pad, -1);
-    it.bk.resize(pad, -1);
-    it.bm.resize(pad, -1);
-    it.gpos.resize(pad, -1);
-    it.n_br = pad;
-  }
+  // the step kernels need no per-slot bounds (each runs exactly bs * bpt
+  // slots); sources must fit slot 0.
+  auto pad_items = [&]() {
+    for (Item &it : A.items) {
+      if (c.is_split[&it - &A.items[0]]) continue;
+      if (it.n_src > bs)
+        throw Error{EMT_EINVAL, "a connected component has more sources (" + std::to_string(it.n_src) +
+                                    ") than lanes (" + std::to_string(bs) + ")"};
+      const int pad = bs * bpt;
+      it.br.resize(pad, -1);
+      it.bk.resize(pad, -1);
+      it.bm.resize(pad, -1);
+      it.gpos.resize(pad, -1);
+      it.n_br = pad;
+    }
+  };
+  pad_items();
 
   // Sweep plans. SPARSE: level-scheduled sweeps only; DENSE: the whole
   // component is the dense tail (it must fit one workgroup's tail); AUTO:
@@ -611,25 +615,44 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   }
   size_t f_sm = 0, a_sm = 0, f_gl = 0, a_gl = 0;
   int wpt = 1;
-  for (const Item &it : A.items) {
-    if (c.is_split[&it - &A.items[0]]) continue;
-    const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym]);
-    f_sm = std::max(f_sm, lds_bytes(sh, true, false));
-    a_sm = std::max(a_sm, lds_bytes(sh, true, true));
-    f_gl = std::max(f_gl, lds_bytes(sh, false, false));
-    a_gl = std::max(a_gl, lds_bytes(sh, false, true));
-    const int d = plans[it.sym].d;
-    if (d > 0) wpt = std::max(wpt, (d + tpr_of(d, bs) - 1) / tpr_of(d, bs));
-    if (plans[it.sym].nsv() > 65535) throw Error{EMT_EINVAL, "a connected component's factor is too large"};
+  auto lds_figures = [&]() {
+    f_sm = a_sm = f_gl = a_gl = 0;
+    wpt = 1;
+    for (const Item &it : A.items) {
+      if (c.is_split[&it - &A.items[0]]) continue;
+      const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym]);
+      f_sm = std::max(f_sm, lds_bytes(sh, true, false));
+      a_sm = std::max(a_sm, lds_bytes(sh, true, true));
+      f_gl = std::max(f_gl, lds_bytes(sh, false, false));
+      a_gl = std::max(a_gl, lds_bytes(sh, false, true));
+      const int d = plans[it.sym].d;
+      if (d > 0) wpt = std::max(wpt, (d + tpr_of(d, bs) - 1) / tpr_of(d, bs));
+      if (plans[it.sym].nsv() > 65535) throw Error{EMT_EINVAL, "a connected component's factor is too large"};
+    }
+    c.sm_fwd = f_sm <= (size_t)max_lds && !sim.sweep_from_global;
+    c.sm_adj = a_sm <= (size_t)max_lds && !sim.sweep_from_global;
+  };
+  lds_figures();
+  if (!c.sm_fwd || !c.sm_adj) {
+    // The global-memory variants exist for 4, 8 and 16 branches per lane and
+    // run every one of those slots: items padded for fewer (1, 2, 6, 12)
+    // are padded again to the global variant's count, which every kernel
+    // (LDS-staged ones too) then uses, and the LDS figures are retaken.
+    const int bg = bpt <= 4 ? 4 : (bpt <= 8 ? 8 : 16);
+    if (bg != bpt) {
+      bpt = bg;
+      c.ks.bpt = bpt;
+      pad_items();
+      lds_figures();
+    }
+    c.bpt_global = bpt;
   }
+  // every step kernel runs exactly bs * ks.bpt branch slots per item
+  for (const Item &it : A.items)
+    if (!c.is_split[&it - &A.items[0]] && it.n_br != bs * c.ks.bpt)
+      throw Error{EMT_EDEVICE, "internal: an item's branch padding differs from the step kernels' slots"};
   c.ks.wpt = wpt <= 4 ? 4 : (wpt <= 16 ? 16 : 32);
   if (wpt > 32 || (wpt > 16 && bs < 512)) throw Error{EMT_EINVAL, "internal: dense tail too large for the block size"};
-  c.sm_fwd = f_sm <= (size_t)max_lds && !sim.sweep_from_global;
-  c.sm_adj = a_sm <= (size_t)max_lds && !sim.sweep_from_global;
-  if (!c.sm_fwd || !c.sm_adj) {
-    // the global-memory variants exist for 4, 8 and 16 branches per lane
-    c.bpt_global = bpt <= 4 ? 4 : (bpt <= 8 ? 8 : 16);
-  }
   c.ks.lds_fwd = c.sm_fwd ? f_sm : f_gl;
   c.ks.lds_adj = c.sm_adj ? a_sm : a_gl;
   if (f_gl > (size_t)max_lds) throw Error{EMT_EINVAL, "a connected component needs more LDS than a workgroup has"};
