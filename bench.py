@@ -484,6 +484,7 @@ def extras_adjoint(torch):
     loop_t, loop_shapes = [], []
     log("extras: per-instance loop")
     for j in pick:
+        log(f"  instance {j} ({sizes[j]} nodes): tuning")
         sh = tune([nets[j]], cfg["dt"], T, checkpoint_every=K, probe_steps=300)["shape"]
         one = Simulator([nets[j]], cfg["dt"], T, checkpoint_every=K, **sh)
         th1 = theta_matrix([nets[j]], device=one.device)

@@ -158,7 +158,12 @@ typedef struct {
  *     through the L2 of their XCD when all of them run on one XCD (the
  *     library places each component on one XCD where its workgroups fit;
  *     they check where they run at the start of every launch). Results are
- *     bitwise the same either way. */
+ *     bitwise the same either way.
+ *   pack_nodes: 0 = one work item (workgroup) per connected component; > 0 =
+ *     a scenario's components are packed, largest first, into work items of
+ *     at most pack_nodes nodes (a larger component stays alone), so small
+ *     components share a workgroup and its lanes (their G is block-diagonal
+ *     within the item). At most 128 with the dense solver. */
 typedef struct {
   double dt;
   int64_t n_steps;
@@ -170,6 +175,7 @@ typedef struct {
   int32_t sweep_from_global;
   int32_t serial_adjoint;
   int32_t split_device_scope;
+  int32_t pack_nodes;
 } emt_sim;
 
 /* Sizes of a built context (emt_info) or of a host-only analysis. */

@@ -53,7 +53,8 @@ class EmtSim(C.Structure):
                 ("checkpoint_every", C.c_int32), ("solver", C.c_int32),
                 ("block_size", C.c_int32), ("split_cols", C.c_int32),
                 ("dense_tail", C.c_int32), ("sweep_from_global", C.c_int32),
-                ("serial_adjoint", C.c_int32), ("split_device_scope", C.c_int32)]
+                ("serial_adjoint", C.c_int32), ("split_device_scope", C.c_int32),
+                ("pack_nodes", C.c_int32)]
 
 
 class EmtInfo(C.Structure):
@@ -167,17 +168,17 @@ class PackedNets:
 
 
 def make_sim(dt, n_steps, checkpoint_every=0, solver=0, block_size=0, split_cols=0, dense_tail=-1,
-             sweep_from_global=0, serial_adjoint=0, split_device_scope=0) -> EmtSim:
+             sweep_from_global=0, serial_adjoint=0, split_device_scope=0, pack_nodes=0) -> EmtSim:
     return EmtSim(float(dt), int(n_steps), int(checkpoint_every), int(solver), int(block_size),
                   int(split_cols), int(dense_tail), int(sweep_from_global), int(serial_adjoint),
-                  int(split_device_scope))
+                  int(split_device_scope), int(pack_nodes))
 
 
-def analyze(nets, dt, n_steps, checkpoint_every=0, solver=0) -> dict:
+def analyze(nets, dt, n_steps, checkpoint_every=0, solver=0, pack_nodes=0) -> dict:
     """Host-only validation and analysis (no device needed)."""
     lib = load()
     P = PackedNets(nets)
-    sim = make_sim(dt, n_steps, checkpoint_every, solver)
+    sim = make_sim(dt, n_steps, checkpoint_every, solver, pack_nodes=pack_nodes)
     info = EmtInfo()
     check(lib.emt_analyze(P.ref, P.n, C.addressof(sim), C.addressof(info)))
     return info.as_dict()

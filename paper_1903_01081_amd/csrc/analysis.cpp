@@ -368,6 +368,9 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
   if (sim.serial_adjoint != 0 && sim.serial_adjoint != 1) fail(EMT_EINVAL, "serial_adjoint must be 0 or 1");
   if (sim.split_device_scope != 0 && sim.split_device_scope != 1)
     fail(EMT_EINVAL, "split_device_scope must be 0 or 1");
+  if (sim.pack_nodes < 0 || sim.pack_nodes > 32766) fail(EMT_EINVAL, "pack_nodes must be 0..32766");
+  if (sim.pack_nodes > 128 && sim.solver == EMT_SOLVER_DENSE)
+    fail(EMT_EINVAL, "the dense solver packs components into work items of at most 128 nodes");
 
   Analysis A;
   std::map<std::vector<int64_t>, std::pair<int, std::vector<int>>> sym_cache;  // key -> (sym, perm)
@@ -430,8 +433,33 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
     DSU d(N);
     for (int b = 0; b < B; ++b)
       if (ever[b] && net.k[b] >= 0 && net.m[b] >= 0) d.join(net.k[b], net.m[b]);
-    std::map<int, std::vector<int>> comps;  // root -> sorted nodes
-    for (int v = 0; v < N; ++v) comps[d.find(v)].push_back(v);
+    // Work items: one per component, or with packing, components packed
+    // first-fit by decreasing size into items of at most pack_nodes nodes
+    // (a larger component stays alone). An item's G is then block-diagonal.
+    std::map<int, int> comp_size;
+    for (int v = 0; v < N; ++v) comp_size[d.find(v)]++;
+    std::map<int, int> bundle;  // component root -> item key (the root of its first component)
+    if (sim.pack_nodes > 0) {
+      std::vector<std::pair<int, int>> by_size;  // (-size, root): largest first, ties by root
+      for (auto &kv : comp_size) by_size.push_back({-kv.second, kv.first});
+      std::sort(by_size.begin(), by_size.end());
+      std::vector<std::pair<int, int>> bins;  // (key, nodes)
+      for (auto &e : by_size) {
+        const int sz = -e.first;
+        size_t q = 0;
+        while (q < bins.size() && bins[q].second + sz > sim.pack_nodes) ++q;
+        if (q == bins.size()) bins.push_back({e.second, 0});
+        bins[q].second += sz;
+        bundle[e.second] = bins[q].first;
+      }
+    } else {
+      for (auto &kv : comp_size) bundle[kv.first] = kv.first;
+    }
+    std::vector<int> key_of(N);
+    for (int v = 0; v < N; ++v) key_of[v] = bundle[d.find(v)];
+    auto item_key = [&](int node) { return key_of[node]; };
+    std::map<int, std::vector<int>> comps;  // item key -> sorted nodes
+    for (int v = 0; v < N; ++v) comps[item_key(v)].push_back(v);
 
     sc.node_item.assign(N, -1);
     sc.node_local.assign(N, -1);
@@ -450,7 +478,7 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       std::vector<std::pair<int, int>> edges;
       for (int b = 0; b < B; ++b) {
         if (!ever[b] || net.k[b] < 0 || net.m[b] < 0 || net.kind[b] == EMT_LINE) continue;
-        if (d.find(net.k[b]) != kv.first) continue;
+        if (item_key(net.k[b]) != kv.first) continue;
         int a = canon[net.k[b]], c = canon[net.m[b]];
         if (a > c) std::swap(a, c);
         edges.push_back({a, c});
@@ -495,7 +523,7 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       for (int b = 0; b < B; ++b) {
         if (!ever[b]) continue;
         const int term = net.k[b] >= 0 ? net.k[b] : net.m[b];
-        if (d.find(term) != kv.first) continue;
+        if (item_key(term) != kv.first) continue;
         (net.kind[b] == EMT_SRC ? srcs : rest).push_back(b);
       }
       it_.n_src = (int)srcs.size();

@@ -8,7 +8,9 @@ The choices (all fields of emt_sim, see include/emt.h):
   * solver "sparse" (sweeps only);
   * solver "dense": components up to 128 nodes with their inverse in one
     workgroup, larger ones split by columns over 16- or 32-column
-    workgroups (forward only, so skipped when checkpoints are asked for).
+    workgroups (forward only, so skipped when checkpoints are asked for);
+  * "auto" with a scenario's small components packed into shared
+    workgroups (pack_nodes 256 or 512), where that changes the work items.
 Every candidate factorises and runs the same prefix of `probe_steps` steps
 (recorded like the real run) twice; the second run's factorisation time
 plus n_steps times its time per step ranks it, so a long horizon is not
@@ -41,7 +43,24 @@ def candidates(checkpoint_every: int = 0) -> List[dict]:
         c += [dict(solver="dense", split_cols=k) for k in (16, 32)]
     else:
         c.append(dict(solver="dense"))
+    # small components packed into shared workgroups (kept only where the
+    # packing changes the batch's work items)
+    c += [dict(solver="auto", pack_nodes=p) for p in PACK_BUDGETS]
+    c += [dict(solver="auto", block_size=256, dense_tail=64, pack_nodes=p) for p in PACK_BUDGETS]
     return c
+
+
+PACK_BUDGETS = (256, 512)
+
+
+def _packing_changes_items(nets, dt, n_steps, checkpoint_every, shape) -> bool:
+    from . import _lib
+    p = shape.get("pack_nodes", 0)
+    if p <= 0:
+        return True
+    a = _lib.analyze(nets, dt, n_steps, checkpoint_every, pack_nodes=p)
+    b = _lib.analyze(nets, dt, n_steps, checkpoint_every)
+    return a["n_items"] != b["n_items"]
 
 
 def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
@@ -81,6 +100,8 @@ def tune(nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0, pro
     "trials": [...]}."""
     trials = []
     for shape in (shapes if shapes is not None else candidates(checkpoint_every)):
+        if shapes is None and not _packing_changes_items(nets, dt, n_steps, checkpoint_every, shape):
+            continue
         try:
             t_fac, t_step, info = _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device)
             trials.append(dict(shape=shape, s_per_step=t_step, factor_s=t_fac,

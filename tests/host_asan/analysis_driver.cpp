@@ -137,6 +137,14 @@ int main(int argc, char **argv) {
     std::snprintf(label, sizeof label, "dense_tail %d", d);
     if (run(label, views, s) != 0) bad = 1;
   }
+  for (int p : {64, 256, 30000}) {
+    emt_sim s = base;
+    s.pack_nodes = p;
+    char label[64];
+    std::snprintf(label, sizeof label, "pack_nodes %d", p);
+    const int st = run(label, views, s);
+    if (st != 0 && st != EMT_EINVAL) bad = 1;
+  }
   // invalid inputs are reported, not crashed on
   {
     std::vector<Net> broken = nets;

@@ -150,7 +150,14 @@ def test_pipelined_adjoint_equals_serial_bitwise(torch_cuda, oracle_mod, K):
     assert grad_err(grads[False][:net.n_params], ref, net.theta0()) < 1e-6
 
 
-def test_uneven_full_size_adjoint_tuned_shape(torch_cuda, oracle_mod):
+# the shape the tuner picks for the uneven batch on MI355X (small grids'
+# phase components packed into shared workgroups), and the same unpacked
+UNEVEN_SHAPES = [dict(solver="auto", block_size=256, dense_tail=64, pack_nodes=256),
+                 dict(solver="auto", block_size=256, dense_tail=64)]
+
+
+@pytest.mark.parametrize("shape", UNEVEN_SHAPES, ids=["packed256", "unpacked"])
+def test_uneven_full_size_adjoint_tuned_shape(torch_cuda, oracle_mod, shape):
     """The benchmarked uneven batch at full size (256 grids of 90-900 nodes,
     5000 steps, fault at step 2500, checkpoint every 500) in the launch shape
     the tuner picks for it on MI355X, as bench.py times it; the smallest,
@@ -161,8 +168,6 @@ def test_uneven_full_size_adjoint_tuned_shape(torch_cuda, oracle_mod):
     from paper_1903_01081_amd.sim import Simulator, theta_matrix
     nets, cfg = netgen.config4()
     dt, T, K = cfg["dt"], cfg["n_steps"], cfg["checkpoint_every"]
-    # the shape the tuner picked for this batch on MI355X
-    shape = dict(solver="auto", block_size=256, dense_tail=64)
     say("uneven full-size adjoint: 256 grids, 5000 steps, K=500, shape", shape)
     sim = Simulator(nets, dt, T, checkpoint_every=K, **shape)
     sim.set_params(theta_matrix(nets, device=sim.device))

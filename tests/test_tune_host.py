@@ -16,3 +16,15 @@ def test_candidates_skip_split_widths_with_checkpoints():
     # default dense shape is tried (the library rejects it if it would split)
     c = candidates(500)
     assert [s for s in c if s["solver"] == "dense"] == [dict(solver="dense")]
+
+
+def test_packing_candidates_only_where_they_change_the_items():
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.tune import PACK_BUDGETS, _packing_changes_items
+    assert any(s.get("pack_nodes", 0) in PACK_BUDGETS for s in candidates(0))
+    big, cfg = netgen.config1(n_bus=400, n_steps=10)      # three 400-node phases
+    small, cfg4 = netgen.config4(n_inst=4, n_steps=10)
+    shape = dict(solver="auto", pack_nodes=256)
+    assert not _packing_changes_items(big, cfg["dt"], 10, 0, shape)
+    assert _packing_changes_items(small, cfg4["dt"], 10, 0, shape)
+    assert _packing_changes_items(big, cfg["dt"], 10, 0, dict(solver="auto"))
