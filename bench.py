@@ -469,6 +469,14 @@ def extras_adjoint(torch):
 
     run_batch()
     t_b, ts_b = median_time(run_batch)
+    # the same iteration (set_params, factorisation, forward, mismatch
+    # against a target, adjoint) captured once as a HIP graph and replayed
+    from paper_1903_01081_amd.sim import IdentificationGraph
+    log("  uneven batch: captured iteration")
+    graph = IdentificationGraph(sim, torch.zeros_like(rec), theta)
+    graph.replay()
+    t_g, ts_g = median_time(graph.replay)
+    del graph
     kname = "k_adjoint_pipe" if info["adjoint_pipelined"] else "k_adjoint"
     roof = roofline_object(info, sum(n.n_rec for n in nets), T, f"k_forward + {kname}", t_b, passes=3.0,
                            extra_bytes_per_step=32 * info["total_branches"])
@@ -511,6 +519,9 @@ def extras_adjoint(torch):
         "workload": "256 grids of 90-900 nodes, 5000 steps at 50 us, forward + adjoint",
         "launch_shape": shape_u, "pipelined": bool(info["adjoint_pipelined"]), "adjoint_kernel": kname,
         "gradients_per_s": len(nets) / t_b, "seconds": t_b, "timings": ts_b, "roofline": roof, "latency": lat,
+        "graph_gradients_per_s": len(nets) / t_g, "graph_seconds": t_g, "graph_timings": ts_g,
+        "graph": "one identification iteration (set_params, factorisation, forward, mismatch, adjoint) "
+                 "captured as one HIP graph, replayed; median of 3",
         "per_instance_loop_gradients_per_s": len(nets) / loop_total,
         "loop_sample": f"{len(pick)} instances spread over the size range "
                        f"({', '.join(str(int(sizes[j])) for j in pick)} nodes), each with its own tuned shape, "
