@@ -165,6 +165,10 @@ struct DenseLU {
   int n = 0;
   std::vector<T> a;
   std::vector<int> piv;
+  // pivot on |Re| (complex step: the imaginary parts are perturbations) or,
+  // for genuinely complex systems, on the modulus
+  bool by_modulus = false;
+  double mag(const T &x) const { return by_modulus ? std::abs(x) : std::fabs(re(x)); }
 
   bool factor(const std::vector<T> &G, int n_) {
     n = n_;
@@ -172,9 +176,9 @@ struct DenseLU {
     piv.resize(n);
     for (int j = 0; j < n; ++j) {
       int p = j;
-      double best = std::fabs(re(a[(size_t)j * n + j]));
+      double best = mag(a[(size_t)j * n + j]);
       for (int i = j + 1; i < n; ++i) {
-        double v = std::fabs(re(a[(size_t)i * n + j]));
+        double v = mag(a[(size_t)i * n + j]);
         if (v > best) {
           best = v;
           p = i;
@@ -435,9 +439,87 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
   return 0;
 }
 
+// Sinusoidal steady state of the initial topology (not in the paper: the
+// usual start of an EMTP-type run). With every source at one angular
+// frequency w, the companion recursion i_n = g u_n + h_n, h_{n+1} = beta i_n
+// + gamma u_n, u_n = A^T v_n - e_n has the periodic solution x_n = Re(X z^n)
+// with z = exp(j w dt): each branch acts as the discrete admittance
+// y = (g z + gamma) / (z - beta), the node phasors solve (A y A^T) V = A y E
+// with E_b = E_b exp(j phase_b) on sources, and the state at step 0 is
+// v_0 = Re V, u_0 = Re U, i_0 = Re(y U), U = A^T V - E. A network without
+// sources rests at zero. Returns 0, 1 (bad input: distributed-parameter
+// lines, sources at different frequencies) or 2 (singular).
+int steady_state(const OracleNet &net, const double *theta, double dt, double *v0, double *i0, double *Vre,
+                 double *Vim) {
+  if (!valid(net, dt, 1) || has_lines(net)) return 1;
+  const int N = net.n_nodes, B = net.n_branches;
+  double w = 0.0;
+  bool any = false;
+  for (int b = 0; b < B; ++b) {
+    if (net.kind[b] != K_SRC) continue;
+    if (any && net.omega[b] != w) return 1;
+    w = net.omega[b];
+    any = true;
+  }
+  std::vector<cplx> V(N, cplx(0.0, 0.0));
+  std::vector<uint8_t> ins(B);
+  for (int b = 0; b < B; ++b)
+    ins[b] = net.in_service0 ? net.in_service0[b] : (net.kind[b] == K_SWITCH ? 0 : 1);
+  Companions<double> c;
+  companions(net, theta, dt, ins, c);
+  const cplx z = std::polar(1.0, w * dt);
+  std::vector<cplx> y(B, cplx(0.0, 0.0)), E(B, cplx(0.0, 0.0));
+  for (int b = 0; b < B; ++b) {
+    if (!ins[b]) continue;
+    y[b] = (c.g[b] * z + c.gamma[b]) / (z - c.beta[b]);
+    if (net.kind[b] == K_SRC) E[b] = std::polar(net.E[b], net.phase[b]);
+  }
+  if (any) {
+    std::vector<cplx> Y((size_t)N * N, cplx(0.0, 0.0));
+    for (int b = 0; b < B; ++b) {
+      const int k = net.k[b], m = net.m[b];
+      if (k >= 0) {
+        Y[(size_t)k * N + k] += y[b];
+        V[k] += y[b] * E[b];
+      }
+      if (m >= 0) {
+        Y[(size_t)m * N + m] += y[b];
+        V[m] -= y[b] * E[b];
+      }
+      if (k >= 0 && m >= 0) {
+        Y[(size_t)k * N + m] -= y[b];
+        Y[(size_t)m * N + k] -= y[b];
+      }
+    }
+    DenseLU<cplx> lu;
+    lu.by_modulus = true;
+    if (!lu.factor(Y, N)) return 2;
+    lu.solve(V);
+  }
+  for (int a = 0; a < N; ++a) {
+    if (v0) v0[a] = V[a].real();
+    if (Vre) Vre[a] = V[a].real();
+    if (Vim) Vim[a] = V[a].imag();
+  }
+  if (i0)
+    for (int b = 0; b < B; ++b) {
+      const cplx vk = net.k[b] >= 0 ? V[net.k[b]] : cplx(0.0, 0.0);
+      const cplx vm = net.m[b] >= 0 ? V[net.m[b]] : cplx(0.0, 0.0);
+      i0[b] = (y[b] * (vk - vm - E[b])).real();
+    }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Steady state of the initial topology: v0 [N], i0 [B] (the state at step
+// 0 for oracle_run) and the node phasors V (all nullable).
+int oracle_steady_state(const OracleNet *net, const double *theta, double dt, double *v0, double *i0,
+                        double *V_re, double *V_im) {
+  return steady_state(*net, theta, dt, v0, i0, V_re, V_im);
+}
 
 // Forward run in double. rec: [T][n_rec]. Trajectories (nullable): [T+1][N]
 // node voltages, [T+1][B] branch currents and passive-branch voltages.

@@ -79,9 +79,10 @@ def _load(path=None):
         lib.oracle_assemble.argtypes = [vp, vp, f64, vp, vp]
         lib.oracle_companions.argtypes = [vp, vp, f64, vp, vp, vp, vp]
         lib.oracle_lu_solve.argtypes = [i32, vp, vp, vp, i32]
+        lib.oracle_steady_state.argtypes = [vp, vp, f64, vp, vp, vp, vp]
         for f in ("oracle_run", "oracle_loss_complex", "oracle_adjoint", "oracle_run_batch",
                   "oracle_assemble", "oracle_companions", "oracle_lu_solve",
-                  "oracle_max_threads"):
+                  "oracle_max_threads", "oracle_steady_state"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
     return _lib
@@ -163,6 +164,24 @@ def run(net, dt: float, n_steps: int, theta=None, v0=None, i0=None, trajectories
                         _ptr(vt), _ptr(it), _ptr(ut))
     _check(st, "oracle_run")
     return (rec, vt, it, ut) if trajectories else rec
+
+
+def steady_state(net, dt: float, theta=None):
+    """Sinusoidal steady state of the initial topology under the sources'
+    common frequency (the trapezoidal recursion's own periodic solution).
+    Returns (v0 [N], i0 [B], V [N] complex node phasors): run(net, dt, T,
+    v0=v0, i0=i0) then gives v_n = Re(V exp(j w n dt)) until the first
+    event."""
+    lib = _load()
+    P = _Packed(net)
+    th = _theta(theta, P.n_params)
+    v0 = np.empty(P.n_nodes)
+    i0 = np.empty(P.n_branches)
+    vr = np.empty(P.n_nodes)
+    vi = np.empty(P.n_nodes)
+    st = lib.oracle_steady_state(P.ref, _ptr(th), float(dt), _ptr(v0), _ptr(i0), _ptr(vr), _ptr(vi))
+    _check(st, "oracle_steady_state")
+    return v0, i0, vr + 1j * vi
 
 
 def run_batch(nets, dt: float, n_steps: int, thetas=None, n_threads: int = 0):

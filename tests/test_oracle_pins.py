@@ -604,3 +604,94 @@ def test_line_rejections(oracle_mod):
         oracle_mod.adjoint(net, 20e-6, 10, np.zeros((10, 2)))
     with pytest.raises(ValueError):
         oracle_mod.run(net, 20e-6, 10, v0=np.zeros(2), i0=np.zeros(3))
+
+
+# ---------------------------------------------------------------------------
+# Sinusoidal steady state of the initial topology (the usual start of an
+# EMTP-type run; not in the paper).
+# ---------------------------------------------------------------------------
+
+def _source_omega(net):
+    return float(net.omega[net.kind == SRC][0])
+
+
+@pytest.mark.parametrize("seed,n_bus,dt", [(5, 10, 50e-6), (9, 25, 20e-6)])
+def test_steady_state_is_the_recursions_periodic_solution(oracle_mod, seed, n_bus, dt):
+    # started from it, the trapezoidal recursion stays on x_n = Re(V z^n),
+    # z = exp(j w dt), at every node for thousands of steps (an open fault
+    # switch included); a wrong branch admittance would start a transient
+    net = netgen.small_grid(seed, n_bus, fault_step=None)
+    v0, i0, V = oracle_mod.steady_state(net, dt)
+    T = 3000
+    rec, vt, it, _ = oracle_mod.run(net, dt, T, v0=v0, i0=i0, trajectories=True)
+    z = np.exp(1j * _source_omega(net) * dt * np.arange(T + 1))
+    ref = (V[None, :] * z[:, None]).real
+    assert np.max(np.abs(vt - ref)) <= 1e-11 * np.max(np.abs(ref))
+    # and the branch currents are periodic too: i_{n+1} + i_{n-1} = 2 cos(w dt) i_n
+    c = math.cos(_source_omega(net) * dt)
+    resid = it[2:] + it[:-2] - 2.0 * c * it[1:-1]
+    assert np.max(np.abs(resid)) <= 1e-10 * np.max(np.abs(it))
+
+
+def _continuous_phasors(net):
+    # the continuous-time phasor solution: R + j w L, j w C, 1/R admittances
+    w = _source_omega(net)
+    N = net.n_nodes
+    Y = np.zeros((N, N), complex)
+    rhs = np.zeros(N, complex)
+    ins = net.in_service0.astype(bool)
+    for b in range(net.n_branches):
+        if not ins[b]:
+            continue
+        kd = net.kind[b]
+        if kd in (RL, SRC):
+            y = 1.0 / (net.R[b] + 1j * w * net.L[b])
+        elif kd == CAP:
+            y = 1j * w * net.C[b]
+        else:
+            y = 1.0 / net.R[b]
+        k, m = net.k[b], net.m[b]
+        E = net.E[b] * np.exp(1j * net.phase[b]) if kd == SRC else 0.0
+        for a, sa in ((k, 1.0), (m, -1.0)):
+            if a < 0:
+                continue
+            rhs[a] += sa * y * E
+            for c_, sc in ((k, 1.0), (m, -1.0)):
+                if c_ >= 0:
+                    Y[a, c_] += sa * sc * y
+    return np.linalg.solve(Y, rhs)
+
+
+def test_steady_state_converges_to_continuous_phasors(oracle_mod):
+    # the discrete steady state differs from the continuous one by the
+    # trapezoidal rule's frequency warping, O((w dt)^2): halving dt quarters it
+    net = netgen.small_grid(13, 12)
+    Vc = _continuous_phasors(net)
+    errs = []
+    for dt in (100e-6, 50e-6, 25e-6):
+        _, _, V = oracle_mod.steady_state(net, dt)
+        errs.append(np.max(np.abs(V - Vc)) / np.max(np.abs(Vc)))
+    assert errs[-1] < 1e-3
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4, errs
+
+
+def test_steady_state_without_sources_is_rest(oracle_mod):
+    net = netgen.circuit(2, [dict(k=0, m=1, kind=RL, R=1.0, L=1e-3), dict(k=1, m=-1, kind=CAP, C=1e-6),
+                             dict(k=0, m=-1, kind=RES, R=10.0)])
+    v0, i0, V = oracle_mod.steady_state(net, 50e-6)
+    assert not np.any(v0) and not np.any(i0) and not np.any(V)
+
+
+def test_steady_state_rejections(oracle_mod):
+    from paper_1903_01081_amd.netgen import LINE
+    two = netgen.circuit(1, [
+        dict(k=0, m=-1, kind=SRC, R=0.5, L=1e-3, E=1.0, omega=377.0, phase=0.0),
+        dict(k=0, m=-1, kind=SRC, R=0.5, L=1e-3, E=1.0, omega=314.0, phase=0.0),
+        dict(k=0, m=-1, kind=RES, R=10.0)])
+    with pytest.raises(Exception):
+        oracle_mod.steady_state(two, 50e-6)
+    tw = netgen.small_grid(3, 12, travelling_wave_dt=20e-6)
+    assert np.any(tw.kind == LINE)
+    with pytest.raises(Exception):
+        oracle_mod.steady_state(tw, 20e-6)
