@@ -328,6 +328,24 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
  * flag, discarding a give-up not yet reported). Stream-ordered. */
 emt_status emt_reset(emt_ctx *ctx, void *stream);
 
+/* Not in the paper (its runs start from rest; the sinusoidal steady state is
+ * the usual start of an EMTP-type run). Return every scenario to step 0 in
+ * the periodic steady state of its initial topology (switches at their
+ * initial positions, the coefficients as set by emt_build / emt_set_params)
+ * under its sources, which must share one angular frequency w per scenario:
+ * with z = exp(j w dt) each branch acts as the discrete admittance
+ * y = (g z + gamma) / (z - beta) of its companion recursion, the node
+ * phasors solve (A y A^T) V = A y E (E = E exp(j phase) on sources), and the
+ * state is v = Re V, u = Re(A^T V - E), i = Re(y u). The recursion started
+ * there stays on v_n = Re(V z^n) until the first event. A component without
+ * sources rests at zero. One workgroup per component factorises Y on the
+ * component's own symbolic pattern (complex LDL^T, allocated at the first
+ * call); runs forward only afterwards (emt_adjoint needs a run from rest).
+ * Synchronises. Errors: EMT_EINVAL (sources of one scenario at different
+ * frequencies; distributed-parameter lines), EMT_ESINGULAR (a zero or
+ * non-finite complex pivot), EMT_ENOMEM, EMT_EDEVICE. */
+emt_status emt_steady_state(emt_ctx *ctx, void *stream);
+
 /* Not in the paper, which has no gradients: an extension that
  * differentiates the paper's time loop (Sec. III-A) exactly. It is the
  * discrete adjoint of the recursion at the top of this header, with the

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "EMT_OK", 1: "EMT_EINVAL", 2: "EMT_ESINGULAR", 3: "EMT_ENOMEM
 # Exported functions of include/emt.h.
 EXPORTS = ("emt_build", "emt_analyze", "emt_info_get", "emt_set_params", "emt_factor", "emt_factor_async",
            "emt_mismatch",
-           "emt_step", "emt_step_noalloc", "emt_sync", "emt_reset", "emt_adjoint", "emt_branch_adjoints", "emt_get_state",
+           "emt_step", "emt_step_noalloc", "emt_sync", "emt_reset", "emt_steady_state", "emt_adjoint",
+           "emt_branch_adjoints", "emt_get_state",
            "emt_set_state", "emt_latency_floor", "emt_destroy", "emt_last_error")
 
 # emt_floor_kernel
@@ -99,6 +100,7 @@ def load():
         "emt_mismatch": [vp, vp, vp, vp, vp, vp],
         "emt_step": [vp, i64, vp, vp],
         "emt_sync": [vp, vp],
+        "emt_steady_state": [vp, vp],
         "emt_step_noalloc": [vp, i64, vp, vp],
         "emt_reset": [vp, vp],
         "emt_adjoint": [vp, vp, vp, vp],

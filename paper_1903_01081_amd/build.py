@@ -27,6 +27,7 @@ SOURCES = [
     ("step.hip", "step512", ["-DEMT_BS=512"]),
     ("split.hip", "split", []),
     ("scratch.hip", "scratch", []),
+    ("steady.hip", "steady", []),
     ("floor.hip", "floor", []),
 ]
 

@@ -95,6 +95,12 @@ struct emt_ctx {
   // pipelined adjoint's give-up flag (dc.flags[2])
   bool pivots_pending = false, adjoint_pending = false;
   int64_t ring_doubles = 0;  // wave rings of the distributed-parameter lines
+  // steady-state solve: scenarios whose sources run at different
+  // frequencies, and (allocated at the first emt_steady_state) per-item
+  // offsets of the complex factor, pivots and solution
+  std::vector<char> scen_mixed_freq;
+  int64_t *d_ss_offl = nullptr, *d_ss_offn = nullptr;
+  double *ss_L = nullptr, *ss_D = nullptr, *ss_X = nullptr;
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -855,6 +861,18 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<uint8_t> cins;
   std::vector<int64_t> br_ids;
   fill_branch_params(c, nets, bkind, bline, bE, bw, bph, bR, bL, bC, bpack, cins, br_ids);
+  c.scen_mixed_freq.assign(A.scens.size(), 0);
+  for (size_t q = 0; q < A.scens.size(); ++q) {
+    const emt_net &net = nets[q];
+    bool any = false;
+    double w = 0.0;
+    for (int b = 0; b < net.n_branches; ++b) {
+      if (net.kind[b] != EMT_SRC) continue;
+      if (any && net.omega[b] != w) c.scen_mixed_freq[q] = 1;
+      w = net.omega[b];
+      any = true;
+    }
+  }
 
   // Line -> branches (global item-branch index), per scenario, fixed order.
   std::vector<int32_t> lptr{0}, line_scen, line_id;
@@ -1305,6 +1323,48 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
     hip_check(hipEventElapsedTime(&ms, sc.e0, sc.e1), "event time");
     if (kernel == EMT_FLOOR_SPLIT) report_split(*ctx);
     *us_per_step = (double)ms * 1e3 / (double)n_steps;
+    return EMT_OK;
+  });
+}
+
+emt_status emt_steady_state(emt_ctx *ctx, void *stream) {
+  return guarded([&]() -> emt_status {
+    if (!ctx) return set_error(EMT_EINVAL, "ctx is required");
+    for (const emt::Item &it : ctx->A.items)
+      if (!it.line_bk.empty())
+        return set_error(EMT_EINVAL, "distributed-parameter lines start from rest (no steady state)");
+    for (size_t q = 0; q < ctx->scen_mixed_freq.size(); ++q)
+      if (ctx->scen_mixed_freq[q])
+        return set_error(EMT_EINVAL, "scenario " + std::to_string(q) +
+                                         ": sources at different frequencies have no single steady state");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int NI = (int)ctx->A.items.size();
+    if (!ctx->ss_L) {
+      std::vector<int64_t> offl(NI), offn(NI);
+      int64_t nl = 0, nn = 0;
+      for (int q = 0; q < NI; ++q) {
+        offl[q] = nl;
+        offn[q] = nn;
+        nl += ctx->A.syms[ctx->A.items[q].sym].nnz();
+        nn += ctx->A.items[q].n;
+      }
+      ctx->d_ss_offl = ctx->upload(offl);
+      ctx->d_ss_offn = ctx->upload(offn);
+      ctx->ss_L = ctx->alloc<double>(2 * (size_t)std::max<int64_t>(nl, 1));
+      ctx->ss_D = ctx->alloc<double>(2 * (size_t)std::max<int64_t>(nn, 1));
+      ctx->ss_X = ctx->alloc<double>(2 * (size_t)std::max<int64_t>(nn, 1));
+    }
+    hip_check(emt::launch_fill_i32(ctx->dc.flags + 3, 1, 0, st), "clear flag");
+    arm_split_flag(*ctx, st);
+    hip_check(emt::launch_steady(ctx->dc, NI, ctx->d_ss_offl, ctx->d_ss_offn, ctx->ss_L, ctx->ss_D, ctx->ss_X,
+                                 ctx->dc.flags + 3, st),
+              "steady state");
+    int32_t bad = 0;
+    hip_check(hipMemcpyAsync(&bad, ctx->dc.flags + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag");
+    hip_check(hipStreamSynchronize(st), "steady-state sync");
+    ctx->step = 0;
+    ctx->clean = false;
+    if (bad) return set_error(EMT_ESINGULAR, std::to_string(bad) + " zero or non-finite complex pivots");
     return EMT_OK;
   });
 }

@@ -90,6 +90,12 @@ hipError_t split_blocks_per_cu(int bpt, int rpl, int rt, size_t lds, int *blocks
 constexpr int64_t kStaticScratchBytes = EMT_STATIC_SCRATCH_BYTES;
 hipError_t static_scratch_ptr(int device, void **ptr);
 // dst[0] = 1 if src[0] != 0 (one lane; stream-ordered)
+// Sinusoidal steady state of every item's initial topology (state at step
+// 0); complex factor, pivots and solution in the scratch given, at the
+// per-item offsets (in complex entries); bad counts zero pivots.
+hipError_t launch_steady(const DevCtx &c, int n_items, const int64_t *off_l, const int64_t *off_n, void *Lc,
+                         void *Dc, void *X, int32_t *bad, hipStream_t st);
+
 hipError_t launch_or_flag(int32_t *dst, const int32_t *src, hipStream_t st);
 
 // Latency floors (floor.hip; the split floor is launch_split with floor set).

@@ -106,6 +106,11 @@ class Simulator:
     def reset(self):
         check(self.lib.emt_reset(self._ctx, _stream()))
 
+    def steady_state(self):
+        """Every scenario back to step 0 in the sinusoidal steady state of its
+        initial topology (emt_steady_state); forward only afterwards."""
+        check(self.lib.emt_steady_state(self._ctx, _stream()))
+
     def mismatch(self, rec: torch.Tensor, target: torch.Tensor, dJ: torch.Tensor, loss: torch.Tensor):
         """dJ = 2 (rec - target) on the recorded columns, loss[s] = sum of
         squares (emt_mismatch); all device tensors, queued."""
