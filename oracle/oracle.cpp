@@ -90,6 +90,10 @@ struct OracleNet {
   const uint8_t *ev_in_service;
   int32_t n_rec;
   const int32_t *rec_nodes;  // may be null: every node
+  // coupled three-phase groups (may be null): group id per branch or -1, and
+  // the mutual entries of each group's circulant R, L or C matrix
+  const int32_t *group;
+  const double *Rm, *Lm, *Cm;
 };
 
 }  // extern "C"
@@ -104,7 +108,23 @@ inline double re(const cplx &x) { return x.real(); }
 template <class T>
 struct Companions {
   std::vector<T> g, beta, gamma;
+  // mutual coefficients of coupled groups (0 elsewhere): the off-diagonal
+  // entries of the group's circulant G, B and Gamma
+  std::vector<T> go, bo, co;
 };
+
+// Members of each coupled group (three branches), in branch order.
+std::vector<std::vector<int>> group_members(const OracleNet &net) {
+  std::vector<std::vector<int>> gm;
+  if (!net.group) return gm;
+  for (int b = 0; b < net.n_branches; ++b) {
+    const int g = net.group[b];
+    if (g < 0) continue;
+    if ((int)gm.size() <= g) gm.resize(g + 1);
+    gm[g].push_back(b);
+  }
+  return gm;
+}
 
 // Per-branch R, L, C with the line parameters theta applied (series branch:
 // R_l, L_l; each shunt capacitor of a pi-section: C_l / 2).
@@ -155,6 +175,39 @@ void companions(const OracleNet &net, const T *theta, double dt,
         c.g[b] = T(1) / R;
         break;
       }
+    }
+  }
+  // Coupled groups: 3 x 3 circulant companions, i = G u + h and
+  // h' = B i + Gamma u per group (RL: G = (R + 2L/dt)^{-1}, B = G (2L/dt -
+  // R), Gamma = G; C: G = 2C/dt, B = -I, Gamma = -G). A 3 x 3 circulant with diagonal d and off-diagonal o has eigenvalues
+  // d + 2o (zero sequence) and d - o (positive and negative sequence), and
+  // products and inverses of circulants are circulants with the products
+  // and inverses of these eigenvalues.
+  c.go.assign(B, T(0));
+  c.bo.assign(B, T(0));
+  c.co.assign(B, T(0));
+  if (!net.group) return;
+  auto diag_off = [](T e0, T e1, T &d, T &o) {  // circulant from its two eigenvalues
+    d = (e0 + T(2) * e1) / T(3);
+    o = (e0 - e1) / T(3);
+  };
+  for (int b = 0; b < B; ++b) {
+    if (net.group[b] < 0 || !ins[b]) continue;
+    if (net.kind[b] == K_RL) {
+      const T Md = T(net.R[b]) + T(2) * T(net.L[b]) / dt, Mo = T(net.Rm[b]) + T(2) * T(net.Lm[b]) / dt;
+      const T Nd = T(2) * T(net.L[b]) / dt - T(net.R[b]), No = T(2) * T(net.Lm[b]) / dt - T(net.Rm[b]);
+      const T l0 = Md + T(2) * Mo, l1 = Md - Mo, m0 = Nd + T(2) * No, m1 = Nd - No;
+      diag_off(T(1) / l0, T(1) / l1, c.g[b], c.go[b]);        // G = M^{-1}
+      diag_off(m0 / l0, m1 / l1, c.beta[b], c.bo[b]);         // B = G N
+      c.gamma[b] = c.g[b];                                    // Gamma = G
+      c.co[b] = c.go[b];
+    } else {  // capacitor group: G = 2 C / dt, B = -I, Gamma = -G
+      c.g[b] = T(2) * T(net.C[b]) / dt;
+      c.go[b] = T(2) * T(net.Cm[b]) / dt;
+      c.beta[b] = T(-1);
+      c.bo[b] = T(0);
+      c.gamma[b] = -c.g[b];
+      c.co[b] = -c.go[b];
     }
   }
 }
@@ -251,6 +304,19 @@ void assemble(const OracleNet &net, const Companions<T> &c, std::vector<T> &G) {
       G[(size_t)m * N + k] -= g;
     }
   }
+  // coupled groups: A Gm A^T with Gm's off-diagonal go between members
+  for (const auto &mem : group_members(net))
+    for (int p : mem)
+      for (int q : mem) {
+        if (p == q) continue;
+        const int tp[2] = {net.k[p], net.m[p]}, tq[2] = {net.k[q], net.m[q]};
+        for (int a = 0; a < 2; ++a)
+          for (int e = 0; e < 2; ++e) {
+            if (tp[a] < 0 || tq[e] < 0) continue;
+            const T v = (a == e) ? c.go[p] : -c.go[p];
+            G[(size_t)tp[a] * N + tq[e]] += v;
+          }
+      }
 }
 
 inline double emf(const OracleNet &net, int b, int64_t n, double dt) {
@@ -277,8 +343,36 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
   }
   for (int r = 0; r < net.n_rec; ++r)
     if (net.rec_nodes && (net.rec_nodes[r] < 0 || net.rec_nodes[r] >= net.n_nodes)) return false;
+  if (net.group) {
+    if (!net.Rm || !net.Lm || !net.Cm) return false;
+    for (int b = 0; b < net.n_branches; ++b)
+      if (net.group[b] < -1) return false;
+    for (const auto &mem : group_members(net)) {
+      if (mem.size() != 3) return false;
+      const int b0 = mem[0];
+      for (int b : mem) {
+        if (net.kind[b] != net.kind[b0] || (net.kind[b] != K_RL && net.kind[b] != K_C) || net.line[b] >= 0)
+          return false;
+        if (net.R[b] != net.R[b0] || net.L[b] != net.L[b0] || net.C[b] != net.C[b0] || net.Rm[b] != net.Rm[b0] ||
+            net.Lm[b] != net.Lm[b0] || net.Cm[b] != net.Cm[b0])
+          return false;
+        if (net.in_service0 && !net.in_service0[b]) return false;
+        for (int j = 0; j < net.n_events; ++j)
+          if (net.ev_branch[j] == b) return false;
+      }
+      if (net.kind[b0] == K_RL) {
+        if (!(net.L[b0] - net.Lm[b0] > 0) || !(net.L[b0] + 2 * net.Lm[b0] > 0) ||
+            !(net.R[b0] - net.Rm[b0] >= 0) || !(net.R[b0] + 2 * net.Rm[b0] >= 0))
+          return false;
+      } else if (!(net.C[b0] - net.Cm[b0] > 0) || !(net.C[b0] + 2 * net.Cm[b0] > 0)) {
+        return false;
+      }
+    }
+  }
   return true;
 }
+
+bool has_groups(const OracleNet &net) { return !group_members(net).empty(); }
 
 inline int rec_node(const OracleNet &net, int r) { return net.rec_nodes ? net.rec_nodes[r] : r; }
 
@@ -359,6 +453,7 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
 
   Waves<T> waves;
   waves.init(net, dt, Tn);
+  const std::vector<std::vector<int>> groups = group_members(net);
 
   // Events sorted by step (stable order within a step).
   std::vector<int> ev(net.n_events);
@@ -390,6 +485,14 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
       h[b] = c.beta[b] * i[b] + c.gamma[b] * u[b];
       e[b] = T(emf(net, b, n, dt));
     }
+    for (const auto &mem : groups) {  // mutual terms: the other members' i, u
+      T si = T(0), su = T(0);
+      for (int q : mem) {
+        si += i[q];
+        su += u[q];
+      }
+      for (int p : mem) h[p] += c.bo[p] * (si - i[p]) + c.co[p] * (su - u[p]);
+    }
     std::fill(x.begin(), x.end(), T(0));
     for (int b = 0; b < B; ++b) {
       if (net.kind[b] == K_LINE) continue;
@@ -420,6 +523,11 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
       T vm = net.m[b] >= 0 ? v[net.m[b]] : T(0);
       u[b] = vk - vm - e[b];
       i[b] = c.g[b] * u[b] + h[b];
+    }
+    for (const auto &mem : groups) {
+      T su = T(0);
+      for (int q : mem) su += u[q];
+      for (int p : mem) i[p] += c.go[p] * (su - u[p]);
     }
     for (size_t q = 0; q < waves.lines.size(); ++q) {
       const int b = waves.lines[q];
@@ -469,11 +577,23 @@ int steady_state(const OracleNet &net, const double *theta, double dt, double *v
   companions(net, theta, dt, ins, c);
   const cplx z = std::polar(1.0, w * dt);
   std::vector<cplx> y(B, cplx(0.0, 0.0)), E(B, cplx(0.0, 0.0));
+  std::vector<cplx> yo(B, cplx(0.0, 0.0));  // mutual admittance of coupled groups
+  const std::vector<std::vector<int>> groups = group_members(net);
   for (int b = 0; b < B; ++b) {
     if (!ins[b]) continue;
     y[b] = (c.g[b] * z + c.gamma[b]) / (z - c.beta[b]);
     if (net.kind[b] == K_SRC) E[b] = std::polar(net.E[b], net.phase[b]);
   }
+  for (const auto &mem : groups)
+    for (int b : mem) {
+      // per sequence (zero: d + 2o, positive/negative: d - o) the scalar
+      // admittance, then back to the circulant's diagonal and off-diagonal
+      const cplx y0 = (cplx(c.g[b] + 2 * c.go[b]) * z + (c.gamma[b] + 2 * c.co[b])) /
+                      (z - (c.beta[b] + 2 * c.bo[b]));
+      const cplx y1 = (cplx(c.g[b] - c.go[b]) * z + (c.gamma[b] - c.co[b])) / (z - (c.beta[b] - c.bo[b]));
+      y[b] = (y0 + 2.0 * y1) / 3.0;
+      yo[b] = (y0 - y1) / 3.0;
+    }
   if (any) {
     std::vector<cplx> Y((size_t)N * N, cplx(0.0, 0.0));
     for (int b = 0; b < B; ++b) {
@@ -491,6 +611,15 @@ int steady_state(const OracleNet &net, const double *theta, double dt, double *v
         Y[(size_t)m * N + k] -= y[b];
       }
     }
+    for (const auto &mem : groups)
+      for (int p : mem)
+        for (int q : mem) {
+          if (p == q) continue;
+          const int tp[2] = {net.k[p], net.m[p]}, tq[2] = {net.k[q], net.m[q]};
+          for (int a = 0; a < 2; ++a)
+            for (int e = 0; e < 2; ++e)
+              if (tp[a] >= 0 && tq[e] >= 0) Y[(size_t)tp[a] * N + tq[e]] += (a == e) ? yo[p] : -yo[p];
+        }
     DenseLU<cplx> lu;
     lu.by_modulus = true;
     if (!lu.factor(Y, N)) return 2;
@@ -501,12 +630,21 @@ int steady_state(const OracleNet &net, const double *theta, double dt, double *v
     if (Vre) Vre[a] = V[a].real();
     if (Vim) Vim[a] = V[a].imag();
   }
+  std::vector<cplx> U(B);
+  for (int b = 0; b < B; ++b) {
+    const cplx vk = net.k[b] >= 0 ? V[net.k[b]] : cplx(0.0, 0.0);
+    const cplx vm = net.m[b] >= 0 ? V[net.m[b]] : cplx(0.0, 0.0);
+    U[b] = vk - vm - E[b];
+  }
+  std::vector<cplx> I(B);
+  for (int b = 0; b < B; ++b) I[b] = y[b] * U[b];
+  for (const auto &mem : groups) {
+    cplx su(0.0, 0.0);
+    for (int q : mem) su += U[q];
+    for (int p : mem) I[p] += yo[p] * (su - U[p]);
+  }
   if (i0)
-    for (int b = 0; b < B; ++b) {
-      const cplx vk = net.k[b] >= 0 ? V[net.k[b]] : cplx(0.0, 0.0);
-      const cplx vm = net.m[b] >= 0 ? V[net.m[b]] : cplx(0.0, 0.0);
-      i0[b] = (y[b] * (vk - vm - E[b])).real();
-    }
+    for (int b = 0; b < B; ++b) i0[b] = I[b].real();
   return 0;
 }
 
@@ -557,7 +695,7 @@ int oracle_loss_complex(const OracleNet *net, const double *theta_re, const doub
 int oracle_adjoint(const OracleNet *net, const double *theta, double dt, int64_t T,
                    const double *dJ_drec, double *grad, double *gbar_out,
                    double *betabar_out, double *gammabar_out) {
-  if (has_lines(*net)) return 1;  // lines run forward only
+  if (has_lines(*net) || has_groups(*net)) return 1;  // lines and coupled groups run forward only
   const int N = net->n_nodes, B = net->n_branches;
   std::vector<double> i_traj((size_t)(T + 1) * B), u_traj((size_t)(T + 1) * B);
   std::vector<int> topo_of_step;

@@ -39,6 +39,7 @@ class _Net(C.Structure):
         ("n_events", C.c_int32), ("ev_step", C.c_void_p), ("ev_branch", C.c_void_p),
         ("ev_in_service", C.c_void_p),
         ("n_rec", C.c_int32), ("rec_nodes", C.c_void_p),
+        ("group", C.c_void_p), ("Rm", C.c_void_p), ("Lm", C.c_void_p), ("Cm", C.c_void_p),
     ]
 
 
@@ -111,6 +112,9 @@ class _Packed:
             ev_ins=np.ascontiguousarray(net.ev_in_service, np.uint8).reshape(n_ev),
             rec=None if net.rec_nodes is None else np.ascontiguousarray(net.rec_nodes, np.int32),
         )
+        grp = getattr(net, "group", None)
+        for f, dt_ in (("group", np.int32), ("Rm", np.float64), ("Lm", np.float64), ("Cm", np.float64)):
+            self.arrs[f] = None if grp is None else np.ascontiguousarray(getattr(net, f), dt_)
         a = self.arrs
         self.n_rec = net.n_nodes if a["rec"] is None else int(a["rec"].shape[0])
         self.n_params = 3 * int(net.n_lines)
@@ -120,7 +124,8 @@ class _Packed:
                       _ptr(a["kind"]), _ptr(a["R"]), _ptr(a["L"]), _ptr(a["C"]), _ptr(a["E"]),
                       _ptr(a["omega"]), _ptr(a["phase"]), _ptr(a["line"]), self.n_params,
                       _ptr(a["ins"]), n_ev, _ptr(a["ev_step"]), _ptr(a["ev_branch"]),
-                      _ptr(a["ev_ins"]), self.n_rec, _ptr(a["rec"]))
+                      _ptr(a["ev_ins"]), self.n_rec, _ptr(a["rec"]), _ptr(a["group"]), _ptr(a["Rm"]),
+                      _ptr(a["Lm"]), _ptr(a["Cm"]))
 
     @property
     def ref(self):

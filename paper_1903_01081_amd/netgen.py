@@ -44,6 +44,9 @@ F_HZ = 60.0
 R_SRC = 0.5          # Thevenin source resistance per phase [ohm]
 L_SRC = 10e-3        # Thevenin source inductance per phase [H]
 R_FAULT = 1e-3       # closed fault switch resistance [ohm]
+# coupled three-phase lines: mutual / self ratios of the circulant series R,
+# L and (negative) shunt C matrices
+COUPLING_R, COUPLING_L, COUPLING_C = 0.25, 0.4, 0.2
 
 
 @dataclasses.dataclass
@@ -75,6 +78,14 @@ class Network:
     ev_in_service: np.ndarray
     rec_nodes: Optional[np.ndarray] = None
     n_lines: int = 0
+    # coupled three-phase groups: group[b] = group id (three branches of one
+    # kind, RL or CAP, with equal self values), -1 otherwise; Rm, Lm, Cm are
+    # the mutual (off-diagonal) entries of the group's circulant 3 x 3 R, L
+    # or C matrix. None when the network has no coupled groups.
+    group: Optional[np.ndarray] = None
+    Rm: Optional[np.ndarray] = None
+    Lm: Optional[np.ndarray] = None
+    Cm: Optional[np.ndarray] = None
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -110,16 +121,22 @@ class _Builder:
     def __init__(self, n_nodes: int):
         self.n_nodes = n_nodes
         self.cols = {c: [] for c in ("k", "m", "kind", "R", "L", "C", "E",
-                                     "omega", "phase", "line", "ins")}
+                                     "omega", "phase", "line", "ins", "group", "Rm", "Lm", "Cm")}
+        self.n_groups = 0
 
     def add(self, k, m, kind, R=0.0, L=0.0, C=0.0, E=0.0, omega=0.0,
-            phase=0.0, line=-1, ins=1) -> int:
+            phase=0.0, line=-1, ins=1, group=-1, Rm=0.0, Lm=0.0, Cm=0.0) -> int:
         c = self.cols
         c["k"].append(k); c["m"].append(m); c["kind"].append(kind)
         c["R"].append(R); c["L"].append(L); c["C"].append(C)
         c["E"].append(E); c["omega"].append(omega); c["phase"].append(phase)
         c["line"].append(line); c["ins"].append(ins)
+        c["group"].append(group); c["Rm"].append(Rm); c["Lm"].append(Lm); c["Cm"].append(Cm)
         return len(c["k"]) - 1
+
+    def new_group(self) -> int:
+        self.n_groups += 1
+        return self.n_groups - 1
 
     def network(self, events, rec_nodes, n_lines, meta) -> Network:
         c = self.cols
@@ -138,7 +155,10 @@ class _Builder:
             ev_branch=np.asarray([e[1] for e in ev], np.int32),
             ev_in_service=np.asarray([e[2] for e in ev], np.uint8),
             rec_nodes=None if rec_nodes is None else np.asarray(rec_nodes, np.int32),
-            n_lines=n_lines, meta=meta)
+            n_lines=n_lines, meta=meta,
+            **({} if self.n_groups == 0 else dict(
+                group=np.asarray(c["group"], np.int32), Rm=np.asarray(c["Rm"], np.float64),
+                Lm=np.asarray(c["Lm"], np.float64), Cm=np.asarray(c["Cm"], np.float64))))
 
 
 def random_lines(rng: np.random.Generator, n_bus: int, n_lines: int) -> np.ndarray:
@@ -172,12 +192,20 @@ def random_lines(rng: np.random.Generator, n_bus: int, n_lines: int) -> np.ndarr
 def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
                      n_gen: int, n_load: int, *, fault_bus: Optional[int] = None,
                      fault_step: int = 0, rec_nodes=None, with_fault_switch=True,
-                     travelling_wave_dt: Optional[float] = None):
+                     travelling_wave_dt: Optional[float] = None, coupled: bool = False):
     """Draw one grid. Returns (builder, bookkeeping) so callers can add events.
 
     Branch order: for each line its 3 series R-L branches, then the 3 shunt
     capacitors at its first bus, then the 3 at its second bus; then 3 source
     branches per generator, 3 load branches per load, 3 fault switches.
+
+    coupled: every line's three phases are coupled: its series R-L
+    branches form one group with mutual Rm = 0.25 R, Lm = 0.4 L, and the
+    C/2 shunts at each end one group with mutual Cm = -0.2 C/2 (a
+    transposed line's circulant matrices; positive sequence R - Rm, L - Lm,
+    C/2 - Cm, zero sequence R + 2 Rm, L + 2 Lm, C/2 + 2 Cm). Coupled lines
+    are not part of the parameter vector. The same random draws as the
+    uncoupled grid.
 
     travelling_wave_dt: if given, every line whose travel time
     tau = sqrt(L C) is at least this time step is drawn the same way but
@@ -198,6 +226,16 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
         if travelling_wave_dt is not None and tau >= travelling_wave_dt:
             for p in range(3):
                 series[l, p] = bld.add(3 * a + p, 3 * b + p, LINE, R=math.sqrt(L / C), L=tau)
+            continue
+        if coupled:
+            g = bld.new_group()
+            for p in range(3):
+                series[l, p] = bld.add(3 * a + p, 3 * b + p, RL, R=R, L=L, group=g,
+                                       Rm=COUPLING_R * R, Lm=COUPLING_L * L)
+            for bus in (a, b):
+                g = bld.new_group()
+                for p in range(3):
+                    bld.add(3 * bus + p, -1, CAP, C=C / 2.0, group=g, Cm=-COUPLING_C * C / 2.0)
             continue
         for p in range(3):
             series[l, p] = bld.add(3 * a + p, 3 * b + p, RL, R=R, L=L, line=l)
@@ -357,7 +395,7 @@ def config4(seed: int = 4, n_inst: int = 256, n_steps: int = 5000,
 def small_grid(seed: int, n_bus: int, *, n_lines=None, n_gen=None, n_load=None,
                fault_step: Optional[int] = None, n_mon: Optional[int] = None,
                remove_series: Optional[int] = None, remove_step: Optional[int] = None,
-               travelling_wave_dt: Optional[float] = None):
+               travelling_wave_dt: Optional[float] = None, coupled: bool = False):
     """A grid of the same recipe at an arbitrary size, for tests."""
     rng = np.random.default_rng(seed)
     if n_lines is None:
@@ -366,7 +404,7 @@ def small_grid(seed: int, n_bus: int, *, n_lines=None, n_gen=None, n_load=None,
     n_load = int(round(0.6 * n_bus)) if n_load is None else n_load
     bld, info = three_phase_grid(rng, n_bus, n_lines, n_gen, n_load,
                                  with_fault_switch=fault_step is not None,
-                                 travelling_wave_dt=travelling_wave_dt)
+                                 travelling_wave_dt=travelling_wave_dt, coupled=coupled)
     events = [] if fault_step is None else _fault_events(info, fault_step)
     if remove_series is not None:
         l, p = divmod(int(remove_series), 3)

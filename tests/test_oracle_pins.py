@@ -695,3 +695,86 @@ def test_steady_state_rejections(oracle_mod):
     assert np.any(tw.kind == LINE)
     with pytest.raises(Exception):
         oracle_mod.steady_state(tw, 20e-6)
+
+
+# ---------------------------------------------------------------------------
+# Coupled three-phase lines: circulant 3 x 3 series R-L and shunt C groups.
+# A symmetric network decouples into symmetrical components, so under
+# balanced excitation (positive sequence) it must behave exactly like the
+# uncoupled network with R - Rm, L - Lm, C - Cm, and under in-phase
+# excitation (zero sequence) like the one with R + 2 Rm, L + 2 Lm, C + 2 Cm.
+# ---------------------------------------------------------------------------
+
+def _sequence_equivalent(net, seq):
+    import copy
+    e = copy.deepcopy(net)
+    g = net.group >= 0
+    f = -1.0 if seq == 1 else 2.0
+    e.R, e.L, e.C = net.R.copy(), net.L.copy(), net.C.copy()
+    e.R[g] = net.R[g] + f * net.Rm[g]
+    e.L[g] = net.L[g] + f * net.Lm[g]
+    e.C[g] = net.C[g] + f * net.Cm[g]
+    e.group = e.Rm = e.Lm = e.Cm = None
+    return e
+
+
+def _in_phase_sources(net):
+    import copy
+    z = copy.deepcopy(net)
+    idx = np.where(z.kind == SRC)[0]
+    z.phase = z.phase.copy()
+    for t in range(0, len(idx), 3):  # each generator's three phases, in order
+        z.phase[idx[t:t + 3]] = z.phase[idx[t]]
+    return z
+
+
+@pytest.mark.parametrize("seed,n_bus", [(7, 12), (19, 30)])
+def test_coupled_balanced_equals_positive_sequence(oracle_mod, seed, n_bus):
+    net = netgen.small_grid(seed, n_bus, coupled=True, fault_step=150)
+    assert net.group is not None and np.any(net.Lm > 0) and np.any(net.Cm < 0)
+    dt, T = 50e-6, 400
+    a = oracle_mod.run(net, dt, T)
+    b = oracle_mod.run(_sequence_equivalent(net, 1), dt, T)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    # and the coupling matters: the uncoupled network differs
+    plain = netgen.small_grid(seed, n_bus, fault_step=150)
+    c = oracle_mod.run(plain, dt, T)
+    assert np.max(np.abs(a - c)) > 1e-3 * np.max(np.abs(c))
+
+
+def test_coupled_in_phase_equals_zero_sequence(oracle_mod):
+    net = _in_phase_sources(netgen.small_grid(7, 12, coupled=True, fault_step=150))
+    dt, T = 50e-6, 400
+    a = oracle_mod.run(net, dt, T)
+    b = oracle_mod.run(_sequence_equivalent(net, 0), dt, T)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_coupled_steady_state_periodic_and_sequence_equivalent(oracle_mod):
+    net = netgen.small_grid(23, 15, coupled=True)
+    dt, T = 50e-6, 2000
+    v0, i0, V = oracle_mod.steady_state(net, dt)
+    _, vt, _, _ = oracle_mod.run(net, dt, T, v0=v0, i0=i0, trajectories=True)
+    z = np.exp(1j * _source_omega(net) * dt * np.arange(T + 1))
+    ref = (V[None, :] * z[:, None]).real
+    assert np.max(np.abs(vt - ref)) <= 1e-11 * np.max(np.abs(ref))
+    _, _, V1 = oracle_mod.steady_state(_sequence_equivalent(net, 1), dt)
+    assert np.max(np.abs(V - V1)) <= 1e-12 * np.max(np.abs(V1))
+
+
+def test_coupled_rejections(oracle_mod):
+    import copy
+    net = netgen.small_grid(7, 8, coupled=True)
+    bad = copy.deepcopy(net)
+    bad.group = net.group.copy()
+    bad.group[1] = -1  # a group of two
+    with pytest.raises(Exception):
+        oracle_mod.run(bad, 50e-6, 10)
+    ev = copy.deepcopy(net)
+    ev.ev_step = np.array([5], np.int64)
+    ev.ev_branch = np.array([0], np.int32)
+    ev.ev_in_service = np.array([0], np.uint8)
+    with pytest.raises(Exception):
+        oracle_mod.run(ev, 50e-6, 10)
+    with pytest.raises(Exception):
+        oracle_mod.adjoint(net, 50e-6, 10, np.zeros((10, net.n_rec)))
