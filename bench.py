@@ -312,7 +312,52 @@ def extras(torch, args):
     out = extras_n1(torch)
     out.update(extras_adjoint(torch))
     out.update(extras_lines(torch, with_cpu=not args.no_cpu))
+    out.update(extras_coupled(torch, with_cpu=not args.no_cpu))
     return out
+
+
+COUPLED_WORKLOAD = ("grid200-coupled: a 200-bus grid with coupled three-phase lines (300 series R-L and 600 "
+                    "shunt C circulant groups), 600 nodes in one component, 15000 steps at 20 us, three-phase "
+                    "fault at step 7500, all nodes recorded")
+
+
+def extras_coupled(torch, with_cpu=True):
+    """The 200-bus grid with coupled three-phase lines: forward node-steps/s
+    in its tuned launch shape, roofline, latency and the oracle's rate."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator
+    from paper_1903_01081_amd.tune import tune
+    log("extras: coupled three-phase lines")
+    nets, cfg = netgen.config1(n_bus=200, n_steps=15000, coupled=True)
+    net = nets[0]
+    N, T = net.n_nodes, cfg["n_steps"]
+    n_groups = int(np.max(net.group)) + 1
+    shape = tune(nets, cfg["dt"], T, probe_steps=400)["shape"]
+    sim = Simulator(nets, cfg["dt"], T, **shape)
+    info = sim.info()
+    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    runs = [time_simulation(torch, sim, rec, 1, 1 if k == 0 else 0) for k in range(3)]
+    wall, kern = sorted(runs)[1]
+    # per group and step: the four mutual coefficients and the members'
+    # descriptor read (the members' own bytes are in the per-branch figure)
+    roof = roofline_object(info, net.n_rec, T, "k_forward", kern, extra_bytes_per_step=(32 + 40) * n_groups)
+    lat = latency_object(sim, "k_forward", kern / T * 1e6, info)
+    sim.close()
+    del rec
+    out = {"workload": COUPLED_WORKLOAD, "value": N * T / wall, "unit": "node-steps/s", "seconds": wall,
+           "kernel_s": kern, "launch_shape": shape, "groups": n_groups, "nnz_L": info["nnz_L"],
+           "roofline": roof, "latency": lat}
+    if with_cpu:
+        from oracle import oracle as O
+        O.use_native_build()
+        k = 3000
+        med, ts = median_time(lambda: O.run(net, cfg["dt"], k))
+        out["cpu_baseline"] = {
+            "value": N * k / med, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (g++ -O3 -march=native, 1 thread) on the first {k} of the 15,000 steps of the "
+                      f"same grid, factorisation included; median of 3 runs "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    return {"coupled_three_phase_lines": out}
 
 
 # per distributed-parameter line and time step: the two new waves written,
@@ -600,7 +645,7 @@ def main():
                     help="only the adjoint kernels in fixed launch shapes, two runs each (for rocprofv3): "
                          "the one-workgroup adjoint (grid100 and the uneven batch) or the pipelined one (grid100)")
     ap.add_argument("--only-lines", action="store_true",
-                    help="run only the grid with travelling-wave lines (one line; for profiling its kernel)")
+                    help="run only the grids with travelling-wave and with coupled three-phase lines (one line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -624,7 +669,9 @@ def main():
                               "workload": N1_WORKLOAD, "launch_shape": shape, "seconds": wall, "kernel_s": kern,
                               "roofline": roof, "latency": lat}), flush=True)
         elif args.only_lines:
-            print(json.dumps(extras_lines(torch, with_cpu=not args.no_cpu)), flush=True)
+            out = extras_lines(torch, with_cpu=not args.no_cpu)
+            out.update(extras_coupled(torch, with_cpu=not args.no_cpu))
+            print(json.dumps(out), flush=True)
         elif args.only_adjoint:
             print(json.dumps(extras_adjoint(torch)), flush=True)
         elif args.profile_adjoint is not None:

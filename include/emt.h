@@ -106,6 +106,21 @@ typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 
  *              ignored) branch ev_branch[j] goes in service
  *              (ev_in_service[j] = 1) or out (0).
  *   rec_nodes  the n_rec recorded nodes (NULL = all nodes, n_rec = n_nodes).
+ *   group, Rm, Lm, Cm  coupled three-phase groups (NULL = none; the
+ *              per-component Norton equivalents of Sec. III-A's first basic
+ *              process with 3 x 3 blocks): group[b] = g >= 0 puts branch b in
+ *              group g, -1 in none. A group is three EMT_RL (series) or
+ *              three EMT_C (shunt) branches with equal R, L, C, Rm, Lm, Cm,
+ *              line = -1, no events, in service from t = 0, whose R, L or C
+ *              matrix is circulant: R, L, C on the diagonal, Rm, Lm, Cm off
+ *              it (positive definite: L - Lm > 0, L + 2 Lm > 0, R - Rm >= 0,
+ *              R + 2 Rm >= 0; C - Cm > 0, C + 2 Cm > 0). Its trapezoidal
+ *              companion is the circulant i = G u + h, h' = B i + Gamma u
+ *              (RL: G = (R + 2L/dt)^-1, B = G (2L/dt - R), Gamma = G; C:
+ *              G = 2C/dt, B = -I, Gamma = -G). A batch with groups runs
+ *              forward only (EMT_EINVAL with checkpoint_every > 0 or with
+ *              components split over workgroups); the three phases a group
+ *              couples form one component.
  */
 typedef struct {
   int32_t n_nodes, n_branches;
@@ -121,6 +136,8 @@ typedef struct {
   const uint8_t *ev_in_service;
   int32_t n_rec;
   const int32_t *rec_nodes;
+  const int32_t *group;
+  const double *Rm, *Lm, *Cm;
 } emt_net;
 
 /* Simulation settings shared by all scenarios of a context.

@@ -44,6 +44,7 @@ class _Net(C.Structure):
 
 
 _lib = None
+_native = False
 
 
 def use_native_build() -> str:
@@ -51,16 +52,20 @@ def use_native_build() -> str:
     source with -O3 -march=native into liboracle_native.so and route every
     later call of this process through it. The compiler may fuse
     multiply-adds there, so results can differ from the test build in the
-    last bits: timing only. Must come before the first oracle call."""
-    global _lib
-    if _lib is not None:
-        raise RuntimeError("use_native_build() must come before the first oracle call")
+    last bits: timing only. Must come before the first oracle call (a
+    second call once the native build is loaded does nothing)."""
+    global _lib, _native
     path = os.path.join(_HERE, "liboracle_native.so")
+    if _lib is not None:
+        if _native:
+            return path
+        raise RuntimeError("use_native_build() must come before the first oracle call")
     tmp = path + ".tmp"
     subprocess.check_call(["g++", "-O3", "-march=native", "-std=c++17", "-fopenmp",
                            "-shared", "-fPIC", "-o", tmp, _SRC])
     os.replace(tmp, path)
     _load(path)
+    _native = True
     return path
 
 

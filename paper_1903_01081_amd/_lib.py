@@ -46,6 +46,7 @@ class EmtNet(C.Structure):
         ("n_events", C.c_int32), ("ev_step", C.c_void_p), ("ev_branch", C.c_void_p),
         ("ev_in_service", C.c_void_p),
         ("n_rec", C.c_int32), ("rec_nodes", C.c_void_p),
+        ("group", C.c_void_p), ("Rm", C.c_void_p), ("Lm", C.c_void_p), ("Cm", C.c_void_p),
     ]
 
 
@@ -154,13 +155,17 @@ class PackedNets:
                 ev_ins=np.ascontiguousarray(net.ev_in_service, np.uint8).reshape(n_ev),
                 rec=None if net.rec_nodes is None else np.ascontiguousarray(net.rec_nodes, np.int32),
             )
+            grp = getattr(net, "group", None)
+            for f, t in (("group", np.int32), ("Rm", np.float64), ("Lm", np.float64), ("Cm", np.float64)):
+                a[f] = None if grp is None else np.ascontiguousarray(getattr(net, f), t)
             self.keep.append(a)
             n_rec = int(net.n_nodes) if a["rec"] is None else int(a["rec"].shape[0])
             structs.append(EmtNet(
                 int(net.n_nodes), int(a["k"].shape[0]), _ptr(a["k"]), _ptr(a["m"]), _ptr(a["kind"]),
                 _ptr(a["R"]), _ptr(a["L"]), _ptr(a["C"]), _ptr(a["E"]), _ptr(a["omega"]),
                 _ptr(a["phase"]), _ptr(a["line"]), 3 * int(net.n_lines), _ptr(a["ins"]), n_ev,
-                _ptr(a["ev_step"]), _ptr(a["ev_branch"]), _ptr(a["ev_ins"]), n_rec, _ptr(a["rec"])))
+                _ptr(a["ev_step"]), _ptr(a["ev_branch"]), _ptr(a["ev_ins"]), n_rec, _ptr(a["rec"]),
+                _ptr(a["group"]), _ptr(a["Rm"]), _ptr(a["Lm"]), _ptr(a["Cm"])))
         self.array = (EmtNet * len(structs))(*structs)
         self.n = len(structs)
 

@@ -86,6 +86,41 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (n.kind[n.ev_branch[j]] == EMT_LINE)
       fail(EMT_EINVAL, where(s, "distributed-parameter lines take no switching events", j));
   }
+  if (n.group) {
+    if (!n.Rm || !n.Lm || !n.Cm) fail(EMT_EINVAL, where(s, "coupled groups need Rm, Lm and Cm"));
+    std::map<int, std::vector<int>> members;
+    for (int b = 0; b < n.n_branches; ++b) {
+      if (n.group[b] < -1) fail(EMT_EINVAL, where(s, "group index must be >= -1", b));
+      if (n.group[b] >= 0) members[n.group[b]].push_back(b);
+    }
+    if (!members.empty() && sim.checkpoint_every > 0)
+      fail(EMT_EINVAL, where(s, "coupled three-phase groups run forward only (no checkpoints)"));
+    for (auto &kv : members) {
+      const std::vector<int> &mem = kv.second;
+      if (mem.size() != 3) fail(EMT_EINVAL, where(s, "a coupled group has exactly three branches", mem[0]));
+      const int b0 = mem[0];
+      for (int b : mem) {
+        const int kd = n.kind[b];
+        if (kd != n.kind[b0] || (kd != EMT_RL && kd != EMT_C))
+          fail(EMT_EINVAL, where(s, "a coupled group is three R-L or three C branches", b));
+        if ((n.line && n.line[b] >= 0))
+          fail(EMT_EINVAL, where(s, "a coupled group's branches belong to no pi-section line", b));
+        if (n.R[b] != n.R[b0] || n.L[b] != n.L[b0] || n.C[b] != n.C[b0] || n.Rm[b] != n.Rm[b0] ||
+            n.Lm[b] != n.Lm[b0] || n.Cm[b] != n.Cm[b0])
+          fail(EMT_EINVAL, where(s, "a coupled group's branches have equal R, L, C, Rm, Lm, Cm", b));
+        if (n.in_service0 && !n.in_service0[b])
+          fail(EMT_EINVAL, where(s, "a coupled group is in service from t = 0", b));
+      }
+      const double R = n.R[b0], L = n.L[b0], C = n.C[b0], Rm = n.Rm[b0], Lm = n.Lm[b0], Cm = n.Cm[b0];
+      const bool ok = n.kind[b0] == EMT_RL
+                          ? (finite(Rm) && finite(Lm) && L - Lm > 0 && L + 2 * Lm > 0 && R - Rm >= 0 && R + 2 * Rm >= 0)
+                          : (finite(Cm) && C - Cm > 0 && C + 2 * Cm > 0);
+      if (!ok) fail(EMT_EINVAL, where(s, "a coupled group's circulant matrix is not positive definite", b0));
+    }
+    for (int j = 0; j < n.n_events; ++j)
+      if (n.group[n.ev_branch[j]] >= 0)
+        fail(EMT_EINVAL, where(s, "coupled groups take no switching events", j));
+  }
   if (n.rec_nodes) {
     if (n.n_rec < 0) fail(EMT_EINVAL, where(s, "n_rec < 0"));
     for (int r = 0; r < n.n_rec; ++r)
@@ -433,6 +468,20 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
     DSU d(N);
     for (int b = 0; b < B; ++b)
       if (ever[b] && net.k[b] >= 0 && net.m[b] >= 0) d.join(net.k[b], net.m[b]);
+    // coupled groups couple the terminals of their members
+    std::map<int, std::vector<int>> groups;  // group -> its branches
+    if (net.group)
+      for (int b = 0; b < B; ++b)
+        if (net.group[b] >= 0) groups[net.group[b]].push_back(b);
+    for (auto &kv : groups) {
+      int first = -1;
+      for (int b : kv.second)
+        for (int t : {net.k[b], net.m[b]}) {
+          if (t < 0) continue;
+          if (first < 0) first = t;
+          else d.join(first, t);
+        }
+    }
     // Work items: one per component, or with packing, components packed
     // first-fit by decreasing size into items of at most pack_nodes nodes
     // (a larger component stays alone). An item's G is then block-diagonal.
@@ -482,6 +531,21 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
         int a = canon[net.k[b]], c = canon[net.m[b]];
         if (a > c) std::swap(a, c);
         edges.push_back({a, c});
+      }
+      // mutual couplings of the groups in this item: every pair of terminals
+      // of two different members
+      for (auto &g : groups) {
+        const std::vector<int> &mem = g.second;
+        if (item_key(net.k[mem[0]] >= 0 ? net.k[mem[0]] : net.m[mem[0]]) != kv.first) continue;
+        for (size_t p = 0; p < mem.size(); ++p)
+          for (size_t q = p + 1; q < mem.size(); ++q)
+            for (int ta : {net.k[mem[p]], net.m[mem[p]]})
+              for (int te : {net.k[mem[q]], net.m[mem[q]]}) {
+                if (ta < 0 || te < 0 || ta == te) continue;
+                int a = canon[ta], c = canon[te];
+                if (a > c) std::swap(a, c);
+                edges.push_back({a, c});
+              }
       }
       std::sort(edges.begin(), edges.end());
       edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
@@ -574,6 +638,41 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
           const int *f = std::lower_bound(lo, hi, c);
           if (f == hi || *f != c) fail(EMT_EDEVICE, "internal: branch missing from the L pattern");
           it_.gpos[j] = S.lrow_ptr[r] + (int)(f - lo);
+        }
+      }
+      // Coupled groups: members' local branches and the mutual stamps.
+      if (!groups.empty()) {
+        std::map<int, std::vector<int>> gl;  // group -> local branches of its members
+        for (int j = 0; j < it_.n_br; ++j) {
+          const int b = it_.br[j];
+          if (b >= 0 && !line_end[j] && net.group[b] >= 0) gl[net.group[b]].push_back(j);
+        }
+        std::vector<std::vector<std::pair<int, int>>> rows(n);
+        for (auto &g : gl) {
+          const std::vector<int> &mem = g.second;
+          for (int j : mem) it_.grp_b.push_back(j);
+          for (size_t p = 0; p < mem.size(); ++p)
+            for (size_t q = p + 1; q < mem.size(); ++q) {
+              const int jp = mem[p], jq = mem[q];
+              const int tp[2] = {it_.bk[jp], it_.bm[jp]}, tq[2] = {it_.bk[jq], it_.bm[jq]};
+              for (int ea = 0; ea < 2; ++ea)
+                for (int ee = 0; ee < 2; ++ee) {
+                  if (tp[ea] < 0 || tq[ee] < 0) continue;
+                  const int r = std::max(tp[ea], tq[ee]), cc = std::min(tp[ea], tq[ee]);
+                  const int *lo = &S.lrow_col[S.lrow_ptr[r]], *hi = &S.lrow_col[S.lrow_ptr[r + 1]];
+                  const int *f = std::lower_bound(lo, hi, cc);
+                  if (f == hi || *f != cc) fail(EMT_EDEVICE, "internal: mutual coupling missing from the L pattern");
+                  rows[r].push_back({S.lrow_ptr[r] + (int)(f - lo), (jp << 1) | (ea != ee ? 1 : 0)});
+                }
+            }
+        }
+        it_.mptr.assign(n + 1, 0);
+        for (int r = 0; r < n; ++r) {
+          it_.mptr[r + 1] = it_.mptr[r] + (int)rows[r].size();
+          for (auto &e : rows[r]) {
+            it_.mpos.push_back(e.first);
+            it_.mcode.push_back(e.second);
+          }
         }
       }
       // Node CSR of incident branch ends, in increasing local branch order.

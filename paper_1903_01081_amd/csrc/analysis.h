@@ -83,6 +83,11 @@ struct Item {
   // its delay tau / dt = D0 + f
   std::vector<int> line_bk, line_bm, line_nk, line_nm, line_d0;
   std::vector<double> line_f;
+  // coupled three-phase groups: the local branches of each group's three
+  // members, and the groups' mutual conductance stamps by row of L (CSR:
+  // entry = L position, and local branch << 1 | 1 if the stamp is -g_o)
+  std::vector<int> grp_b;
+  std::vector<int> mptr, mpos, mcode;
 };
 
 struct Scenario {

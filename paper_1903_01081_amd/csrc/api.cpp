@@ -178,10 +178,11 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
       // ground terminals point at the node slot n, which holds 0
       const uint32_t k = it.bk[j] >= 0 ? (uint32_t)it.bk[j] : (uint32_t)it.n;
       const uint32_t m = it.bm[j] >= 0 ? (uint32_t)it.bm[j] : (uint32_t)it.n;
-      const uint32_t cls = (kind == EMT_RL || kind == EMT_SRC)
-                               ? emt::GAMMA_PLUS_G
-                               : (kind == EMT_C ? emt::GAMMA_MINUS_G
-                                                : (kind == EMT_LINE ? emt::GAMMA_LINE : emt::GAMMA_ZERO));
+      const bool pass = kind == EMT_LINE || (net.group && net.group[b] >= 0);
+      const uint32_t cls = pass ? emt::GAMMA_PASS
+                                : ((kind == EMT_RL || kind == EMT_SRC)
+                                       ? emt::GAMMA_PLUS_G
+                                       : (kind == EMT_C ? emt::GAMMA_MINUS_G : emt::GAMMA_ZERO));
       bpack.push_back(k | (m << 15) | (cls << 30));
     }
   }
@@ -525,6 +526,9 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
       if (!it.line_bk.empty())
         throw Error{EMT_EINVAL, "components with distributed-parameter lines run in one workgroup; the dense "
                                 "solver would split one of " + std::to_string(it.n) + " nodes"};
+      if (!it.grp_b.empty())
+        throw Error{EMT_EINVAL, "components with coupled three-phase groups run in one workgroup; the dense "
+                                "solver would split one of " + std::to_string(it.n) + " nodes"};
       c.is_split[q] = 1;
       continue;
     }
@@ -755,6 +759,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<int32_t> bk, bm, bgpos, bscen, bitem, blocal, nptr, rptr;
   std::vector<uint16_t> nent, rnode, rcolumn;
   int64_t coef_off = 0, fac_off = 0, dfac_off = 0, sv_off = 0, w_off = 0, ck_off = 0, seg_off = 0, node_off = 0;
+  std::vector<GroupDesc> group_tab;
+  std::vector<int32_t> mptr_all, ment_all;
   std::vector<LineDesc> line_tab;
   std::vector<double> line_gf;
   int64_t ring_off = 0;
@@ -790,6 +796,28 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.topo = scen_topo_off[it.scen];
     d.ck = ck_off;
     d.seg = seg_off;
+    d.n_groups = (int32_t)(it.grp_b.size() / 3);
+    d.groups = (int64_t)group_tab.size();
+    for (size_t g = 0; g + 2 < it.grp_b.size(); g += 3) {
+      GroupDesc gd{};
+      for (int p = 0; p < 3; ++p) {
+        const int j = it.grp_b[g + p];
+        gd.b[p] = j;
+        gd.k[p] = it.bk[j] >= 0 ? it.bk[j] : it.n;
+        gd.m[p] = it.bm[j] >= 0 ? it.bm[j] : it.n;
+      }
+      gd.sgn = nets[it.scen].kind[it.br[it.grp_b[g]]] == EMT_C ? -1 : 1;
+      group_tab.push_back(gd);
+    }
+    d.mptr = (int64_t)mptr_all.size();
+    d.ment = (int64_t)ment_all.size();
+    if (!it.grp_b.empty()) {
+      for (int r = 0; r <= it.n; ++r) mptr_all.push_back(it.mptr[r]);
+      for (size_t e = 0; e < it.mpos.size(); ++e) {
+        ment_all.push_back(it.mpos[e]);
+        ment_all.push_back(it.mcode[e]);
+      }
+    }
     d.n_lines = (int32_t)it.line_bk.size();
     d.lines = (int64_t)line_tab.size();
     for (size_t l = 0; l < it.line_bk.size(); ++l) {
@@ -952,6 +980,31 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.line_gf = line_gf.empty() ? nullptr : c.upload(line_gf);
   dc.ring = ring_off > 0 ? c.alloc<double>(ring_off) : nullptr;
   c.ring_doubles = ring_off;
+  if (!group_tab.empty()) {
+    // per-branch mutual values and member flags, in the branch arrays' order
+    std::vector<double> bRm, bLm, bCm;
+    std::vector<int32_t> bgrp;
+    for (const Item &it : A.items) {
+      const emt_net &net = nets[it.scen];
+      for (int j = 0; j < it.n_br; ++j) {
+        const int b = it.br[j];
+        const bool g = b >= 0 && net.group && net.group[b] >= 0 && net.kind[b] != EMT_LINE;
+        bgrp.push_back(g ? 1 : 0);
+        bRm.push_back(g ? net.Rm[b] : 0.0);
+        bLm.push_back(g ? net.Lm[b] : 0.0);
+        bCm.push_back(g ? net.Cm[b] : 0.0);
+      }
+    }
+    dc.group_tab = c.upload(group_tab);
+    dc.mptr = c.upload(mptr_all);
+    dc.ment = ment_all.empty() ? nullptr : c.upload(ment_all);
+    dc.bRm = c.upload(bRm);
+    dc.bLm = c.upload(bLm);
+    dc.bCm = c.upload(bCm);
+    dc.bgrp = c.upload(bgrp);
+    dc.cgo = c.alloc<double>(coef_off);
+    dc.cbo = c.alloc<double>(coef_off);
+  }
   dc.flags = c.alloc<int32_t>(4);
   hip_check(launch_fill_i32(dc.flags, 4, 0, nullptr), "clear flags");
   dc.dt = sim.dt;

@@ -48,6 +48,38 @@ __global__ void k_companions(DevCtx c, const int64_t *coef_base, const int64_t *
   const int64_t gb = br_base[item] + b;
   const int64_t ci = coef_base[item] + (int64_t)t * nbr + b;
   double g = 0.0, be = 0.0;
+  if (c.bgrp && c.bgrp[gb]) {
+    // member of a coupled group (always in service): the circulant
+    // companion from its zero- and positive-sequence eigenvalues d + 2o and
+    // d - o (a circulant's products and inverses are circulants with the
+    // products and inverses of these); diagonal -> cg, cb, off-diagonal ->
+    // cgo, cbo
+    const double dt = c.dt;
+    double go = 0.0, bo = 0.0;
+    if (c.bkind[gb] == KIND_RL) {
+      const double Md = c.bR[gb] + 2.0 * c.bL[gb] / dt, Mo = c.bRm[gb] + 2.0 * c.bLm[gb] / dt;
+      const double Nd = 2.0 * c.bL[gb] / dt - c.bR[gb], No = 2.0 * c.bLm[gb] / dt - c.bRm[gb];
+      const double l0 = Md + 2.0 * Mo, l1 = Md - Mo, m0 = Nd + 2.0 * No, m1 = Nd - No;
+      const double g0 = 1.0 / l0, g1 = 1.0 / l1, b0 = m0 / l0, b1 = m1 / l1;
+      g = (g0 + 2.0 * g1) / 3.0;
+      go = (g0 - g1) / 3.0;
+      be = (b0 + 2.0 * b1) / 3.0;
+      bo = (b0 - b1) / 3.0;
+    } else {
+      g = 2.0 * c.bC[gb] / dt;
+      go = 2.0 * c.bCm[gb] / dt;
+      be = -1.0;
+    }
+    c.cg[ci] = g;
+    c.cb[ci] = be;
+    c.cgo[ci] = go;
+    c.cbo[ci] = bo;
+    return;
+  }
+  if (c.cgo) {
+    c.cgo[ci] = 0.0;
+    c.cbo[ci] = 0.0;
+  }
   if (c.cins[ci]) {
     const double dt = c.dt;
     const int kind = c.bkind[gb];
@@ -119,6 +151,18 @@ __global__ __launch_bounds__(BS) void k_factor(DevCtx c, const int32_t *pairs) {
       if (other >= 0 && other < r) Lr[gpos[b]] = Lr[gpos[b]] - gv;
     }
     D[r] = d;
+    if (it.n_groups > 0) {
+      // mutual conductances of coupled groups: +g_o between like terminals
+      // of two members, -g_o between a k and an m terminal
+      const int32_t *mp = c.mptr + it.mptr;
+      const int32_t *me = c.ment + it.ment;
+      const double *go = c.cgo + it.coef + (int64_t)t * it.n_br;
+      for (int e = mp[r]; e < mp[r + 1]; ++e) {
+        const int pos = me[2 * e], code = me[2 * e + 1];
+        const double v = go[code >> 1];
+        Lr[pos] = (code & 1) ? Lr[pos] - v : Lr[pos] + v;
+      }
+    }
   }
   __syncthreads();
   for (int l = 0; l < sd.nlev; ++l) {

@@ -13,12 +13,14 @@ enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4,
 // Packed branch descriptor for the step kernels: local terminals in 15 bits
 // each (a grounded terminal holds the node count n: the step kernels keep a
 // zero at x[n]) and the history-coefficient class in 2 bits: gamma = g (R-L
-// and sources), -g (capacitors) or 0 (resistors, switches), or a line end
-// (gamma = beta = 0; its history comes from the other end's travelling wave,
-// written into its injection by the line pass, not by the branch update).
+// and sources), -g (capacitors) or 0 (resistors, switches), or a branch
+// whose history a pass after the branch update writes into its injection
+// (a line end: the other end's travelling wave; a member of a coupled
+// group: its circulant companion with the other members' currents and
+// voltages).
 constexpr uint32_t kTermGround = 0x7FFF;  // mask of one packed terminal
 constexpr int kMaxItemNodes = 0x7FFF;
-enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2, GAMMA_LINE = 3 };
+enum : uint32_t { GAMMA_PLUS_G = 0, GAMMA_MINUS_G = 1, GAMMA_ZERO = 2, GAMMA_PASS = 3 };
 
 // Symbolic factor and sweep plan (shared by isomorphic items). Offsets index
 // DevCtx::symi (int32) or DevCtx::symh (uint16).
@@ -55,6 +57,17 @@ struct ItemDesc {
   int64_t ck;    // checkpoints (i, u) [n_ck][n_br]
   int64_t seg;   // adjoint segment buffer (i, u) [K+1][n_br]
   int64_t lines; // distributed-parameter lines: first entry of line_tab / line_gf
+  int32_t n_groups, pad2;  // coupled three-phase groups
+  int64_t groups;  // first entry of group_tab
+  int64_t mptr;    // mutual stamps by row of L [n+1] (int32), into ment
+  int64_t ment;    // mutual stamps: (L position, local branch << 1 | negative) pairs (int32)
+};
+
+// One coupled three-phase group: its members' local branches and terminals
+// (a grounded terminal is the item's zero node slot n) and the sign of its
+// Gamma (+1: R-L, Gamma = G; -1: C, Gamma = -G).
+struct GroupDesc {
+  int32_t b[3], k[3], m[3], sgn;
 };
 
 // One distributed-parameter line: its two local branches (k end, m end),
@@ -156,6 +169,14 @@ struct DevCtx {
   const LineDesc *line_tab;
   const double *line_gf;
   double *ring;
+  // coupled groups: descriptors, mutual stamps, per-branch mutual values and
+  // member flags, and the mutual companion coefficients g_o, beta_o per
+  // (topology, branch) beside cg, cb
+  const GroupDesc *group_tab;
+  const int32_t *mptr, *ment;
+  const double *bRm, *bLm, *bCm;
+  const int32_t *bgrp;
+  double *cgo, *cbo;
 };
 
 }  // namespace emt

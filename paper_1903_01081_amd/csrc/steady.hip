@@ -32,14 +32,33 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-// Discrete admittance of local branch b of an item in topology 0.
-__device__ __forceinline__ cplx admittance(const DevCtx &c, const ItemDesc &it, int b, cplx z) {
-  const double g = c.cg[it.coef + b], be = c.cb[it.coef + b];
-  const uint32_t cls = c.bpack[it.br + b] >> 30;
-  const double gam = cls == GAMMA_PLUS_G ? g : (cls == GAMMA_MINUS_G ? -g : 0.0);
+// Scalar discrete admittance (g z + gamma) / (z - beta).
+__device__ __forceinline__ cplx scalar_admittance(double g, double gam, double be, cplx z) {
   const cplx num = {g * z.re + gam, g * z.im};
   const cplx den = {z.re - be, z.im};
   return (g == 0.0 && gam == 0.0) ? cplx{0.0, 0.0} : cdiv(num, den);
+}
+
+// Discrete admittance of local branch b of an item in topology 0; for a
+// member of a coupled group (class "pass": lines are refused before this
+// kernel runs) the diagonal of its circulant admittance, with the
+// off-diagonal in *mutual: per sequence (zero: d + 2o, positive: d - o) the
+// scalar admittance, then back to the circulant.
+__device__ __forceinline__ cplx admittance(const DevCtx &c, const ItemDesc &it, int b, cplx z,
+                                           cplx *mutual = nullptr) {
+  const double g = c.cg[it.coef + b], be = c.cb[it.coef + b];
+  const uint32_t cls = c.bpack[it.br + b] >> 30;
+  if (cls == GAMMA_PASS) {
+    const double go = c.cgo[it.coef + b], bo = c.cbo[it.coef + b];
+    const double sg = c.bkind[it.br + b] == KIND_C ? -1.0 : 1.0;
+    const cplx y0 = scalar_admittance(g + 2.0 * go, sg * (g + 2.0 * go), be + 2.0 * bo, z);
+    const cplx y1 = scalar_admittance(g - go, sg * (g - go), be - bo, z);
+    if (mutual) *mutual = {(y0.re - y1.re) / 3.0, (y0.im - y1.im) / 3.0};
+    return {(y0.re + 2.0 * y1.re) / 3.0, (y0.im + 2.0 * y1.im) / 3.0};
+  }
+  if (mutual) *mutual = {0.0, 0.0};
+  const double gam = cls == GAMMA_PLUS_G ? g : (cls == GAMMA_MINUS_G ? -g : 0.0);
+  return scalar_admittance(g, gam, be, z);
 }
 
 // Source phasor E exp(j phase) of local branch b (0 for other branches).
@@ -92,6 +111,18 @@ __global__ __launch_bounds__(BS) void k_steady(DevCtx c, const int64_t *off_l, c
       }
       D[r] = d;
       x[r] = rhs;
+      if (it.n_groups > 0) {
+        // mutual admittances of coupled groups (+y_o between like terminals
+        // of two members, -y_o between a k and an m terminal)
+        const int32_t *mp = c.mptr + it.mptr;
+        const int32_t *me = c.ment + it.ment;
+        for (int e = mp[r]; e < mp[r + 1]; ++e) {
+          const int pos = me[2 * e], code = me[2 * e + 1];
+          cplx yo;
+          admittance(c, it, code >> 1, z, &yo);
+          L[pos] = (code & 1) ? csub(L[pos], yo) : cadd(L[pos], yo);
+        }
+      }
     }
     __syncthreads();
     // LDL^T by the factorisation's levels: pivots of a level's rows, then the
@@ -172,11 +203,32 @@ __global__ __launch_bounds__(BS) void k_steady(DevCtx c, const int64_t *off_l, c
       // no source in the item: at rest, u = -e(0) = 0
       uv = 0.0;
     }
-    c.si[gb] = iv;
+    // a coupled member's current needs the other members' voltages: the
+    // group loop below writes it
+    if (!(driven && (c.bpack[gb] >> 30) == GAMMA_PASS)) c.si[gb] = iv;
     c.su[gb] = uv;
     if (c.K > 0) {
       c.ck_i[it.ck + b] = iv;
       c.ck_u[it.ck + b] = uv;
+    }
+  }
+  if (it.n_groups > 0 && driven) {
+    // members of coupled groups: i_p = y_d u_p + y_o (S_u - u_p) (members
+    // carry no source; coupled groups take no checkpoints)
+    for (int q = threadIdx.x; q < it.n_groups; q += BS) {
+      const GroupDesc gd = c.group_tab[it.groups + q];
+      cplx u[3], su = {0.0, 0.0};
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const cplx vk = gd.k[p] < n ? x[gd.k[p]] : cplx{0.0, 0.0};
+        const cplx vm = gd.m[p] < n ? x[gd.m[p]] : cplx{0.0, 0.0};
+        u[p] = csub(vk, vm);
+        su = cadd(su, u[p]);
+      }
+      cplx yo;
+      const cplx yd = admittance(c, it, gd.b[0], z, &yo);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) c.si[it.br + gd.b[p]] = cadd(cmul(yd, u[p]), cmul(yo, csub(su, u[p]))).re;
     }
   }
 }

@@ -487,19 +487,20 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
   for (int j = 0; j < BPT; ++j) {
     const int b = tid + j * BS;
     const uint32_t pk = L.pk[j];
-    // a line end's history is its injection in every slot (no source there),
-    // and the line pass, not this update, writes its next injection
-    const bool line = (pk >> 30) == GAMMA_LINE;
+    // a line end's or a coupled member's history is its injection in every
+    // slot (no source there), and a pass after this update, not the update,
+    // writes its next injection and its stored state
+    const bool line = (pk >> 30) == GAMMA_PASS;
     const double vk = v.x[pk & kTermGround], vm = v.x[(pk >> 15) & kTermGround];
     const double e = j == 0 ? L.e0 : 0.0;
     const double h = (j == 0 && !line) ? L.h0 : -v.J[b];
     const double u = (L.g[j] != 0.0) ? (vk - vm) - e : 0.0;
     const double i = L.g[j] * u + h;
-    if (st_i) {
+    if (st_i && !line) {
       st_i[b] = i;
       st_u[b] = u;
     }
-    if (st2_i) {
+    if (st2_i && !line) {
       st2_i[b] = i;
       st2_u[b] = u;
     }
@@ -527,7 +528,7 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
 // injections of step n + 1 written; otherwise only those of step n.
 template <int BS, bool SM>
 __device__ __forceinline__ void line_pass(const DevCtx &c, const ItemDesc &it, const View<SM> &v, int64_t n,
-                                          bool advance) {
+                                          bool advance, double *st_i, double *st_u) {
   for (int q = lane_id(); q < it.n_lines; q += BS) {
     const LineDesc ld = c.line_tab[it.lines + q];
     const double g = c.line_gf[2 * (it.lines + q)], f = c.line_gf[2 * (it.lines + q) + 1];
@@ -538,6 +539,12 @@ __device__ __forceinline__ void line_pass(const DevCtx &c, const ItemDesc &it, c
       const double ik = g * vk - v.J[ld.bk], im = g * vm - v.J[ld.bm];
       rk[n & ld.mask] = g * vk + ik;
       rm[n & ld.mask] = g * vm + im;
+      if (st_i) {  // each end's current into the line and its voltage
+        st_i[ld.bk] = ik;
+        st_u[ld.bk] = vk;
+        st_i[ld.bm] = im;
+        st_u[ld.bm] = vm;
+      }
       m = n + 1;
     }
     const int64_t j0 = m - ld.d0, j1 = j0 - 1;
@@ -545,6 +552,57 @@ __device__ __forceinline__ void line_pass(const DevCtx &c, const ItemDesc &it, c
     const double m0 = j0 > 0 ? rm[j0 & ld.mask] : 0.0, m1 = j1 > 0 ? rm[j1 & ld.mask] : 0.0;
     v.J[ld.bk] = (1.0 - f) * m0 + f * m1;
     v.J[ld.bm] = (1.0 - f) * k0 + f * k1;
+  }
+}
+
+// Coupled three-phase groups, one lane per group. A member's current and
+// history involve all three members through the circulant companion: with
+// the group sums S_u, S_i,
+//   i_p  = g u_p + g_o (S_u - u_p) + h_p,
+//   h'_p = beta i_p + sgn g u_p + beta_o (S_i - i_p) + sgn g_o (S_u - u_p),
+// sgn = +1 for R-L and -1 for C groups. Members carry no source (u = v_k -
+// v_m); the branch update leaves their injections and stored state to this
+// pass, which reads h_p = -J and writes J = -h'_p (when inj) and the state
+// (when st_i is set). With init, (i, u) are the stored state instead (the
+// start of a launch) and only the injections are written. The members take
+// no events, so the coefficients of topology 0 hold in every topology.
+template <int BS, bool SM>
+__device__ __forceinline__ void group_pass(const DevCtx &c, const ItemDesc &it, const View<SM> &v, bool init,
+                                           bool inj, double *st_i, double *st_u) {
+  for (int q = lane_id(); q < it.n_groups; q += BS) {
+    const GroupDesc gd = c.group_tab[it.groups + q];
+    const int64_t k0 = it.coef + gd.b[0];
+    const double g = c.cg[k0], go = c.cgo[k0], be = c.cb[k0], bo = c.cbo[k0];
+    const double sg = (double)gd.sgn;
+    double u[3], i[3];
+    if (init) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        u[p] = c.su[it.br + gd.b[p]];
+        i[p] = c.si[it.br + gd.b[p]];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) u[p] = v.x[gd.k[p]] - v.x[gd.m[p]];
+      const double su = u[0] + u[1] + u[2];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) i[p] = (g * u[p] - v.J[gd.b[p]]) + go * (su - u[p]);
+      if (st_i) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          st_i[gd.b[p]] = i[p];
+          st_u[gd.b[p]] = u[p];
+        }
+      }
+    }
+    if (init || inj) {
+      const double su = u[0] + u[1] + u[2], si = i[0] + i[1] + i[2];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const double h = (be * i[p] + sg * g * u[p]) + (bo * (si - i[p]) + sg * go * (su - u[p]));
+        v.J[gd.b[p]] = -h;
+      }
+    }
   }
 }
 
@@ -567,9 +625,10 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   select_factor<BS, WPT, SM>(c, it, v, t, w);
   inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
-  const bool lines = it.n_lines > 0;
-  if (lines) {
-    line_pass<BS, SM>(c, it, v, n0 + 1, false);
+  const bool lines = it.n_lines > 0, groups = it.n_groups > 0;
+  if (lines || groups) {
+    if (lines) line_pass<BS, SM>(c, it, v, n0 + 1, false, nullptr, nullptr);
+    if (groups) group_pass<BS, SM>(c, it, v, true, true, nullptr, nullptr);
     lds_barrier();
   }
   const int R = c.rec_stride;
@@ -594,9 +653,10 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
     }
     update_inject<BS, BPT, SM>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
                                n < n_end, n);
-    if (lines) {
+    if (lines || groups) {
       lds_barrier();
-      line_pass<BS, SM>(c, it, v, n, true);
+      if (lines) line_pass<BS, SM>(c, it, v, n, true, st_i, st_u);
+      if (groups) group_pass<BS, SM>(c, it, v, false, n < n_end, st_i, st_u);
     }
     if (sw) {
       ++t;

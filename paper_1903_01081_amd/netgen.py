@@ -294,20 +294,22 @@ def config0(seed: int = 0, n_steps: int = 4000):
 
 
 def config1(seed: int = 1, n_bus: int = 1000, n_steps: int = 50000,
-            fault_step: Optional[int] = None, travelling_wave: bool = False):
+            fault_step: Optional[int] = None, travelling_wave: bool = False,
+            coupled: bool = False):
     """1000-bus grid (3000 nodes), 1500 lines, 200 sources, 600 loads,
     dt = 20 us, 1 s, one fault at mid-horizon, all nodes recorded.
     travelling_wave: the same draw with every line whose travel time is at
     least one step entered as distributed-parameter lines (see
-    three_phase_grid)."""
+    three_phase_grid). coupled: the same draw with coupled three-phase
+    lines (one component of 3 n_bus nodes)."""
     rng = np.random.default_rng(seed)
     dt = 20e-6
     n_lines = int(round(1.5 * n_bus))
     ev = n_steps // 2 if fault_step is None else fault_step
     bld, info = three_phase_grid(rng, n_bus, n_lines, int(round(0.2 * n_bus)),
                                  int(round(0.6 * n_bus)),
-                                 travelling_wave_dt=dt if travelling_wave else None)
-    name = f"grid{n_bus}" + ("-tw" if travelling_wave else "")
+                                 travelling_wave_dt=dt if travelling_wave else None, coupled=coupled)
+    name = f"grid{n_bus}" + ("-tw" if travelling_wave else "") + ("-coupled" if coupled else "")
     net = bld.network(_fault_events(info, ev), None, n_lines, dict(info, name=name))
     return [net], dict(dt=dt, n_steps=n_steps)
 
