@@ -69,7 +69,7 @@
 
 namespace {
 
-enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4, K_LINE = 5 };
+enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4, K_LINE = 5, K_DIODE = 6 };
 
 }  // namespace
 
@@ -331,7 +331,9 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
     const int k = net.k[b], m = net.m[b];
     if (k < -1 || k >= net.n_nodes || m < -1 || m >= net.n_nodes) return false;
     if (k < 0 && m < 0) return false;
-    if (net.kind[b] < 0 || net.kind[b] > 5) return false;
+    if (net.kind[b] < 0 || net.kind[b] > 6) return false;
+    if (net.kind[b] == K_DIODE && (!(net.R[b] > 0) || net.line[b] >= 0 || (net.group && net.group[b] >= 0)))
+      return false;
     if (net.kind[b] == K_LINE &&
         (k < 0 || m < 0 || k == m || !(net.R[b] > 0) || !(net.L[b] >= dt) || net.C[b] != 0.0 || net.line[b] >= 0))
       return false;
@@ -339,7 +341,7 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
   for (int j = 0; j < net.n_events; ++j) {
     if (net.ev_step[j] < 1) return false;
     if (net.ev_branch[j] < 0 || net.ev_branch[j] >= net.n_branches) return false;
-    if (net.kind[net.ev_branch[j]] == K_LINE) return false;
+    if (net.kind[net.ev_branch[j]] == K_LINE || net.kind[net.ev_branch[j]] == K_DIODE) return false;
   }
   for (int r = 0; r < net.n_rec; ++r)
     if (net.rec_nodes && (net.rec_nodes[r] < 0 || net.rec_nodes[r] >= net.n_nodes)) return false;
@@ -373,6 +375,12 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
 }
 
 bool has_groups(const OracleNet &net) { return !group_members(net).empty(); }
+
+bool has_diodes(const OracleNet &net) {
+  for (int b = 0; b < net.n_branches; ++b)
+    if (net.kind[b] == K_DIODE) return true;
+  return false;
+}
 
 inline int rec_node(const OracleNet &net, int r) { return net.rec_nodes ? net.rec_nodes[r] : r; }
 
@@ -462,9 +470,15 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
                    [&](int a, int b) { return net.ev_step[a] < net.ev_step[b]; });
   size_t next_ev = 0;
   int topo = 0;
+  // ideal diodes (state-dependent switches): a conducting diode (1/R_on)
+  // whose current is negative after a step blocks from the next step on; a
+  // blocking one whose voltage v_k - v_m is positive conducts from the next
+  // step on
+  bool flipped = false;
 
   for (int64_t n = 1; n <= Tn; ++n) {
-    bool changed = false;
+    bool changed = flipped;
+    flipped = false;
     while (next_ev < ev.size() && net.ev_step[ev[next_ev]] == n) {
       const int j = ev[next_ev++];
       ins[net.ev_branch[j]] = net.ev_in_service[j] ? 1 : 0;
@@ -529,6 +543,18 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
       for (int q : mem) su += u[q];
       for (int p : mem) i[p] += c.go[p] * (su - u[p]);
     }
+    for (int b = 0; b < B; ++b) {
+      if (net.kind[b] != K_DIODE) continue;
+      const T vk = net.k[b] >= 0 ? v[net.k[b]] : T(0);
+      const T vm = net.m[b] >= 0 ? v[net.m[b]] : T(0);
+      if (ins[b] && re(i[b]) < 0.0) {
+        ins[b] = 0;
+        flipped = true;
+      } else if (!ins[b] && re(vk - vm) > 0.0) {
+        ins[b] = 1;
+        flipped = true;
+      }
+    }
     for (size_t q = 0; q < waves.lines.size(); ++q) {
       const int b = waves.lines[q];
       const T g = c.g[b], vk = v[net.k[b]], vm = v[net.m[b]];
@@ -559,7 +585,7 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
 // lines, sources at different frequencies) or 2 (singular).
 int steady_state(const OracleNet &net, const double *theta, double dt, double *v0, double *i0, double *Vre,
                  double *Vim) {
-  if (!valid(net, dt, 1) || has_lines(net)) return 1;
+  if (!valid(net, dt, 1) || has_lines(net) || has_diodes(net)) return 1;
   const int N = net.n_nodes, B = net.n_branches;
   double w = 0.0;
   bool any = false;
@@ -695,7 +721,7 @@ int oracle_loss_complex(const OracleNet *net, const double *theta_re, const doub
 int oracle_adjoint(const OracleNet *net, const double *theta, double dt, int64_t T,
                    const double *dJ_drec, double *grad, double *gbar_out,
                    double *betabar_out, double *gammabar_out) {
-  if (has_lines(*net) || has_groups(*net)) return 1;  // lines and coupled groups run forward only
+  if (has_lines(*net) || has_groups(*net) || has_diodes(*net)) return 1;  // forward only
   const int N = net->n_nodes, B = net->n_branches;
   std::vector<double> i_traj((size_t)(T + 1) * B), u_traj((size_t)(T + 1) * B);
   std::vector<int> topo_of_step;

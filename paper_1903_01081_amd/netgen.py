@@ -37,8 +37,10 @@ import numpy as np
 
 # Branch kinds; the integer codes are part of the C interface. LINE is a
 # distributed-parameter (travelling-wave) line: R = surge impedance Z,
-# L = travel time tau.
-RL, CAP, RES, SWITCH, SRC, LINE = 0, 1, 2, 3, 4, 5
+# L = travel time tau. DIODE is an ideal diode (state-dependent switch):
+# R = on-resistance, conducting from k to m while its current is positive,
+# blocking while its voltage v_k - v_m is not.
+RL, CAP, RES, SWITCH, SRC, LINE, DIODE = 0, 1, 2, 3, 4, 5, 6
 
 F_HZ = 60.0
 R_SRC = 0.5          # Thevenin source resistance per phase [ohm]
