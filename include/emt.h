@@ -73,7 +73,9 @@ typedef enum {
   EMT_ESTATE = 5      /* call out of order (see each call) */
 } emt_status;
 
-typedef enum { EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5 } emt_kind;
+typedef enum {
+  EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5, EMT_DIODE = 6
+} emt_kind;
 
 typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 } emt_solver;
 
@@ -94,6 +96,19 @@ typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 
  *              lines runs forward only (EMT_EINVAL with checkpoint_every >
  *              0 or with components split over workgroups) and takes no
  *              emt_set_state.
+ *              DIODE (an ideal diode, a state-dependent switch): R = its
+ *              on-resistance > 0, conducting from k to m. in_service0 is
+ *              its initial state; after every step a conducting diode
+ *              whose current is negative blocks from the next step on and a
+ *              blocking one whose voltage v_k - v_m is positive conducts
+ *              from the next step on, the conductance matrix being
+ *              refactorised inside the time loop (one-workgroup solvers,
+ *              sweeps without a dense tail). Diodes take no events; a batch
+ *              with diodes runs forward only (EMT_EINVAL with checkpoints,
+ *              the dense solver or emt_steady_state). The plain trapezoidal
+ *              rule rings when a diode interrupts an inductor's current, so
+ *              a diode can chatter after it blocks (no damping step is
+ *              added).
  *   E, omega, phase  source EMF E cos(omega t + phase); read for EMT_SRC only.
  *   line       pi-section line index l of the branch, or -1. Line parameters
  *              theta[3l + {0,1,2}] = (R_l, L_l, C_l) are the series R and L

@@ -41,7 +41,7 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (k < -1 || k >= n.n_nodes || m < -1 || m >= n.n_nodes)
       fail(EMT_EINVAL, where(s, "branch terminal out of range", b));
     if (k == m) fail(EMT_EINVAL, where(s, "branch with both terminals equal (or both ground)", b));
-    if (kd < EMT_RL || kd > EMT_LINE) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
+    if (kd < EMT_RL || kd > EMT_DIODE) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
     const double R = n.R[b], L = n.L[b], C = n.C[b];
     switch (kd) {
       case EMT_RL:
@@ -56,6 +56,14 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
         break;
       case EMT_C:
         if (!finite(C) || !(C > 0)) fail(EMT_EINVAL, where(s, "capacitor needs C > 0", b));
+        break;
+      case EMT_DIODE:
+        if (!finite(R) || !(R > 0)) fail(EMT_EINVAL, where(s, "a diode needs its on-resistance R > 0", b));
+        if (sim.checkpoint_every > 0)
+          fail(EMT_EINVAL, where(s, "diodes run forward only (no checkpoints)", b));
+        if (sim.solver == EMT_SOLVER_DENSE)
+          fail(EMT_EINVAL, where(s, "diodes need the sweep solvers (auto or sparse), refactorised in the loop", b));
+        if (n.group && n.group[b] >= 0) fail(EMT_EINVAL, where(s, "a diode cannot belong to a coupled group", b));
         break;
       case EMT_LINE:
         if (k < 0 || m < 0) fail(EMT_EINVAL, where(s, "a line joins two nodes (neither end at ground)", b));
@@ -85,6 +93,8 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (n.ev_in_service[j] > 1) fail(EMT_EINVAL, where(s, "ev_in_service must be 0 or 1", j));
     if (n.kind[n.ev_branch[j]] == EMT_LINE)
       fail(EMT_EINVAL, where(s, "distributed-parameter lines take no switching events", j));
+    if (n.kind[n.ev_branch[j]] == EMT_DIODE)
+      fail(EMT_EINVAL, where(s, "diodes switch by their own state, not by events", j));
   }
   if (n.group) {
     if (!n.Rm || !n.Lm || !n.Cm) fail(EMT_EINVAL, where(s, "coupled groups need Rm, Lm and Cm"));
@@ -465,6 +475,9 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
     std::vector<uint8_t> ever(B, 0);
     for (int t = 0; t < sc.n_topo; ++t)
       for (int b = 0; b < B; ++b) ever[b] |= sc.ins[t][b];
+    // a diode may conduct at any step, whatever its initial state
+    for (int b = 0; b < B; ++b)
+      if (net.kind[b] == EMT_DIODE) ever[b] = 1;
     DSU d(N);
     for (int b = 0; b < B; ++b)
       if (ever[b] && net.k[b] >= 0 && net.m[b] >= 0) d.join(net.k[b], net.m[b]);

@@ -595,10 +595,18 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<char> sym_split(A.syms.size(), 0);
   for (int q = 0; q < NI; ++q)
     if (c.is_split[q]) sym_split[A.items[q].sym] = 1;
+  // items with diodes refactorise inside the time loop: sweeps only (the
+  // dense tail's inverse would have to be recomputed there too)
+  std::vector<char> sym_diode(A.syms.size(), 0);
+  for (int q = 0; q < NI; ++q) {
+    const Item &it = A.items[q];
+    for (int b : it.br)
+      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) sym_diode[it.sym] = 1;
+  }
   for (size_t q = 0; q < A.syms.size(); ++q) {
     const int n = A.syms[q].n;
     int d;
-    if (sym_split[q]) {
+    if (sym_split[q] || sym_diode[q]) {
       d = 0;  // factor values only; the split kernels use the explicit inverse
     } else if (solver == EMT_SOLVER_SPARSE) {
       d = 0;
@@ -619,7 +627,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     for (const Item &it : A.items) {
       if (c.is_split[&it - &A.items[0]]) continue;
       SweepPlan &P = plans[it.sym];
-      if (item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
+      if (!sym_diode[it.sym] && item_lds(it, false) > (size_t)max_lds && P.d < std::min(c.ks.dmax, it.n))
         P = plan_sweeps(A.syms[it.sym], std::min(c.ks.dmax, it.n));
     }
   }
@@ -759,6 +767,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   std::vector<int32_t> bk, bm, bgpos, bscen, bitem, blocal, nptr, rptr;
   std::vector<uint16_t> nent, rnode, rcolumn;
   int64_t coef_off = 0, fac_off = 0, dfac_off = 0, sv_off = 0, w_off = 0, ck_off = 0, seg_off = 0, node_off = 0;
+  int64_t dyn_off = 0;
   std::vector<GroupDesc> group_tab;
   std::vector<int32_t> mptr_all, ment_all;
   std::vector<LineDesc> line_tab;
@@ -796,6 +805,11 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.topo = scen_topo_off[it.scen];
     d.ck = ck_off;
     d.seg = seg_off;
+    d.n_diodes = 0;
+    for (int b : it.br)
+      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) d.n_diodes++;
+    d.dyn = dyn_off;
+    if (d.n_diodes > 0) dyn_off += (int64_t)it.n_br + S.nnz() + 2 * (int64_t)it.n + plans[it.sym].nsv();
     d.n_groups = (int32_t)(it.grp_b.size() / 3);
     d.groups = (int64_t)group_tab.size();
     for (size_t g = 0; g + 2 < it.grp_b.size(); g += 3) {
@@ -980,6 +994,10 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   dc.line_gf = line_gf.empty() ? nullptr : c.upload(line_gf);
   dc.ring = ring_off > 0 ? c.alloc<double>(ring_off) : nullptr;
   c.ring_doubles = ring_off;
+  if (dyn_off > 0) {
+    dc.dyn = c.alloc<double>(dyn_off);
+    dc.dstate = c.alloc<int32_t>(c.nbr_total);
+  }
   if (!group_tab.empty()) {
     // per-branch mutual values and member flags, in the branch arrays' order
     std::vector<double> bRm, bLm, bCm;
@@ -1005,8 +1023,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     dc.cgo = c.alloc<double>(coef_off);
     dc.cbo = c.alloc<double>(coef_off);
   }
-  dc.flags = c.alloc<int32_t>(4);
-  hip_check(launch_fill_i32(dc.flags, 4, 0, nullptr), "clear flags");
+  dc.flags = c.alloc<int32_t>(8);
+  hip_check(launch_fill_i32(dc.flags, 8, 0, nullptr), "clear flags");
   dc.dt = sim.dt;
   dc.T = T;
   dc.K = K;
@@ -1126,6 +1144,14 @@ static void report_all(emt_ctx &c) {
     c.adjoint_pending = false;
     if (read_flag(c.dc.flags + 2) != 0)
       throw emt::Error{EMT_EDEVICE, "the pipelined adjoint gave up waiting for its recompute workgroups"};
+  }
+  if (c.dc.dyn) {
+    // pivots of the factorisations inside the time loop (diode changes)
+    const int32_t bad = read_flag(c.dc.flags + 4);
+    if (bad != 0) {
+      hip_check(emt::launch_fill_i32(c.dc.flags + 4, 1, 0, nullptr), "clear flag");
+      throw emt::Error{EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots in the loop"};
+    }
   }
 }
 
@@ -1386,6 +1412,7 @@ emt_status emt_steady_state(emt_ctx *ctx, void *stream) {
     for (const emt::Item &it : ctx->A.items)
       if (!it.line_bk.empty())
         return set_error(EMT_EINVAL, "distributed-parameter lines start from rest (no steady state)");
+    if (ctx->dc.dyn) return set_error(EMT_EINVAL, "diodes switch by their own state (no steady state)");
     for (size_t q = 0; q < ctx->scen_mixed_freq.size(); ++q)
       if (ctx->scen_mixed_freq[q])
         return set_error(EMT_EINVAL, "scenario " + std::to_string(q) +

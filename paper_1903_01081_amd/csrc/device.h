@@ -8,7 +8,7 @@
 
 namespace emt {
 
-enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4, KIND_LINE = 5 };
+enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4, KIND_LINE = 5, KIND_DIODE = 6 };
 
 // Packed branch descriptor for the step kernels: local terminals in 15 bits
 // each (a grounded terminal holds the node count n: the step kernels keep a
@@ -61,6 +61,9 @@ struct ItemDesc {
   int64_t groups;  // first entry of group_tab
   int64_t mptr;    // mutual stamps by row of L [n+1] (int32), into ment
   int64_t ment;    // mutual stamps: (L position, local branch << 1 | negative) pairs (int32)
+  int32_t n_diodes, pad3;  // ideal diodes (state-dependent switches)
+  int64_t dyn;     // items with diodes: the factor refreshed inside the time loop, in DevCtx::dyn:
+                   // current conductances [n_br], L [nnz], D [n], sweep values [nsv], 1/D [n]
 };
 
 // One coupled three-phase group: its members' local branches and terminals
@@ -177,6 +180,10 @@ struct DevCtx {
   const double *bRm, *bLm, *bCm;
   const int32_t *bgrp;
   double *cgo, *cbo;
+  // ideal diodes: the dynamic factor slots and the conducting state per
+  // branch (meaningful for diode branches)
+  double *dyn;
+  int32_t *dstate;
 };
 
 }  // namespace emt

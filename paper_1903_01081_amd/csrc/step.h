@@ -606,6 +606,149 @@ __device__ __forceinline__ void group_pass(const DevCtx &c, const ItemDesc &it, 
   }
 }
 
+// Ideal diodes (state-dependent switches). A diode is a resistive branch
+// whose conductance is 1/R_on while it conducts and 0 while it blocks; its
+// state lives in c.dstate and changes after a step (a conducting diode whose
+// current g u went negative blocks, a blocking one whose voltage v_k - v_m
+// went positive conducts), taking effect from the next step. dmask marks a
+// lane's diode slots. Returns the slots that change; their new state is
+// stored at once, their conductance only after the branch update of this
+// step (which still uses the old one).
+template <int BS, int BPT, bool SM>
+__device__ __forceinline__ uint32_t diode_flips(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
+                                                const Lane<BPT> &L, uint32_t dmask) {
+  uint32_t fl = 0;
+  const int tid = lane_id();
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (!((dmask >> j) & 1u)) continue;
+    const uint32_t pk = L.pk[j];
+    const double du = v.x[pk & kTermGround] - v.x[(pk >> 15) & kTermGround];
+    const bool on = L.g[j] != 0.0;
+    const bool next = on ? !(L.g[j] * du < 0.0) : (du > 0.0);
+    if (next != on) {
+      fl |= 1u << j;
+      c.dstate[it.br + tid + j * BS] = next ? 1 : 0;
+    }
+  }
+  return fl;
+}
+
+// The diode slots' conductances from their stored state.
+template <int BS, int BPT>
+__device__ __forceinline__ void diode_conductances(const DevCtx &c, const ItemDesc &it, Lane<BPT> &L,
+                                                   uint32_t dmask) {
+  const int tid = lane_id();
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) {
+    if (!((dmask >> j) & 1u)) continue;
+    const int64_t gb = it.br + tid + j * BS;
+    L.g[j] = c.dstate[gb] ? 1.0 / c.bR[gb] : 0.0;
+    L.be[j] = 0.0;
+  }
+}
+
+// The factor of an item with diodes for its current conductances (the
+// lanes' L.g), computed inside the time loop into the item's dynamic slot:
+// G on the item's symbolic pattern (with any coupled groups' mutual
+// stamps), LDL^T by the factorisation's levels (the same arithmetic as the
+// factorisation before the loop), then the sweep values and 1/D, which the
+// sweeps then read (staged into LDS under SM). Such items have no dense
+// tail. Non-positive pivots are counted in c.flags[4].
+template <int BS, int BPT, bool SM>
+__device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &v, const Lane<BPT> &L) {
+  const SymDesc sd = c.syms[it.sym];
+  const int n = it.n;
+  double *gcur = c.dyn + it.dyn;
+  double *Lr = gcur + it.n_br;
+  double *D = Lr + sd.nnz;
+  double *sv = D + n;
+  double *di = sv + sd.nsv;
+  const int32_t *rowptr = c.symi + sd.rowptr, *rowcol = c.symi + sd.rowcol;
+  const int32_t *colrow = c.symi + sd.colrow, *colpos = c.symi + sd.colpos;
+  const int32_t *flevptr = c.symi + sd.flevptr, *flevrows = c.symi + sd.flevrows;
+  const int32_t *fentptr = c.symi + sd.fentptr, *fent = c.symi + sd.fent;
+  const int32_t *svmap = c.symi + sd.svmap;
+  const int32_t *nptr = c.nptr + it.nptr;
+  const uint16_t *nent = c.nent + it.nent;
+  const int32_t *bk = c.bk + it.br, *bm = c.bm + it.br, *gpos = c.bgpos + it.br;
+  const int tid = lane_id();
+#pragma unroll
+  for (int j = 0; j < BPT; ++j) gcur[tid + j * BS] = L.g[j];
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += BS) {
+    for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) Lr[q] = 0.0;
+    double d = 0.0;
+    for (int e = nptr[r]; e < nptr[r + 1]; ++e) {
+      const int ent = nent[e];
+      const int b = ent >> 1;
+      const double gv = gcur[b];
+      d = d + gv;
+      const int other = (ent & 1) ? bk[b] : bm[b];
+      if (other >= 0 && other < r) Lr[gpos[b]] = Lr[gpos[b]] - gv;
+    }
+    D[r] = d;
+    if (it.n_groups > 0) {
+      const int32_t *mp = c.mptr + it.mptr;
+      const int32_t *me = c.ment + it.ment;
+      const double *go = c.cgo + it.coef;
+      for (int e = mp[r]; e < mp[r + 1]; ++e) {
+        const int pos = me[2 * e], code = me[2 * e + 1];
+        const double gv = go[code >> 1];
+        Lr[pos] = (code & 1) ? Lr[pos] - gv : Lr[pos] + gv;
+      }
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < sd.nlev; ++l) {
+    for (int p = flevptr[l] + threadIdx.x; p < flevptr[l + 1]; p += BS) {
+      const int j = flevrows[p];
+      double d = D[j];
+      for (int q = rowptr[j]; q < rowptr[j + 1]; ++q) {
+        const double ljk = Lr[q];
+        d = d - ljk * ljk * D[rowcol[q]];
+      }
+      D[j] = d;
+      if (!(d > 0.0) || !isfinite(d)) atomicAdd(c.flags + 4, 1);
+    }
+    __syncthreads();
+    for (int p = fentptr[l] + threadIdx.x; p < fentptr[l + 1]; p += BS) {
+      const int e = fent[p];
+      const int i = colrow[e];
+      const int pos = colpos[e];
+      const int j = rowcol[pos];
+      double s = Lr[pos];
+      int qi = rowptr[i], qj = rowptr[j];
+      const int qi1 = rowptr[i + 1], qj1 = rowptr[j + 1];
+      while (qi < qi1 && qj < qj1) {
+        const int ci = rowcol[qi], cj = rowcol[qj];
+        if (ci >= j) break;
+        if (ci == cj) {
+          s = s - Lr[qi] * D[ci] * Lr[qj];
+          ++qi;
+          ++qj;
+        } else if (ci < cj) {
+          ++qi;
+        } else {
+          ++qj;
+        }
+      }
+      Lr[pos] = s / D[j];
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < sd.nsv; q += BS) sv[q] = Lr[svmap[q]];
+  for (int r = threadIdx.x; r < n; r += BS) di[r] = 1.0 / D[r];
+  __syncthreads();
+  if constexpr (SM) {
+    copy_to<BS>(v.sv_s.off, sv, v.nsv);
+    copy_to<BS>(v.dinv_s.off, di, v.ns);
+  } else {
+    v.sv.p = sv;
+    v.dinv.p = di;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Forward loop: steps n0+1 .. n0+nsteps for every item.
 // ---------------------------------------------------------------------------
@@ -621,8 +764,23 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
+  const bool diodes = it.n_diodes > 0;
+  uint32_t dmask = 0;
+  if (diodes) {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j)
+      if (c.bkind[it.br + threadIdx.x + j * BS] == KIND_DIODE) dmask |= 1u << j;
+    diode_conductances<BS, BPT>(c, it, L, dmask);
+  }
   history_from_state<BS, BPT, SM>(c.si + it.br, c.su + it.br, L, v);
-  select_factor<BS, WPT, SM>(c, it, v, t, w);
+  if (diodes) {
+    // no dense tail: w stays zero
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) w[q] = 0.0;
+    refactor_dynamic<BS, BPT, SM>(c, it, v, L);
+  } else {
+    select_factor<BS, WPT, SM>(c, it, v, t, w);
+  }
   inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
   const bool lines = it.n_lines > 0, groups = it.n_groups > 0;
@@ -641,6 +799,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       for (int q = lane_id(); q < v.nrec; q += BS) row[v.rcolumn[q]] = v.x[v.rnode[q]];
     }
     const bool sw = (n + 1 == next);
+    const uint32_t fl = diodes ? diode_flips<BS, BPT, SM>(c, it, v, L, dmask) : 0u;
     double *ck_i = nullptr, *ck_u = nullptr, *st_i = nullptr, *st_u = nullptr;
     if (c.K > 0 && n % c.K == 0) {
       const int64_t o = it.ck + (n / c.K) * (int64_t)v.nbr;
@@ -658,10 +817,18 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       if (lines) line_pass<BS, SM>(c, it, v, n, true, st_i, st_u);
       if (groups) group_pass<BS, SM>(c, it, v, false, n < n_end, st_i, st_u);
     }
+    if (diodes) {
+      // a diode changed state or the topology switched: the conductances
+      // of step n+1 and their factor, inside the loop
+      if (__syncthreads_or(fl != 0u) || sw) {
+        diode_conductances<BS, BPT>(c, it, L, dmask);
+        refactor_dynamic<BS, BPT, SM>(c, it, v, L);
+      }
+    }
     if (sw) {
       ++t;
       next = (t + 1 < it.n_topo) ? topo[t + 1] : kNever;
-      select_factor<BS, WPT, SM>(c, it, v, t, w);
+      if (!diodes) select_factor<BS, WPT, SM>(c, it, v, t, w);
     }
     lds_barrier();
   }

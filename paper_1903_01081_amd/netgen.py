@@ -46,6 +46,8 @@ F_HZ = 60.0
 R_SRC = 0.5          # Thevenin source resistance per phase [ohm]
 L_SRC = 10e-3        # Thevenin source inductance per phase [H]
 R_FAULT = 1e-3       # closed fault switch resistance [ohm]
+# diode-bridge loads: diode on-resistance, DC capacitor, DC-side reference
+R_DIODE_ON, C_DC, R_DC_REF = 1e-2, 100e-6, 1e6
 # coupled three-phase lines: mutual / self ratios of the circulant series R,
 # L and (negative) shunt C matrices
 COUPLING_R, COUPLING_L, COUPLING_C = 0.25, 0.4, 0.2
@@ -194,12 +196,19 @@ def random_lines(rng: np.random.Generator, n_bus: int, n_lines: int) -> np.ndarr
 def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
                      n_gen: int, n_load: int, *, fault_bus: Optional[int] = None,
                      fault_step: int = 0, rec_nodes=None, with_fault_switch=True,
-                     travelling_wave_dt: Optional[float] = None, coupled: bool = False):
+                     travelling_wave_dt: Optional[float] = None, coupled: bool = False,
+                     rectifiers: int = 0):
     """Draw one grid. Returns (builder, bookkeeping) so callers can add events.
 
     Branch order: for each line its 3 series R-L branches, then the 3 shunt
     capacitors at its first bus, then the 3 at its second bus; then 3 source
     branches per generator, 3 load branches per load, 3 fault switches.
+
+    rectifiers: the first this many loads also feed a six-pulse diode
+    bridge (ideal diodes, 10 mOhm on, starting blocked) whose DC side is a
+    resistor of twice the load's R in parallel with 100 uF, referenced to
+    ground through 1 MOhm at its negative node; each bridge adds two DC
+    nodes after the 3 n_bus AC nodes. No extra random draws.
 
     coupled: every line's three phases are coupled: its series R-L
     branches form one group with mutual Rm = 0.25 R, Lm = 0.4 L, and the
@@ -216,7 +225,7 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
     pi-sections; it is then not part of the parameter vector.
     """
     edges = random_lines(rng, n_bus, n_lines)
-    n_nodes = 3 * n_bus
+    n_nodes = 3 * n_bus + 2 * rectifiers
     bld = _Builder(n_nodes)
     series = np.zeros((n_lines, 3), np.int32)
     for l, (a, b) in enumerate(edges):
@@ -255,11 +264,19 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
         for p in range(3):
             bld.add(3 * int(g) + p, -1, SRC, R=R_SRC, L=L_SRC, E=mag, omega=w,
                     phase=phi - p * 2.0 * math.pi / 3.0)
-    for ld in loads:
+    for q, ld in enumerate(loads):
         R = rng.uniform(50.0, 200.0)
         L = rng.uniform(0.1, 0.5)
         for p in range(3):
             bld.add(3 * int(ld) + p, -1, RL, R=R, L=L)
+        if q < rectifiers:
+            P, N = 3 * n_bus + 2 * q, 3 * n_bus + 2 * q + 1
+            for p in range(3):
+                bld.add(3 * int(ld) + p, P, DIODE, R=R_DIODE_ON, ins=0)
+                bld.add(N, 3 * int(ld) + p, DIODE, R=R_DIODE_ON, ins=0)
+            bld.add(P, N, RES, R=2.0 * R)
+            bld.add(P, N, CAP, C=C_DC)
+            bld.add(N, -1, RES, R=R_DC_REF)
     fault_sw = []
     if with_fault_switch:
         if fault_bus is None:
@@ -297,21 +314,24 @@ def config0(seed: int = 0, n_steps: int = 4000):
 
 def config1(seed: int = 1, n_bus: int = 1000, n_steps: int = 50000,
             fault_step: Optional[int] = None, travelling_wave: bool = False,
-            coupled: bool = False):
+            coupled: bool = False, rectifiers: int = 0):
     """1000-bus grid (3000 nodes), 1500 lines, 200 sources, 600 loads,
     dt = 20 us, 1 s, one fault at mid-horizon, all nodes recorded.
     travelling_wave: the same draw with every line whose travel time is at
     least one step entered as distributed-parameter lines (see
     three_phase_grid). coupled: the same draw with coupled three-phase
-    lines (one component of 3 n_bus nodes)."""
+    lines (one component of 3 n_bus nodes). rectifiers: the same draw with
+    that many loads also feeding diode bridges."""
     rng = np.random.default_rng(seed)
     dt = 20e-6
     n_lines = int(round(1.5 * n_bus))
     ev = n_steps // 2 if fault_step is None else fault_step
     bld, info = three_phase_grid(rng, n_bus, n_lines, int(round(0.2 * n_bus)),
                                  int(round(0.6 * n_bus)),
-                                 travelling_wave_dt=dt if travelling_wave else None, coupled=coupled)
-    name = f"grid{n_bus}" + ("-tw" if travelling_wave else "") + ("-coupled" if coupled else "")
+                                 travelling_wave_dt=dt if travelling_wave else None, coupled=coupled,
+                                 rectifiers=rectifiers)
+    name = (f"grid{n_bus}" + ("-tw" if travelling_wave else "") + ("-coupled" if coupled else "")
+            + (f"-rect{rectifiers}" if rectifiers else ""))
     net = bld.network(_fault_events(info, ev), None, n_lines, dict(info, name=name))
     return [net], dict(dt=dt, n_steps=n_steps)
 
