@@ -566,6 +566,12 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
                                 " branches; the step kernel holds at most " + std::to_string(16 * bs)};
   c.ks.bs = bs;
   c.ks.bpt = bpt;
+  c.ks.ext = false;
+  for (const Item &it : A.items) {
+    if (!it.line_bk.empty() || !it.grp_b.empty()) c.ks.ext = true;
+    for (int b : it.br)
+      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) c.ks.ext = true;
+  }
   c.ks.dmax = tail_max(bs);
   // Pad every item's branch list to whole lane slots with inert branches, so
   // the step kernels need no per-slot bounds (each runs exactly bs * bpt

@@ -24,6 +24,7 @@ struct KernelShape {
   bool sm = true;  // index arrays and factors staged in LDS
   size_t lds_fwd = 0, lds_adj = 0;
   int dmax = 0;    // largest dense tail this block size supports
+  bool ext = false;  // the batch has distributed-parameter lines, coupled groups or diodes
 };
 
 struct CompanionArgs {

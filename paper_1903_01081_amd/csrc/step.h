@@ -477,7 +477,7 @@ __device__ __forceinline__ void inject(const DevCtx &c, const View<SM> &v, Lane<
 // coefficients; optional stores of (i, u) to up to two places (null = none);
 // if step n+1 starts a new topology its coefficients are loaded; the history
 // of step n+1; and, when inj is set, the injections of step n+1.
-template <int BS, int BPT, bool SM>
+template <int BS, int BPT, bool SM, bool PASS = false>
 __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v, Lane<BPT> &L, double *st_i,
                                               double *st_u, double *st2_i, double *st2_u, bool switch_next,
                                               int64_t next_coef, bool inj, int64_t n) {
@@ -489,8 +489,9 @@ __device__ __forceinline__ void update_inject(const DevCtx &c, const View<SM> &v
     const uint32_t pk = L.pk[j];
     // a line end's or a coupled member's history is its injection in every
     // slot (no source there), and a pass after this update, not the update,
-    // writes its next injection and its stored state
-    const bool line = (pk >> 30) == GAMMA_PASS;
+    // writes its next injection and its stored state (PASS: the batch has
+    // such branches; the kernels of other batches carry none of this)
+    const bool line = PASS && (pk >> 30) == GAMMA_PASS;
     const double vk = v.x[pk & kTermGround], vm = v.x[(pk >> 15) & kTermGround];
     const double e = j == 0 ? L.e0 : 0.0;
     const double h = (j == 0 && !line) ? L.h0 : -v.J[b];
@@ -752,7 +753,9 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
 // ---------------------------------------------------------------------------
 // Forward loop: steps n0+1 .. n0+nsteps for every item.
 // ---------------------------------------------------------------------------
-template <int BS, int BPT, int WPT, bool SM>
+// EXT: the batch has distributed-parameter lines, coupled groups or diodes
+// (the variant without them carries none of their code or registers).
+template <int BS, int BPT, int WPT, bool SM, bool EXT>
 __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, int64_t n0, int64_t nsteps,
                                                 double *rec) {
   const ItemDesc it = c.items[order[blockIdx.x]];
@@ -764,7 +767,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-  const bool diodes = it.n_diodes > 0;
+  const bool diodes = EXT && it.n_diodes > 0;
   uint32_t dmask = 0;
   if (diodes) {
 #pragma unroll
@@ -783,7 +786,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   }
   inject<BS, BPT, SM>(c, v, L, n0 + 1);
   lds_barrier();
-  const bool lines = it.n_lines > 0, groups = it.n_groups > 0;
+  const bool lines = EXT && it.n_lines > 0, groups = EXT && it.n_groups > 0;
   if (lines || groups) {
     if (lines) line_pass<BS, SM>(c, it, v, n0 + 1, false, nullptr, nullptr);
     if (groups) group_pass<BS, SM>(c, it, v, true, true, nullptr, nullptr);
@@ -810,7 +813,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       st_i = c.si + it.br;
       st_u = c.su + it.br;
     }
-    update_inject<BS, BPT, SM>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
+    update_inject<BS, BPT, SM, EXT>(c, v, L, ck_i, ck_u, st_i, st_u, sw, it.coef + (int64_t)(t + 1) * v.nbr,
                                n < n_end, n);
     if (lines || groups) {
       lds_barrier();

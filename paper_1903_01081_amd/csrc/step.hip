@@ -13,10 +13,10 @@ namespace emt {
 
 namespace {
 
-template <int BPT, int WPT, bool SM>
+template <int BPT, int WPT, bool SM, bool EXT>
 hipError_t fwd(const DevCtx &c, const int32_t *order, int n_items, int64_t n0, int64_t ns, double *rec,
                size_t lds, hipStream_t st) {
-  auto k = step::k_forward<EMT_BS, BPT, WPT, SM>;
+  auto k = step::k_forward<EMT_BS, BPT, WPT, SM, EXT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -80,8 +80,10 @@ hipError_t adj_pipe_occupancy(size_t lds, int *blocks) {
 hipError_t EMT_CAT(launch_forward_bs, EMT_BS)(const DevCtx &c, const KernelShape &ks, const int32_t *order,
                                               int n_items, int64_t n0, int64_t ns, double *rec,
                                               hipStream_t st) {
-#define EMT_CASE(BPT, WPT, SM) \
-  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM) return fwd<BPT, WPT, SM>(c, order, n_items, n0, ns, rec, ks.lds_fwd, st);
+#define EMT_CASE(BPT, WPT, SM)                                                                      \
+  if (ks.bpt == BPT && ks.wpt == WPT && ks.sm == SM)                                                \
+    return ks.ext ? fwd<BPT, WPT, SM, true>(c, order, n_items, n0, ns, rec, ks.lds_fwd, st)          \
+                  : fwd<BPT, WPT, SM, false>(c, order, n_items, n0, ns, rec, ks.lds_fwd, st);
   EMT_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;
