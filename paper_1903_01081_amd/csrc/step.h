@@ -649,6 +649,15 @@ __device__ __forceinline__ void diode_conductances(const DevCtx &c, const ItemDe
   }
 }
 
+// A workgroup barrier for data in LDS (SM) or in global memory.
+template <bool SM>
+__device__ __forceinline__ void wg_sync() {
+  if constexpr (SM)
+    lds_barrier();
+  else
+    __syncthreads();
+}
+
 // The factor of an item with diodes for its current conductances (the
 // lanes' L.g), computed inside the time loop into the item's dynamic slot:
 // G on the item's symbolic pattern (with any coupled groups' mutual
@@ -661,9 +670,20 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
   const SymDesc sd = c.syms[it.sym];
   const int n = it.n;
   double *gcur = c.dyn + it.dyn;
-  double *Lr = gcur + it.n_br;
-  double *D = Lr + sd.nnz;
-  double *sv = D + n;
+  // Under SM the factorisation runs in LDS: without a dense tail the sweep
+  // values are exactly L's nonzeros in row order (sv index = CSR position),
+  // so L is built in place in the staged sweep values and D in the staged
+  // 1/D, which is inverted at the end. Otherwise in the dynamic slot in
+  // global memory.
+  double *Lr, *D;
+  if constexpr (SM) {
+    Lr = reinterpret_cast<double *>(emt_lds + v.sv_s.off);
+    D = reinterpret_cast<double *>(emt_lds + v.dinv_s.off);
+  } else {
+    Lr = gcur + it.n_br;
+    D = Lr + sd.nnz;
+  }
+  double *sv = gcur + it.n_br + sd.nnz + n;
   double *di = sv + sd.nsv;
   const int32_t *rowptr = c.symi + sd.rowptr, *rowcol = c.symi + sd.rowcol;
   const int32_t *colrow = c.symi + sd.colrow, *colpos = c.symi + sd.colpos;
@@ -700,7 +720,7 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
       }
     }
   }
-  __syncthreads();
+  wg_sync<SM>();
   for (int l = 0; l < sd.nlev; ++l) {
     for (int p = flevptr[l] + threadIdx.x; p < flevptr[l + 1]; p += BS) {
       const int j = flevrows[p];
@@ -712,7 +732,7 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
       D[j] = d;
       if (!(d > 0.0) || !isfinite(d)) atomicAdd(c.flags + 4, 1);
     }
-    __syncthreads();
+    wg_sync<SM>();
     for (int p = fentptr[l] + threadIdx.x; p < fentptr[l + 1]; p += BS) {
       const int e = fent[p];
       const int i = colrow[e];
@@ -736,15 +756,18 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
       }
       Lr[pos] = s / D[j];
     }
-    __syncthreads();
+    wg_sync<SM>();
   }
-  for (int q = threadIdx.x; q < sd.nsv; q += BS) sv[q] = Lr[svmap[q]];
-  for (int r = threadIdx.x; r < n; r += BS) di[r] = 1.0 / D[r];
-  __syncthreads();
   if constexpr (SM) {
-    copy_to<BS>(v.sv_s.off, sv, v.nsv);
-    copy_to<BS>(v.dinv_s.off, di, v.ns);
+    (void)svmap;
+    (void)sv;
+    (void)di;
+    for (int r = threadIdx.x; r < n; r += BS) D[r] = 1.0 / D[r];
+    lds_barrier();
   } else {
+    for (int q = threadIdx.x; q < sd.nsv; q += BS) sv[q] = Lr[svmap[q]];
+    for (int r = threadIdx.x; r < n; r += BS) di[r] = 1.0 / D[r];
+    __syncthreads();
     v.sv.p = sv;
     v.dinv.p = di;
   }
