@@ -77,7 +77,9 @@ typedef enum {
   EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5, EMT_DIODE = 6
 } emt_kind;
 
-typedef enum { EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2 } emt_solver;
+typedef enum {
+  EMT_SOLVER_AUTO = 0, EMT_SOLVER_DENSE = 1, EMT_SOLVER_SPARSE = 2, EMT_SOLVER_COMPENSATION = 3
+} emt_solver;
 
 /* One network (scenario): a branch list, its switching events and outputs.
  * Per-branch arrays have n_branches entries.
@@ -171,6 +173,24 @@ typedef struct {
  *     checkpoint_every > 0). AUTO: sweeps over the leading rows of the
  *     elimination order and the dense inverse of its trailing block, cut
  *     where a cost model finds fewest dependent phases.
+ *     COMPENSATION (Sec. III-B's many scenarios of one network, with Sec.
+ *     III-A's factorisation done once for all of them; the compensation
+ *     itself is not in the paper): the first scenario's components, in
+ *     their initial topology, are the base. Every scenario's component is
+ *     one of them with at most 4 branches switched differently (in service
+ *     or not, or present in one and not the other; branches are matched by
+ *     kind, terminals, R, L, C and line). Each base's dense inverse Z =
+ *     G0^-1 is formed once by emt_factor and shared: a scenario's solve in
+ *     topology t is w = Z rhs followed by the Sherman-Morrison-Woodbury
+ *     correction v = w - Z U K U^T w, K = (D^-1 + U^T Z U)^-1 (U: the
+ *     switched branches' incidence vectors, D: their conductances, + where
+ *     the scenario has the branch in service and the base not, - the
+ *     reverse), and a workgroup applies Z to several scenarios' right-hand
+ *     sides at once (comp_items). Components of at most 256 nodes; forward
+ *     only (EMT_EINVAL with checkpoint_every > 0, lines, coupled groups or
+ *     diodes); every scenario's pi-section parameters must equal the first
+ *     scenario's where their branches are matched (emt_factor: EMT_EINVAL).
+ *     The result equals the other solvers' up to rounding.
  * Launch shape (0 / -1 = chosen by the library; paper_1903_01081_amd.tune
  * times the alternatives):
  *   block_size: lanes of a one-workgroup component (64, 256 or 512);
@@ -195,7 +215,10 @@ typedef struct {
  *     a scenario's components are packed, largest first, into work items of
  *     at most pack_nodes nodes (a larger component stays alone), so small
  *     components share a workgroup and its lanes (their G is block-diagonal
- *     within the item). At most 128 with the dense solver. */
+ *     within the item). At most 128 with the dense solver.
+ *   comp_items: COMPENSATION only, scenarios' components per workgroup (1 ..
+ *     6; 0 = the fewest that keep the workgroups within one per compute
+ *     unit). */
 typedef struct {
   double dt;
   int64_t n_steps;
@@ -208,6 +231,7 @@ typedef struct {
   int32_t serial_adjoint;
   int32_t split_device_scope;
   int32_t pack_nodes;
+  int32_t comp_items;
 } emt_sim;
 
 /* Sizes of a built context (emt_info) or of a host-only analysis. */
@@ -238,6 +262,10 @@ typedef struct {
                                 the previous segment's reversal (two workgroups per item) */
   int32_t split_local;   /* split components whose last launch exchanged through one XCD's L2
                             (0 before the first step; synchronises the device) */
+  int32_t comp_families;   /* COMPENSATION: base components (dense inverses) */
+  int32_t comp_max_rank;   /* COMPENSATION: most switched branches of a component and topology */
+  int32_t comp_items;      /* COMPENSATION: components per workgroup (built contexts) */
+  int32_t comp_blocks;     /* COMPENSATION: workgroups of the step kernel (built contexts) */
 } emt_info;
 
 /* Source: Sec. II-A and II-B (a simulation task is a model of connected
@@ -278,9 +306,13 @@ emt_status emt_set_params(emt_ctx *ctx, const double *theta_dev, void *stream);
  * conductance matrix), done here once per topology that the switching
  * events produce, before the time loop.
  * Numerically factorise G of every topology of every scenario (LDL^T on the
- * shared symbolic pattern). Starts a run (clears the device error flag) and
- * synchronises `stream` to check the pivots: EMT_ESINGULAR if any pivot is
- * non-positive or not finite. */
+ * shared symbolic pattern; with the COMPENSATION solver also each base's
+ * dense inverse and every scenario's K per topology). Starts a run (clears
+ * the device error flag) and synchronises `stream` to check the pivots:
+ * EMT_ESINGULAR if any pivot is non-positive or not finite (or a K does not
+ * exist); EMT_EINVAL if, with the COMPENSATION solver, a scenario's
+ * pi-section parameters differ from the first scenario's on matched
+ * branches. */
 emt_status emt_factor(emt_ctx *ctx, void *stream);
 
 /* Source: Sec. III-A, third basic process, as emt_factor: the same

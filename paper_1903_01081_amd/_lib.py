@@ -56,7 +56,7 @@ class EmtSim(C.Structure):
                 ("block_size", C.c_int32), ("split_cols", C.c_int32),
                 ("dense_tail", C.c_int32), ("sweep_from_global", C.c_int32),
                 ("serial_adjoint", C.c_int32), ("split_device_scope", C.c_int32),
-                ("pack_nodes", C.c_int32)]
+                ("pack_nodes", C.c_int32), ("comp_items", C.c_int32)]
 
 
 class EmtInfo(C.Structure):
@@ -72,6 +72,8 @@ class EmtInfo(C.Structure):
         ("lds_limit", C.c_int32), ("lds_staged", C.c_int32), ("lanes_per_block", C.c_int32),
         ("split_tiles", C.c_int32), ("split_cols", C.c_int32), ("adjoint_pipelined", C.c_int32),
         ("split_local", C.c_int32),
+        ("comp_families", C.c_int32), ("comp_max_rank", C.c_int32), ("comp_items", C.c_int32),
+        ("comp_blocks", C.c_int32),
     ]
 
     def as_dict(self):
@@ -175,10 +177,11 @@ class PackedNets:
 
 
 def make_sim(dt, n_steps, checkpoint_every=0, solver=0, block_size=0, split_cols=0, dense_tail=-1,
-             sweep_from_global=0, serial_adjoint=0, split_device_scope=0, pack_nodes=0) -> EmtSim:
+             sweep_from_global=0, serial_adjoint=0, split_device_scope=0, pack_nodes=0,
+             comp_items=0) -> EmtSim:
     return EmtSim(float(dt), int(n_steps), int(checkpoint_every), int(solver), int(block_size),
                   int(split_cols), int(dense_tail), int(sweep_from_global), int(serial_adjoint),
-                  int(split_device_scope), int(pack_nodes))
+                  int(split_device_scope), int(pack_nodes), int(comp_items))
 
 
 def analyze(nets, dt, n_steps, checkpoint_every=0, solver=0, pack_nodes=0) -> dict:

@@ -29,6 +29,8 @@ SOURCES = [
     ("scratch.hip", "scratch", []),
     ("steady.hip", "steady", []),
     ("floor.hip", "floor", []),
+    ("comp_plan.cpp", "comp_plan", []),
+    ("comp.hip", "comp", []),
 ]
 
 COMMON = [

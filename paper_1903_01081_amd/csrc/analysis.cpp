@@ -402,8 +402,9 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
   if (!(sim.dt > 0) || !std::isfinite(sim.dt)) fail(EMT_EINVAL, "dt must be positive and finite");
   if (sim.n_steps < 1) fail(EMT_EINVAL, "n_steps must be >= 1");
   if (sim.checkpoint_every < 0) fail(EMT_EINVAL, "checkpoint_every must be >= 0");
-  if (sim.solver < EMT_SOLVER_AUTO || sim.solver > EMT_SOLVER_SPARSE)
+  if (sim.solver < EMT_SOLVER_AUTO || sim.solver > EMT_SOLVER_COMPENSATION)
     fail(EMT_EINVAL, "unknown solver");
+  if (sim.comp_items < 0 || sim.comp_items > 6) fail(EMT_EINVAL, "comp_items must be 0..6");
   if (sim.block_size != 0 && sim.block_size != 64 && sim.block_size != 256 && sim.block_size != 512)
     fail(EMT_EINVAL, "block_size must be 0, 64, 256 or 512");
   if (sim.split_cols != 0 && sim.split_cols != 16 && sim.split_cols != 32)

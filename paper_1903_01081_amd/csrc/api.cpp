@@ -12,6 +12,8 @@
 #include <vector>
 
 #include "analysis.h"
+#include "comp.h"
+#include "comp_plan.h"
 #include "device.h"
 #include "emt.h"
 #include "launch.h"
@@ -101,6 +103,11 @@ struct emt_ctx {
   std::vector<char> scen_mixed_freq;
   int64_t *d_ss_offl = nullptr, *d_ss_offn = nullptr;
   double *ss_L = nullptr, *ss_D = nullptr, *ss_X = nullptr;
+  // compensation solver: device tables, items per workgroup, workgroups
+  bool comp = false;
+  emt::CompCtx cc{};
+  int comp_q = 0, comp_blocks = 0, comp_max_rank = 0;
+  size_t comp_lds = 0;
   int64_t step = 0;
   bool factored = false;
   bool clean = true;  // state evolved from the zero state with no set_state since
@@ -501,6 +508,106 @@ static bool build_split_with(emt_ctx &c, const std::vector<uint32_t> &bpack, int
   return true;
 }
 
+// Compensation solver tables: the plan's modifications with their
+// conductances' device indices, matched pi-section branches as global branch
+// ids, and the workgroups (items of one family, comp_items per workgroup).
+static void build_comp(emt_ctx &c, const emt_net *nets) {
+  using namespace emt;
+  const CompPlan P = plan_compensation(c.A, nets, c.sim);
+  const int NI = (int)c.A.items.size();
+  const int nbr = c.ks.bs * c.ks.bpt;
+  int max_n = 0;
+  for (const CompFamily &f : P.fams) max_n = std::max(max_n, f.n);
+  std::vector<CompMod> mods = P.mods;
+  for (size_t m = 0; m < mods.size(); ++m) {
+    CompMod &md = mods[m];
+    const int n = P.fams[md.fam].n;
+    for (int a = 0; a < md.r; ++a) {
+      const CompRef &ref = P.gref[m * kCompMaxRank + a];
+      const ItemDesc &d = c.items[ref.item];
+      md.g[a] = d.coef + (int64_t)ref.topo * d.n_br + ref.local;
+      if (md.k[a] < -1 || md.k[a] >= n || md.m[a] < -1 || md.m[a] >= n || (md.k[a] < 0 && md.m[a] < 0) ||
+          (md.sgn[a] != 1 && md.sgn[a] != -1) || ref.local < 0 || ref.local >= d.n_br || ref.topo >= d.n_topo)
+        throw Error{EMT_EDEVICE, "internal: a compensation entry is out of range"};
+    }
+  }
+  for (int q = 0; q < NI; ++q) {
+    const int n = P.fams[P.item_family[q]].n;
+    if (c.items[q].n != n || c.items[q].n_br != nbr || P.poff[q] + 2 * n > (int64_t)P.perm.size())
+      throw Error{EMT_EDEVICE, "internal: a compensation item does not match its family"};
+    for (int i = 0; i < 2 * n; ++i)
+      if (P.perm[P.poff[q] + i] >= n) throw Error{EMT_EDEVICE, "internal: a compensation node map is out of range"};
+  }
+  std::vector<int64_t> pairs;
+  for (size_t e = 0; e + 3 < P.pairs.size(); e += 4) {
+    pairs.push_back(c.items[P.pairs[e]].br + P.pairs[e + 1]);
+    pairs.push_back(c.items[P.pairs[e + 2]].br + P.pairs[e + 3]);
+  }
+  // items per workgroup: the fewest that keep the workgroups within one per
+  // compute unit, among the shapes whose kernel exists and whose LDS fits
+  std::vector<int> per_fam(P.fams.size(), 0);
+  for (int q = 0; q < NI; ++q) per_fam[P.item_family[q]]++;
+  auto n_blocks = [&](int Q) {
+    int64_t b = 0;
+    for (int k : per_fam) b += (k + Q - 1) / Q;
+    return b;
+  };
+  auto fits = [&](int Q) {
+    return comp_shape_exists(c.ks.bpt, Q) && comp_lds_bytes(max_n, nbr, Q) <= (size_t)c.lds_limit;
+  };
+  int n_cu = 0;
+  hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device), "CU count");
+  int Q = c.sim.comp_items;
+  if (Q > 0) {
+    if (!fits(Q))
+      throw Error{EMT_EINVAL, "compensation solver: comp_items = " + std::to_string(Q) +
+                                  " does not fit a workgroup at " + std::to_string(c.ks.bpt) + " branches per lane"};
+  } else {
+    for (int cand = 1; cand <= kCompMaxItems; ++cand) {
+      if (!fits(cand)) break;
+      Q = cand;
+      if (n_blocks(cand) <= n_cu) break;
+    }
+    if (Q == 0)
+      throw Error{EMT_EINVAL, "compensation solver: a component's branches (" + std::to_string(nbr) +
+                                  " slots) do not fit the compensation kernel"};
+  }
+  std::vector<int32_t> list;
+  std::vector<CompBlock> blocks;
+  for (size_t f = 0; f < P.fams.size(); ++f) {
+    std::vector<int32_t> mine;
+    for (int q = 0; q < NI; ++q)
+      if (P.item_family[q] == (int)f) mine.push_back(q);
+    for (size_t i = 0; i < mine.size(); i += Q) {
+      CompBlock b{};
+      b.family = (int32_t)f;
+      b.q0 = (int32_t)list.size();
+      b.nq = (int32_t)std::min<size_t>(Q, mine.size() - i);
+      for (int k = 0; k < b.nq; ++k) list.push_back(mine[i + k]);
+      blocks.push_back(b);
+    }
+  }
+  CompCtx &cc = c.cc;
+  cc.fam = c.upload(P.fams);
+  cc.blocks = c.upload(blocks);
+  cc.list = c.upload(list);
+  cc.mod0 = c.upload(P.mod0);
+  cc.poff = c.upload(P.poff);
+  cc.perm = c.upload(P.perm);
+  cc.mods = c.upload(mods);
+  cc.K = c.alloc<double>(16 * std::max<size_t>(mods.size(), 1));
+  cc.z = c.alloc<double>((size_t)P.z_doubles);
+  cc.pairs = pairs.empty() ? nullptr : c.upload(pairs);
+  cc.n_pairs = (int64_t)pairs.size() / 2;
+  cc.n_fam = (int32_t)P.fams.size();
+  cc.n_mods = (int32_t)mods.size();
+  c.comp = true;
+  c.comp_q = Q;
+  c.comp_blocks = (int)blocks.size();
+  c.comp_lds = comp_lds_bytes(max_n, nbr, Q);
+  c.comp_max_rank = P.max_rank;
+}
+
 static void upload_all(emt_ctx &c, const emt_net *nets) {
   using namespace emt;
   Analysis &A = c.A;
@@ -547,6 +654,11 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // at most 8 per lane (12 with 512 lanes); 512 lanes run 2 waves per SIMD,
   // which leaves 256 VGPRs per lane for the branch state and tail inverse.
   int bs = sim.block_size;
+  if (sim.solver == EMT_SOLVER_COMPENSATION) {
+    if (bs != 0 && bs != kCompBS)
+      throw Error{EMT_EINVAL, "the compensation solver runs " + std::to_string(kCompBS) + " lanes per workgroup"};
+    bs = kCompBS;
+  }
   if (bs == 0) {
     bs = 512;
     for (int cand : {64, 256})
@@ -614,8 +726,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     int d;
     if (sym_split[q] || sym_diode[q]) {
       d = 0;  // factor values only; the split kernels use the explicit inverse
-    } else if (solver == EMT_SOLVER_SPARSE) {
-      d = 0;
+    } else if (solver == EMT_SOLVER_SPARSE || solver == EMT_SOLVER_COMPENSATION) {
+      d = 0;  // compensation: the factors only check the pivots of every topology
     } else if (solver == EMT_SOLVER_DENSE) {
       if (n > c.ks.dmax)
         throw Error{EMT_EINVAL, "the dense solver holds components of at most " + std::to_string(c.ks.dmax) +
@@ -1061,10 +1173,44 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     max_scen_br = std::max(max_scen_br, c.scen_br_off[s + 1] - c.scen_br_off[s]);
   c.d_stage = c.alloc<double>(max_scen_br);
   build_split(c, bpack);
+  if (sim.solver == EMT_SOLVER_COMPENSATION) build_comp(c, nets);
   // statistics
   c.sweep_levels = 0;
   for (const Item &it : A.items)
     c.sweep_levels = std::max(c.sweep_levels, plans[it.sym].nfpass() + plans[it.sym].nbpass() + (plans[it.sym].d > 0 ? 1 : 0));
+}
+
+static hipError_t launch_comp_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
+  return emt::launch_comp(c.dc, c.cc, c.ks.bpt, c.comp_q, c.comp_blocks, n0, ns, rec, c.comp_lds, st);
+}
+
+// The compensation solver's factor work after the LDL^T factors: the bases'
+// inverses, the parameter check of matched pi-section branches (flags[5])
+// and every K (flags[6]).
+static void launch_comp_factor(emt_ctx &c, hipStream_t st) {
+  if (!c.comp) return;
+  hip_check(emt::launch_fill_i32(c.dc.flags + 5, 2, 0, st), "clear flags");
+  hip_check(emt::launch_comp_factor(c.dc, c.cc, st), "compensation factor");
+}
+
+// Status words of a factorisation (after its work has finished).
+static void check_factor_flags(emt_ctx &c) {
+  int32_t f[8] = {0};
+  hip_check(hipMemcpy(f, c.dc.flags, sizeof(f), hipMemcpyDeviceToHost), "status flags");
+  if (f[0] != 0) {
+    c.factored = false;
+    throw emt::Error{EMT_ESINGULAR, std::to_string(f[0]) + " non-positive or non-finite pivots"};
+  }
+  if (c.comp && f[5] != 0) {
+    c.factored = false;
+    throw emt::Error{EMT_EINVAL, "compensation solver: " + std::to_string(f[5]) +
+                                     " pi-section branches have parameters that differ from the first scenario's"};
+  }
+  if (c.comp && f[6] != 0) {
+    c.factored = false;
+    throw emt::Error{EMT_ESINGULAR, "compensation solver: " + std::to_string(f[6]) +
+                                        " switched topologies have no Sherman-Morrison-Woodbury correction"};
+  }
 }
 
 static hipError_t launch_forward(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
@@ -1140,11 +1286,7 @@ static void report_all(emt_ctx &c) {
   report_split(c);
   if (c.pivots_pending) {
     c.pivots_pending = false;
-    const int32_t bad = read_flag(c.dc.flags);
-    if (bad != 0) {
-      c.factored = false;
-      throw emt::Error{EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots"};
-    }
+    check_factor_flags(c);
   }
   if (c.adjoint_pending) {
     c.adjoint_pending = false;
@@ -1181,6 +1323,11 @@ emt_status emt_analyze(const emt_net *nets, int32_t n_scen, const emt_sim *sim, 
     if (!sim || !info) return set_error(EMT_EINVAL, "sim and info are required");
     emt::Analysis A = emt::analyze(nets, n_scen, *sim);
     emt::fill_info(A, info);
+    if (sim->solver == EMT_SOLVER_COMPENSATION) {
+      const emt::CompPlan P = emt::plan_compensation(A, nets, *sim);
+      info->comp_families = (int32_t)P.fams.size();
+      info->comp_max_rank = P.max_rank;
+    }
     return EMT_OK;
   });
 }
@@ -1222,6 +1369,11 @@ emt_status emt_info_get(const emt_ctx *ctx, emt_info *info) {
     info->split_tiles = ctx->n_tiles;
     info->adjoint_pipelined = ctx->adj_pipe ? 1 : 0;
     info->split_cols = ctx->n_tiles > 0 ? ctx->split_rt : 0;
+    info->comp_families = ctx->cc.n_fam;
+    info->comp_max_rank = ctx->comp_max_rank;
+    info->comp_items = ctx->comp_q;
+    info->comp_blocks = ctx->comp_blocks;
+    if (ctx->comp) info->lds_bytes = (int32_t)ctx->comp_lds;
     info->split_local = 0;
     if (ctx->n_tiles > 0 && ctx->sc.allow_local) {
       // the XCD record of the last launch (all -1 before the first one)
@@ -1266,14 +1418,10 @@ emt_status emt_factor(emt_ctx *ctx, void *stream) {
     if (ctx->n_tiles > 0)
       hip_check(emt::launch_inverse(ctx->dc, ctx->sc, ctx->d_inv_jobs, ctx->n_inv_jobs, ctx->inverse_lds, st),
                 "inverse");
-    int32_t bad = 0;
-    hip_check(hipMemcpyAsync(&bad, ctx->dc.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag");
+    launch_comp_factor(*ctx, st);
     hip_check(hipStreamSynchronize(st), "factor sync");
     ctx->pivots_pending = false;
-    if (bad) {
-      ctx->factored = false;
-      return set_error(EMT_ESINGULAR, std::to_string(bad) + " non-positive or non-finite pivots");
-    }
+    check_factor_flags(*ctx);
     ctx->factored = true;
     return EMT_OK;
   });
@@ -1289,6 +1437,7 @@ emt_status emt_factor_async(emt_ctx *ctx, void *stream) {
     if (ctx->n_tiles > 0)
       hip_check(emt::launch_inverse(ctx->dc, ctx->sc, ctx->d_inv_jobs, ctx->n_inv_jobs, ctx->inverse_lds, st),
                 "inverse");
+    launch_comp_factor(*ctx, st);
     ctx->factored = true;
     ctx->pivots_pending = true;
     return EMT_OK;
@@ -1303,7 +1452,10 @@ emt_status emt_step(emt_ctx *ctx, int64_t n, double *rec_dev, void *stream) {
     if (ctx->step + n > ctx->sim.n_steps) return set_error(EMT_ESTATE, "stepping past n_steps");
     if (n == 0) return EMT_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    if (ctx->comp)
+      hip_check(launch_comp_step(*ctx, ctx->step, n, rec_dev, st), "compensation forward");
+    else if (ctx->n_fwd > 0)
+      hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
     if (ctx->n_tiles > 0) launch_split_step(*ctx, ctx->step, n, rec_dev, st);
     ctx->step += n;
     return EMT_OK;
@@ -1324,7 +1476,10 @@ emt_status emt_step_noalloc(emt_ctx *ctx, int64_t n, double *rec_dev, void *stre
                                        std::to_string(emt::kStaticScratchBytes));
     if (n == 0) return EMT_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (ctx->n_fwd > 0) hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
+    if (ctx->comp)
+      hip_check(launch_comp_step(*ctx, ctx->step, n, rec_dev, st), "compensation forward");
+    else if (ctx->n_fwd > 0)
+      hip_check(launch_forward(*ctx, ctx->step, n, rec_dev, st), "forward");
     if (ctx->n_tiles > 0) {
       void *base = nullptr;
       hip_check(emt::static_scratch_ptr(ctx->device, &base), "static scratch address");
@@ -1383,7 +1538,16 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
     Scratch sc;
     hip_check(hipEventCreate(&sc.e0), "event");
     hip_check(hipEventCreate(&sc.e1), "event");
-    if (kernel == EMT_FLOOR_ONE_WORKGROUP) {
+    if (kernel == EMT_FLOOR_ONE_WORKGROUP && ctx->comp) {
+      // the compensation kernel's four phases per step (gather, product,
+      // correction, branch update) in its grid, workgroup and LDS size
+      hip_check(hipMalloc(reinterpret_cast<void **>(&sc.out), (size_t)ctx->comp_blocks * emt::kCompBS * sizeof(double)),
+                "hipMalloc");
+      hip_check(hipEventRecord(sc.e0, st), "event");
+      hip_check(emt::launch_barrier_floor(emt::kCompBS, ctx->comp_blocks, 4, n_steps, ctx->comp_lds, sc.out, st),
+                "barrier floor");
+      hip_check(hipEventRecord(sc.e1, st), "event");
+    } else if (kernel == EMT_FLOOR_ONE_WORKGROUP) {
       if (ctx->n_fwd == 0) return set_error(EMT_EINVAL, "no component of this batch runs in one workgroup");
       hip_check(hipMalloc(reinterpret_cast<void **>(&sc.out), (size_t)ctx->n_fwd * ctx->ks.bs * sizeof(double)),
                 "hipMalloc");

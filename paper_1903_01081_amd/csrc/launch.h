@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "comp.h"
 #include "device.h"
 #include "emt.h"
 
@@ -98,6 +99,15 @@ hipError_t launch_steady(const DevCtx &c, int n_items, const int64_t *off_l, con
                          void *Dc, void *X, int32_t *bad, hipStream_t st);
 
 hipError_t launch_or_flag(int32_t *dst, const int32_t *src, hipStream_t st);
+
+// Compensation solver (comp.hip): LDS of a step workgroup of q items, the
+// (branches per lane, items) shapes that have a kernel, the step launch, and
+// the factor work (bases' inverses, parameter check, K per item and topology).
+size_t comp_lds_bytes(int n, int nbr, int q);
+bool comp_shape_exists(int bpt, int q);
+hipError_t launch_comp(const DevCtx &c, const CompCtx &cc, int bpt, int q, int n_blocks, int64_t n0, int64_t ns,
+                       double *rec, size_t lds, hipStream_t st);
+hipError_t launch_comp_factor(const DevCtx &c, const CompCtx &cc, hipStream_t st);
 
 // Latency floors (floor.hip; the split floor is launch_split with floor set).
 hipError_t launch_barrier_floor(int bs, int n_blocks, int phases, int64_t nsteps, size_t lds, double *out,

@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import EMTError, check
 
-SOLVERS = {"auto": 0, "dense": 1, "sparse": 2}
+SOLVERS = {"auto": 0, "dense": 1, "sparse": 2, "compensation": 3}
 
 
 def _stream():
@@ -43,7 +43,8 @@ class Simulator:
     def __init__(self, nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0,
                  solver: str = "auto", device: Optional[torch.device] = None, block_size: int = 0,
                  split_cols: int = 0, dense_tail: int = -1, sweep_from_global: bool = False,
-                 serial_adjoint: bool = False, split_device_scope: bool = False, pack_nodes: int = 0):
+                 serial_adjoint: bool = False, split_device_scope: bool = False, pack_nodes: int = 0,
+                 comp_items: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the EMT library needs a HIP device")
         self.lib = _lib.load()
@@ -56,10 +57,10 @@ class Simulator:
         self.shape = dict(solver=solver, block_size=int(block_size), split_cols=int(split_cols),
                           dense_tail=int(dense_tail), sweep_from_global=bool(sweep_from_global),
                           serial_adjoint=bool(serial_adjoint), split_device_scope=bool(split_device_scope),
-                          pack_nodes=int(pack_nodes))
+                          pack_nodes=int(pack_nodes), comp_items=int(comp_items))
         sim = _lib.make_sim(dt, n_steps, checkpoint_every, SOLVERS[solver], block_size, split_cols, dense_tail,
                             int(bool(sweep_from_global)), int(bool(serial_adjoint)),
-                            int(bool(split_device_scope)), int(pack_nodes))
+                            int(bool(split_device_scope)), int(pack_nodes), int(comp_items))
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             check(self.lib.emt_build(packed.ref, packed.n, C.addressof(sim), C.byref(self._ctx)))
