@@ -283,21 +283,46 @@ def solver_comparison(torch, nets, cfg, tuned, shape, best_run_s):
 N1_WORKLOAD = "grid200 N-1: 400 scenarios x 600 nodes, 15,000 steps at 20 us"
 
 
-def batched_n1(torch):
+def comp_roofline_object(info, nets, time_steps, kernel_s):
+    """Roofline of the compensation kernel (k_comp): its solve is a dense
+    product, Z rhs for every component of every scenario and step (2 n^2
+    FP64 operations, fused multiply-adds on the vector units), plus 10 per
+    branch for the branch phase (the Woodbury correction, 4 n per switched
+    branch, is left out); bound by the FP64 rate, 78.6 TF/s. Each workgroup
+    reads its family's Z (8 n^2 B) from L2 once per step: l2_gbs."""
+    sizes = [int(c) for n in nets for c in component_sizes(n)]
+    fam = [int(c) for c in component_sizes(nets[0])]
+    flops = 2 * sum(c * c for c in sizes) + 10 * info["total_branches"]
+    tflops = flops * time_steps / kernel_s / 1e12
+    z_bytes = info["comp_blocks"] * 8 * float(np.mean([c * c for c in fam]))
+    return {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / FP64_PEAK_TFLOPS, "traffic": None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "kernel": "k_comp", "kernel_s": kernel_s, "time_steps": time_steps,
+            "fp64_flops_per_time_step": flops, "l2_z_bytes_per_time_step": z_bytes,
+            "l2_gbs": z_bytes * time_steps / kernel_s / 1e9,
+            "comp_items": info["comp_items"], "comp_blocks": info["comp_blocks"]}
+
+
+def batched_n1(torch, exclude_solvers=()):
     """The 400-scenario N-1 batch in one launch with its tuned shape:
     returns (networks, settings, shape, wall s, kernel s, roofline, latency)."""
     from paper_1903_01081_amd import netgen
     from paper_1903_01081_amd.sim import Simulator
     from paper_1903_01081_amd.tune import tune
     nets, cfg = netgen.config2()
-    shape_b = tune(nets, cfg["dt"], cfg["n_steps"], probe_steps=300)["shape"]
+    shape_b = tune(nets, cfg["dt"], cfg["n_steps"], probe_steps=300, exclude_solvers=exclude_solvers)["shape"]
     sim = Simulator(nets, cfg["dt"], cfg["n_steps"], **shape_b)
     info = sim.info()
     rec = torch.empty((sim.S, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
     wall, kern = time_simulation(torch, sim, rec, 1, 1)
-    kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
     T = cfg["n_steps"]
-    roof = roofline_object(info, sum(n.n_rec for n in nets), T, kernel, kern)
+    if shape_b.get("solver") == "compensation":
+        kernel = "k_comp"
+        roof = comp_roofline_object(info, nets, T, kern)
+    else:
+        kernel = "k_split" if info["split_tiles"] > 0 else "k_forward"
+        roof = roofline_object(info, sum(n.n_rec for n in nets), T, kernel, kern)
     lat = latency_object(sim, kernel, kern / T * 1e6, info)
     sim.close()
     del rec
@@ -479,6 +504,15 @@ def extras_n1(torch):
                          "plain_loop_sample": f"{len(plain_t)} scenarios (every 50th) run one at a time, "
                                               f"median of 3 runs each",
                          "plain_launch_shape": shape_1, "speedup_vs_plain_loop": batched / plain}
+    if shape_b.get("solver") == "compensation":
+        # the same batch with the per-scenario factors (sweeps), tuned without
+        # the compensation solver
+        log("extras: batched N-1, sweep solvers")
+        _, _, shape_s, wall_s, _, roof_s, lat_s = batched_n1(torch, exclude_solvers=("compensation",))
+        sweeps = len(nets) * N * T / wall_s
+        out["batched_n1"]["per_scenario_factors"] = {
+            "value": sweeps, "seconds": wall_s, "launch_shape": shape_s, "roofline": roof_s, "latency": lat_s}
+        out["batched_n1"]["speedup_vs_per_scenario_factors"] = batched / sweeps
     return out
 
 
@@ -683,6 +717,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-n1", action="store_true",
                     help="run only the batched N-1 workload (one line; for profiling its kernel)")
+    ap.add_argument("--n1-solver", choices=["tuned", "sweeps"], default="tuned",
+                    help="with --only-n1: the tuned shape (any solver) or the best shape without the "
+                         "compensation solver (per-scenario factors)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the adjoint workloads (one line; for profiling the adjoint kernels)")
     ap.add_argument("--profile-adjoint", choices=["serial", "pipelined"],
@@ -708,7 +745,8 @@ def main():
         if args.calibrate_copy:
             calibrate_copy(torch)
         elif args.only_n1:
-            nets, cfg, shape, wall, kern, roof, lat = batched_n1(torch)
+            excl = ("compensation",) if args.n1_solver == "sweeps" else ()
+            nets, cfg, shape, wall, kern, roof, lat = batched_n1(torch, exclude_solvers=excl)
             nsteps = len(nets) * nets[0].n_nodes * cfg["n_steps"]
             print(json.dumps({"metric": "node-steps/s, batched N-1", "value": nsteps / wall, "unit": "node-steps/s",
                               "workload": N1_WORKLOAD, "launch_shape": shape, "seconds": wall, "kernel_s": kern,

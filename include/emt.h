@@ -186,7 +186,8 @@ typedef struct {
  *     switched branches' incidence vectors, D: their conductances, + where
  *     the scenario has the branch in service and the base not, - the
  *     reverse), and a workgroup applies Z to several scenarios' right-hand
- *     sides at once (comp_items). Components of at most 256 nodes; forward
+ *     sides at once (comp_items). Components of at most 256 nodes and 2048
+ *     branches; forward
  *     only (EMT_EINVAL with checkpoint_every > 0, lines, coupled groups or
  *     diodes); every scenario's pi-section parameters must equal the first
  *     scenario's where their branches are matched (emt_factor: EMT_EINVAL).
@@ -217,8 +218,12 @@ typedef struct {
  *     components share a workgroup and its lanes (their G is block-diagonal
  *     within the item). At most 128 with the dense solver.
  *   comp_items: COMPENSATION only, scenarios' components per workgroup (1 ..
- *     6; 0 = the fewest that keep the workgroups within one per compute
- *     unit). */
+ *     8; 0 = the fewest that keep the workgroups within one per compute
+ *     unit); each component runs its branch phase on block_size lanes of
+ *     the workgroup (COMPENSATION: 64, 128, 192 or 256; 0 = the fewest
+ *     that hold its branches at up to 8 per lane), and a workgroup of
+ *     block_size x comp_items lanes (at most 1024, covering the
+ *     component's nodes) applies Z to all of its components at once. */
 typedef struct {
   double dt;
   int64_t n_steps;

@@ -405,8 +405,13 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
   if (sim.solver < EMT_SOLVER_AUTO || sim.solver > EMT_SOLVER_COMPENSATION)
     fail(EMT_EINVAL, "unknown solver");
   if (sim.comp_items < 0 || sim.comp_items > 6) fail(EMT_EINVAL, "comp_items must be 0..6");
-  if (sim.block_size != 0 && sim.block_size != 64 && sim.block_size != 256 && sim.block_size != 512)
+  if (sim.solver == EMT_SOLVER_COMPENSATION) {
+    if (sim.block_size != 0 && sim.block_size != 64 && sim.block_size != 128 && sim.block_size != 192 &&
+        sim.block_size != 256)
+      fail(EMT_EINVAL, "compensation solver: block_size (lanes per component) must be 0, 64, 128, 192 or 256");
+  } else if (sim.block_size != 0 && sim.block_size != 64 && sim.block_size != 256 && sim.block_size != 512) {
     fail(EMT_EINVAL, "block_size must be 0, 64, 256 or 512");
+  }
   if (sim.split_cols != 0 && sim.split_cols != 16 && sim.split_cols != 32)
     fail(EMT_EINVAL, "split_cols must be 0, 16 or 32");
   if (sim.dense_tail < -1) fail(EMT_EINVAL, "dense_tail must be >= -1");

@@ -106,7 +106,7 @@ struct emt_ctx {
   // compensation solver: device tables, items per workgroup, workgroups
   bool comp = false;
   emt::CompCtx cc{};
-  int comp_q = 0, comp_blocks = 0, comp_max_rank = 0;
+  int comp_q = 0, comp_blocks = 0, comp_max_rank = 0, comp_lanes = 0;
   size_t comp_lds = 0;
   int64_t step = 0;
   bool factored = false;
@@ -552,25 +552,37 @@ static void build_comp(emt_ctx &c, const emt_net *nets) {
     for (int k : per_fam) b += (k + Q - 1) / Q;
     return b;
   };
+  int ne_max = 0, nr_max = 0, ns_max = 0;
+  for (const Item &it : c.A.items) {
+    ne_max = std::max(ne_max, (int)it.nent.size());
+    nr_max = std::max(nr_max, (int)it.rec_node.size());
+    ns_max = std::max(ns_max, it.n_src);
+  }
+  if (ns_max > c.ks.bs)
+    throw Error{EMT_EINVAL, "compensation solver: a component has more sources than lanes"};
   auto fits = [&](int Q) {
-    return comp_shape_exists(c.ks.bpt, Q) && comp_lds_bytes(max_n, nbr, Q) <= (size_t)c.lds_limit;
+    return comp_shape_exists(c.ks.bs, c.ks.bpt, Q) &&
+           comp_lds_bytes(max_n, nbr, Q, ne_max, nr_max, ns_max, c.ks.bs) <= (size_t)c.lds_limit;
   };
   int n_cu = 0;
   hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device), "CU count");
   int Q = c.sim.comp_items;
   if (Q > 0) {
     if (!fits(Q))
-      throw Error{EMT_EINVAL, "compensation solver: comp_items = " + std::to_string(Q) +
-                                  " does not fit a workgroup at " + std::to_string(c.ks.bpt) + " branches per lane"};
+      throw Error{EMT_EINVAL, "compensation solver: comp_items = " + std::to_string(Q) + " does not fit a " +
+                                  "workgroup (" + std::to_string(c.ks.bs) + " lanes per component, " +
+                                  std::to_string(max_n) + " nodes, LDS)"};
   } else {
+    // the fewest items per workgroup that keep the workgroups within one
+    // per compute unit, else the most that fit
     for (int cand = 1; cand <= kCompMaxItems; ++cand) {
-      if (!fits(cand)) break;
+      if (!fits(cand)) continue;
       Q = cand;
       if (n_blocks(cand) <= n_cu) break;
     }
     if (Q == 0)
-      throw Error{EMT_EINVAL, "compensation solver: a component's branches (" + std::to_string(nbr) +
-                                  " slots) do not fit the compensation kernel"};
+      throw Error{EMT_EINVAL, "compensation solver: a component (" + std::to_string(max_n) + " nodes, " +
+                                  std::to_string(nbr) + " branch slots) does not fit the compensation kernel"};
   }
   std::vector<int32_t> list;
   std::vector<CompBlock> blocks;
@@ -601,10 +613,14 @@ static void build_comp(emt_ctx &c, const emt_net *nets) {
   cc.n_pairs = (int64_t)pairs.size() / 2;
   cc.n_fam = (int32_t)P.fams.size();
   cc.n_mods = (int32_t)mods.size();
+  cc.ne_max = ne_max;
+  cc.nr_max = nr_max;
+  cc.ns_max = ns_max;
   c.comp = true;
   c.comp_q = Q;
   c.comp_blocks = (int)blocks.size();
-  c.comp_lds = comp_lds_bytes(max_n, nbr, Q);
+  c.comp_lds = comp_lds_bytes(max_n, nbr, Q, ne_max, nr_max, ns_max, c.ks.bs);
+  c.comp_lanes = comp_lanes(max_n, Q, c.ks.bs);
   c.comp_max_rank = P.max_rank;
 }
 
@@ -655,9 +671,21 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   // which leaves 256 VGPRs per lane for the branch state and tail inverse.
   int bs = sim.block_size;
   if (sim.solver == EMT_SOLVER_COMPENSATION) {
-    if (bs != 0 && bs != kCompBS)
-      throw Error{EMT_EINVAL, "the compensation solver runs " + std::to_string(kCompBS) + " lanes per workgroup"};
-    bs = kCompBS;
+    // lanes per scenario component: the fewest that hold its branches at
+    // up to 8 per lane
+    if (bs == 0) {
+      for (int cand : {64, 128, 192, 256})
+        if ((max_nbr + cand - 1) / cand <= 8) {
+          bs = cand;
+          break;
+        }
+      if (bs == 0)
+        throw Error{EMT_EINVAL, "compensation solver: a component has " + std::to_string(max_nbr) +
+                                    " branches; at most 2048"};
+    }
+    if ((max_nbr + bs - 1) / bs > 8)
+      throw Error{EMT_EINVAL, "compensation solver: a component has " + std::to_string(max_nbr) +
+                                  " branches, more than 8 per lane at " + std::to_string(bs) + " lanes"};
   }
   if (bs == 0) {
     bs = 512;
@@ -668,7 +696,12 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
       }
   }
   int bpt = 0;
-  for (int cand : {1, 2, 4, 6, 8, 12, 16})
+  const bool comp = sim.solver == EMT_SOLVER_COMPENSATION;
+  // the compensation kernel exists for every count up to 8 (it is the only
+  // step kernel a compensation context launches)
+  const std::vector<int> bpts = comp ? std::vector<int>{1, 2, 3, 4, 5, 6, 7, 8}
+                                     : std::vector<int>{1, 2, 4, 6, 8, 12, 16};
+  for (int cand : bpts)
     if (cand * bs >= std::max(max_nbr, 1)) {
       bpt = cand;
       break;
@@ -769,7 +802,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     c.sm_adj = a_sm <= (size_t)max_lds && !sim.sweep_from_global;
   };
   lds_figures();
-  if (!c.sm_fwd || !c.sm_adj) {
+  if (!comp && (!c.sm_fwd || !c.sm_adj)) {
     // The global-memory variants exist for 4, 8 and 16 branches per lane and
     // run every one of those slots: items padded for fewer (1, 2, 6, 12)
     // are padded again to the global variant's count, which every kernel
@@ -1181,7 +1214,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
 }
 
 static hipError_t launch_comp_step(emt_ctx &c, int64_t n0, int64_t ns, double *rec, hipStream_t st) {
-  return emt::launch_comp(c.dc, c.cc, c.ks.bpt, c.comp_q, c.comp_blocks, n0, ns, rec, c.comp_lds, st);
+  return emt::launch_comp(c.dc, c.cc, c.ks.bs, c.ks.bpt, c.comp_q, c.comp_lanes, c.comp_blocks, n0, ns, rec,
+                          c.comp_lds, st);
 }
 
 // The compensation solver's factor work after the LDL^T factors: the bases'
@@ -1541,10 +1575,12 @@ emt_status emt_latency_floor(emt_ctx *ctx, int32_t kernel, int64_t n_steps, doub
     if (kernel == EMT_FLOOR_ONE_WORKGROUP && ctx->comp) {
       // the compensation kernel's four phases per step (gather, product,
       // correction, branch update) in its grid, workgroup and LDS size
-      hip_check(hipMalloc(reinterpret_cast<void **>(&sc.out), (size_t)ctx->comp_blocks * emt::kCompBS * sizeof(double)),
+      int fb = 64;  // the floor kernel's lanes: a power of two, at least the workgroup's
+      while (fb < ctx->comp_lanes) fb *= 2;
+      hip_check(hipMalloc(reinterpret_cast<void **>(&sc.out), (size_t)ctx->comp_blocks * fb * sizeof(double)),
                 "hipMalloc");
       hip_check(hipEventRecord(sc.e0, st), "event");
-      hip_check(emt::launch_barrier_floor(emt::kCompBS, ctx->comp_blocks, 4, n_steps, ctx->comp_lds, sc.out, st),
+      hip_check(emt::launch_barrier_floor(fb, ctx->comp_blocks, 4, n_steps, ctx->comp_lds, sc.out, st),
                 "barrier floor");
       hip_check(hipEventRecord(sc.e1, st), "event");
     } else if (kernel == EMT_FLOOR_ONE_WORKGROUP) {

@@ -18,11 +18,10 @@
 
 namespace emt {
 
-constexpr int kCompBS = 256;        // lanes per workgroup: one row of Z per lane
+constexpr int kCompBS = 256;        // lanes of a workgroup of the factor kernels
 constexpr int kCompMaxNodes = 256;  // nodes of a family (a connected component)
 constexpr int kCompMaxRank = 4;     // switched branches per item and topology
-constexpr int kCompMaxItems = 6;    // items per workgroup
-constexpr int kCompMaxSlots = 36;   // branch slots per lane x items per workgroup
+constexpr int kCompMaxItems = 6;    // items per workgroup of the step kernel
 
 // One family: its nodes, its base item (the first scenario's component, in
 // its initial topology) and the offset of its Z in CompCtx::z (n x n,
@@ -60,6 +59,7 @@ struct CompCtx {
   const int64_t *pairs;    // (item branch, base branch) pairs of pi-section branches, global branch ids
   int64_t n_pairs;
   int32_t n_fam, n_mods;
+  int32_t ne_max, nr_max, ns_max;  // most node-CSR entries, recorded nodes and sources of an item
 };
 
 }  // namespace emt

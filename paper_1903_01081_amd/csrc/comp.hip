@@ -33,8 +33,6 @@ namespace {
 
 using step::emt_lds;
 using step::lds_barrier;
-using step::Lane;
-using step::View;
 
 __global__ __launch_bounds__(kCompBS) void k_comp_assemble(DevCtx c, CompCtx cc) {
   const CompFamily F = cc.fam[blockIdx.x];
@@ -169,127 +167,279 @@ __global__ void k_comp_k(DevCtx c, CompCtx cc) {
     for (int b = 0; b < r; ++b) Kq[a * 4 + b] = M[a][r + b];
 }
 
-// LDS of k_comp per item slot: x [n+1] (item order, x[n] = 0 is the
-// ground), J [nbr], xb [n] (right-hand side, base order), wb [n+1] (w, base
-// order, wb[n] = 0).
+// Layout of a k_comp workgroup. Item q of the workgroup is run by lanes
+// q*SB .. q*SB+SB-1 (its "sub-group": branch phase, gather and correction);
+// the product uses every lane. Per item slot (byte offsets, 16-byte
+// aligned parts):
+//   meta   int32 [16]: scen, n_src, n_rec, n_topo, mod0, r, k[4], m[4];
+//          int64 [8] from byte 64: br, coef, node, topo
+//   K      [16]  the current topology's K (leading dimension 4)
+//   x      [n+1] voltages in the item's node order (x[n] = 0: the ground);
+//                between the gather and the correction the same array
+//                holds the right-hand side in the base's node order
+//   J      [nbr] branch injections
+//   zu     [4n]  Z u_a of the current topology's switched branches
+//   perm   [2n]  uint16: item -> base node map, base -> item
+//   nptr   [n+1] int32, nent [ne] uint16: the item's node CSR
+//   rnode, rcol [nr] uint16: recorded nodes and their columns
+//   src    [ns][3] the sources' E, omega, phase (slot 0 of the first ns lanes)
+// After the Q slots: the product's partial sums P [KS][Q][n].
+struct CompSlot {
+  uint32_t meta, K, x, J, zu, perm, nptr, nent, rnode, rcol, src, bytes;
+};
 __host__ __device__ inline uint32_t align16(uint32_t b) { return (b + 15u) & ~15u; }
-__host__ __device__ inline uint32_t comp_slot_bytes(int n, int nbr) {
-  return align16((uint32_t)(n + 1) * 8u) + align16((uint32_t)nbr * 8u) + align16((uint32_t)n * 8u) +
-         align16((uint32_t)(n + 1) * 8u);
+__host__ __device__ inline CompSlot comp_slot(int n, int nbr, int ne, int nr, int ns) {
+  CompSlot s;
+  uint32_t o = 0;
+  auto take = [&o](uint32_t b) {
+    const uint32_t r = o;
+    o += align16(b);
+    return r;
+  };
+  s.meta = take(128);
+  s.K = take(16 * 8);
+  s.x = take((uint32_t)(n + 1) * 8u);
+  s.J = take((uint32_t)nbr * 8u);
+  s.zu = take((uint32_t)kCompMaxRank * n * 8u);
+  s.perm = take((uint32_t)(2 * n) * 2u);
+  s.nptr = take((uint32_t)(n + 1) * 4u);
+  s.nent = take((uint32_t)ne * 2u);
+  s.rnode = take((uint32_t)nr * 2u);
+  s.rcol = take((uint32_t)nr * 2u);
+  s.src = take(3u * 8u * (uint32_t)ns);
+  s.bytes = o;
+  return s;
+}
+// k-splits of the product: lanes are (split, row) pairs over rows rounded
+// up to whole waves, at most 4 splits.
+__host__ __device__ inline int comp_ksplits(int n, int bs) {
+  const int rw = (n + 63) / 64 * 64;
+  const int ks = bs / rw;
+  return ks < 1 ? 1 : (ks > 4 ? 4 : ks);
+}
+__host__ __device__ inline uint32_t comp_lds(int n, int nbr, int ne, int nr, int ns, int q, int bs) {
+  return (uint32_t)q * comp_slot(n, nbr, ne, nr, ns).bytes + align16((uint32_t)(comp_ksplits(n, bs) * q * n) * 8u);
 }
 
-constexpr int kChunk = 8;  // rows of Z in flight per lane
+// A value hidden from the optimiser at each use, so that per-slot index and
+// address arithmetic inside the time loop is recomputed there (a few
+// integer operations) instead of being hoisted out of it into VGPRs.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 
-template <int BPT, int Q>
-__global__ __launch_bounds__(kCompBS) void k_comp(DevCtx c, CompCtx cc, int64_t n0, int64_t nsteps, double *rec) {
-  constexpr int BS = kCompBS;
+// Values that are the same in every lane of a wave (a sub-group is whole
+// waves), moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+enum { M_SCEN = 0, M_NSRC, M_NREC, M_NTOPO, M_MOD0, M_R, M_K, M_M = M_K + 4 };
+enum { M64_BR = 8, M64_COEF, M64_NODE, M64_TOPO };
+
+constexpr int kChunk = 8;        // k ranges of the product splits are multiples of this
+constexpr int kCompQMax = kCompMaxItems;  // accumulators per lane of the product
+
+// SB lanes per item, BPT branch slots per lane; Q = blockDim.x / SB items.
+template <int SB, int BPT>
+__global__ __launch_bounds__(1024) void k_comp(DevCtx c, CompCtx cc, int Q, int64_t n0, int64_t nsteps, double *rec) {
   const CompBlock blk = cc.blocks[blockIdx.x];
   const int nq = blk.nq;
+  const int BS = blockDim.x;  // at least SB * Q; the lanes past them join the gather, product and correction
   const CompFamily F = cc.fam[blk.family];
   const int n = F.n;
   const double *Z = cc.z + F.z;
   const int tid = threadIdx.x;
-  const int nbr = BS * BPT;
-  const uint32_t slot = comp_slot_bytes(n, nbr);
-  const uint32_t o_x = 0, o_j = align16((uint32_t)(n + 1) * 8u), o_xb = o_j + align16((uint32_t)nbr * 8u),
-                 o_wb = o_xb + align16((uint32_t)n * 8u);
-  auto X = [&](int q) { return reinterpret_cast<double *>(emt_lds + q * slot + o_x); };
-  auto XB = [&](int q) { return reinterpret_cast<double *>(emt_lds + q * slot + o_xb); };
-  auto WB = [&](int q) { return reinterpret_cast<double *>(emt_lds + q * slot + o_wb); };
-  auto view = [&](int q, int nsrc) {
-    View<false> v{};
-    v.n = n;
-    v.nbr = nbr;
-    v.nsrc = nsrc;
-    v.x.off = q * slot + o_x;
-    v.J.off = q * slot + o_j;
-    return v;
+  const int sq = uni(tid / SB);   // this lane's item slot (whole waves)
+  const int jl = tid - sq * SB;   // lane within the sub-group
+  const bool mine = sq < nq;      // the slot holds an item
+  const int nbr = SB * BPT;
+  const CompSlot S = comp_slot(n, nbr, cc.ne_max, cc.nr_max, cc.ns_max);
+  char *slot = emt_lds + sq * S.bytes;
+  int32_t *m32 = reinterpret_cast<int32_t *>(slot + S.meta);
+  int64_t *m64 = reinterpret_cast<int64_t *>(slot + S.meta);
+  double *Kq = reinterpret_cast<double *>(slot + S.K);
+  double *x = reinterpret_cast<double *>(slot + S.x);
+  double *J = reinterpret_cast<double *>(slot + S.J);
+  double *zu = reinterpret_cast<double *>(slot + S.zu);
+  uint16_t *perm = reinterpret_cast<uint16_t *>(slot + S.perm);
+  int32_t *nptr = reinterpret_cast<int32_t *>(slot + S.nptr);
+  uint16_t *nent = reinterpret_cast<uint16_t *>(slot + S.nent);
+  uint16_t *rnode = reinterpret_cast<uint16_t *>(slot + S.rnode);
+  uint16_t *rcol = reinterpret_cast<uint16_t *>(slot + S.rcol);
+  double *src = reinterpret_cast<double *>(slot + S.src);
+  const int KS = comp_ksplits(n, BS);
+  double *P = reinterpret_cast<double *>(emt_lds + Q * S.bytes);  // [KS][Q][n]
+
+  // the correction data of topology t: r, terminals, K and the vectors
+  // Z u_a (rows k_a and m_a of Z, Z being symmetric), by the sub-group
+  auto load_corr = [&](int mod0, int t) {
+    const int mi = mod0 + t;
+    const CompMod *md = cc.mods + mi;
+    const int r = md->r;
+    if (jl == 0) {
+      m32[M_R] = r;
+      for (int a = 0; a < kCompMaxRank; ++a) {
+        m32[M_K + a] = md->k[a];
+        m32[M_M + a] = md->m[a];
+      }
+    }
+    if (jl < 16) Kq[jl] = cc.K[(int64_t)mi * 16 + jl];
+    for (int a = 0; a < r; ++a) {
+      const int ka = md->k[a], ma = md->m[a];
+      for (int i = jl; i < n; i += SB) {
+        const double zk = ka >= 0 ? Z[(int64_t)ka * n + i] : 0.0;
+        const double zm = ma >= 0 ? Z[(int64_t)ma * n + i] : 0.0;
+        zu[a * n + i] = zk - zm;
+      }
+    }
   };
 
-  Lane<BPT> L[Q];
-  int t[Q], pf[Q], pi[Q];
-  int64_t next[Q];
+  // Branch state of this lane's slots (the same recursion as k_forward's
+  // branch phase): packed terminals, coefficients, the source of slot 0.
+  uint32_t pk[BPT];
+  double g[BPT], be[BPT];
+  double h0 = 0.0, e0 = 0.0;
+  int t = 0;
+  int64_t next = step::kNever;
+  int nsrc = 0;
+  int64_t br = 0, coef = 0;
+  if (mine) {
+    const int item = uni(cc.list[blk.q0 + sq]);
+    const ItemDesc it = c.items[item];
+    const int64_t *topo = c.topo + it.topo;
+    t = uni(step::topo_of(topo, it.n_topo, n0 + 1));
+    next = uni64((t + 1 < it.n_topo) ? topo[t + 1] : step::kNever);
+    nsrc = uni(it.n_src);
+    br = uni64(it.br);
+    coef = uni64(it.coef);
+    if (jl == 0) {
+      m32[M_SCEN] = it.scen;
+      m32[M_NSRC] = it.n_src;
+      m32[M_NREC] = it.n_rec;
+      m32[M_NTOPO] = it.n_topo;
+      m32[M_MOD0] = cc.mod0[item];
+      m64[M64_BR] = it.br;
+      m64[M64_COEF] = it.coef;
+      m64[M64_NODE] = it.node;
+      m64[M64_TOPO] = it.topo;
+      x[n] = 0.0;
+    }
+    const uint16_t *g_perm = cc.perm + cc.poff[item];
+    for (int i = jl; i < 2 * n; i += SB) perm[i] = g_perm[i];
+    const int32_t *g_nptr = c.nptr + it.nptr;
+    const uint16_t *g_nent = c.nent + it.nent;
+    for (int r = jl; r <= n; r += SB) nptr[r] = g_nptr[r];
+    const int ne = g_nptr[n];
+    for (int e = jl; e < ne; e += SB) nent[e] = g_nent[e];
+    for (int e = jl; e < it.n_rec; e += SB) {
+      rnode[e] = c.rnode[it.rec + e];
+      rcol[e] = c.rcolumn[it.rec + e];
+    }
+    load_corr(cc.mod0[item], t);
+    const int64_t cb0 = coef + (int64_t)t * nbr;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    t[q] = 0;
-    next[q] = step::kNever;
-    pf[q] = 0;
-    pi[q] = 0;
-    if (q < nq) {
-      const ItemDesc it = c.items[cc.list[blk.q0 + q]];
-      const int64_t *topo = c.topo + it.topo;
-      t[q] = step::topo_of(topo, it.n_topo, n0 + 1);
-      next[q] = (t[q] + 1 < it.n_topo) ? topo[t[q] + 1] : step::kNever;
-      const uint16_t *perm = cc.perm + cc.poff[cc.list[blk.q0 + q]];
-      if (tid < n) {
-        pf[q] = perm[tid];
-        pi[q] = perm[n + tid];
-      }
-      step::load_lane<BS, BPT>(c, it, L[q]);
-      step::load_coefs<BS, BPT>(c, it, t[q], L[q].g, L[q].be);
-      View<false> v = view(q, it.n_src);
-      step::history_from_state<BS, BPT, false>(c.si + it.br, c.su + it.br, L[q], v);
-      step::inject<BS, BPT, false>(c, v, L[q], n0 + 1);
-      if (tid == 0) {
-        X(q)[n] = 0.0;
-        WB(q)[n] = 0.0;
-      }
-    } else {
-      // an empty slot: its right-hand side stays zero
-      for (int r = tid; r < n; r += BS) XB(q)[r] = 0.0;
+    for (int j = 0; j < BPT; ++j) {
+      const int b = jl + j * SB;
+      pk[j] = c.bpack[br + b];
+      g[j] = c.cg[cb0 + b];
+      be[j] = c.cb[cb0 + b];
+      const double h = be[j] * c.si[br + b] + step::gamma_of(pk[j], g[j]) * c.su[br + b];
+      if (j == 0)
+        h0 = h;
+      else
+        J[b] = -h;
+    }
+    if (jl < nsrc) {
+      const double sE = c.bE[br + jl], sw = c.bw[br + jl], sph = c.bph[br + jl];
+      src[3 * jl] = sE;
+      src[3 * jl + 1] = sw;
+      src[3 * jl + 2] = sph;
+      e0 = sE * emf_cos(sw * ((double)(n0 + 1) * c.dt) + sph);
+    }
+    J[jl] = g[0] * e0 - h0;
+  } else {
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      pk[j] = 0;
+      g[j] = 0.0;
+      be[j] = 0.0;
     }
   }
-  lds_barrier();
+  step::lds_barrier();
 
   const int R = c.rec_stride;
   const int64_t n_end = n0 + nsteps;
+  // product lanes: (split g, row pr); k range of split g
+  const int rw = (n + 63) / 64 * 64;
+  const int pg = uni(tid / rw), pr = tid - pg * rw;
+  const int kc = ((n + KS - 1) / KS + kChunk - 1) / kChunk * kChunk;
+  const int KSe = (n + kc - 1) / kc;  // splits with a non-empty k range (<= KS)
+  const int k0 = pg * kc, k1 = (pg + 1) * kc < n ? (pg + 1) * kc : n;
+  const bool prod = pg < KSe && pr < n;
   for (int64_t s = n0 + 1; s <= n_end; ++s) {
-    // gather: rhs in the base's node order
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if (q >= nq) continue;
-      const ItemDesc *ip = c.items + cc.list[blk.q0 + q];
-      const int32_t *nptr = c.nptr + ip->nptr;
-      const uint16_t *nent = c.nent + ip->nent;
-      const double *J = reinterpret_cast<const double *>(emt_lds + q * slot + o_j);
-      if (tid < n) {
-        double acc = 0.0;
-        const int e1 = nptr[tid + 1];
-        for (int e = nptr[tid]; e < e1; ++e) {
-          const int ent = nent[e];
-          const double jv = J[ent >> 1];
-          acc = (ent & 1) ? acc - jv : acc + jv;
-        }
-        XB(q)[pf[q]] = acc;
+    // gather: every (item, node) pair of the workgroup, the right-hand
+    // side into the item's x in the base's node order
+    for (int p = tid; p < nq * n; p += BS) {
+      const int q = p / n, r = p - q * n;
+      char *sl = emt_lds + q * S.bytes;
+      const int32_t *np = reinterpret_cast<const int32_t *>(sl + S.nptr);
+      const uint16_t *ne = reinterpret_cast<const uint16_t *>(sl + S.nent);
+      const double *Jq = reinterpret_cast<const double *>(sl + S.J);
+      double acc = 0.0;
+      int e = np[r];
+      const int e1 = np[r + 1];
+      for (; e + 4 <= e1; e += 4) {
+        const int a0 = ne[e], a1 = ne[e + 1], a2 = ne[e + 2], a3 = ne[e + 3];
+        const double j0 = Jq[a0 >> 1], j1 = Jq[a1 >> 1], j2 = Jq[a2 >> 1], j3 = Jq[a3 >> 1];
+        acc = (a0 & 1) ? acc - j0 : acc + j0;
+        acc = (a1 & 1) ? acc - j1 : acc + j1;
+        acc = (a2 & 1) ? acc - j2 : acc + j2;
+        acc = (a3 & 1) ? acc - j3 : acc + j3;
       }
+      for (; e < e1; ++e) {
+        const int a0 = ne[e];
+        const double j0 = Jq[a0 >> 1];
+        acc = (a0 & 1) ? acc - j0 : acc + j0;
+      }
+      const uint16_t *pm = reinterpret_cast<const uint16_t *>(sl + S.perm);
+      reinterpret_cast<double *>(sl + S.x)[pm[r]] = acc;
     }
-    lds_barrier();
-    // product: w = Z rhs for every item (row tid of Z is column tid). Z is
-    // read from L2 in chunks of kChunk rows, the next chunk's loads in
-    // flight while the current one is multiplied; fused multiply-adds.
-    double w[Q];
+    step::lds_barrier();
+    // product: partial sums of w = Z rhs over this lane's k range for every
+    // item of the workgroup (row pr of Z is its column pr). Z comes from L2
+    // in chunks of kChunk rows, the next chunk in flight while the current
+    // one is multiplied.
+    if (prod) {
+      double w[kCompQMax];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) w[q] = 0.0;
-    if (tid < n) {
-      const double *zc = Z + tid;
-      const int nfull = n / kChunk * kChunk;
-      double zb[kChunk];
-      if (nfull > 0) {
+      for (int q = 0; q < kCompQMax; ++q) w[q] = 0.0;
+      const double *zc = Z + opaque(pr);
+      constexpr int CH = 8;
+      const int kf = k0 + (k1 - k0) / CH * CH;
+      double zb[CH];
+      if (kf > k0) {
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) zb[u] = zc[(int64_t)u * n];
+        for (int u = 0; u < CH; ++u) zb[u] = zc[(int64_t)(k0 + u) * n];
       }
-      for (int k = 0; k < nfull; k += kChunk) {
-        double zn[kChunk];
-        const bool more = k + kChunk < nfull;
+      for (int k = k0; k < kf; k += CH) {
+        double zn[CH];
+        const bool more = k + CH < kf;
         if (more) {
 #pragma unroll
-          for (int u = 0; u < kChunk; ++u) zn[u] = zc[(int64_t)(k + kChunk + u) * n];
+          for (int u = 0; u < CH; ++u) zn[u] = zc[(int64_t)(k + CH + u) * n];
         }
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const double2 *xb = reinterpret_cast<const double2 *>(XB(q) + k);
+        for (int q = 0; q < kCompQMax; ++q) {
+          if (q >= nq) break;
+          const double2 *xb = reinterpret_cast<const double2 *>(
+              reinterpret_cast<const double *>(emt_lds + q * S.bytes + S.x) + k);
 #pragma unroll
-          for (int u = 0; u < kChunk / 2; ++u) {
+          for (int u = 0; u < CH / 2; ++u) {
             const double2 a = xb[u];
             w[q] = __builtin_fma(zb[2 * u], a.x, w[q]);
             w[q] = __builtin_fma(zb[2 * u + 1], a.y, w[q]);
@@ -297,37 +447,55 @@ __global__ __launch_bounds__(kCompBS) void k_comp(DevCtx c, CompCtx cc, int64_t 
         }
         if (more) {
 #pragma unroll
-          for (int u = 0; u < kChunk; ++u) zb[u] = zn[u];
+          for (int u = 0; u < CH; ++u) zb[u] = zn[u];
         }
       }
-      for (int k = nfull; k < n; ++k) {
-        const double zk = zc[(int64_t)k * n];
+      if (kf < k1) {
+        double zt[8];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) w[q] = __builtin_fma(zk, XB(q)[k], w[q]);
+        for (int u = 0; u < 8; ++u) zt[u] = (kf + u < k1) ? zc[(int64_t)(kf + u) * n] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (kf + u >= k1) break;
+#pragma unroll
+          for (int q = 0; q < kCompQMax; ++q) {
+            if (q >= nq) break;
+            const double *xb = reinterpret_cast<const double *>(emt_lds + q * S.bytes + S.x);
+            w[q] = __builtin_fma(zt[u], xb[kf + u], w[q]);
+          }
+        }
       }
 #pragma unroll
-      for (int q = 0; q < Q; ++q) WB(q)[tid] = w[q];
+      for (int q = 0; q < kCompQMax; ++q) {
+        if (q >= nq) break;
+        P[(pg * Q + q) * n + pr] = w[q];
+      }
     }
-    lds_barrier();
-    // correction, then the voltages in each item's own node order
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if (q >= nq) continue;
-      const int item = cc.list[blk.q0 + q];
-      const int mi = cc.mod0[item] + t[q];
-      const CompMod *md = cc.mods + mi;
-      const int r = md->r;
-      double v = w[q];
+    step::lds_barrier();
+    // correction: w = sum of the partials; v = w - sum_a (K y)_a Z u_a with
+    // y_a = u_a^T w; the voltages into x in the item's node order; every
+    // (item, node) pair of the workgroup
+    for (int p = tid; p < nq * n; p += BS) {
+      const int q = p / n, i = p - q * n;
+      char *sl = emt_lds + q * S.bytes;
+      const int32_t *mq = reinterpret_cast<const int32_t *>(sl + S.meta);
+      const int r = mq[M_R];
+      double v = 0.0;
+      for (int gg = 0; gg < KSe; ++gg) v = v + P[(gg * Q + q) * n + i];
       if (r > 0) {
-        const double *Kq = cc.K + (int64_t)mi * 16;
-        const double *wb = WB(q);
+        const double *Kr = reinterpret_cast<const double *>(sl + S.K);
+        const double *zq = reinterpret_cast<const double *>(sl + S.zu);
         double y[kCompMaxRank];
 #pragma unroll
         for (int a = 0; a < kCompMaxRank; ++a) {
           y[a] = 0.0;
           if (a < r) {
-            const int ka = md->k[a], ma = md->m[a];
-            y[a] = wb[ka < 0 ? n : ka] - wb[ma < 0 ? n : ma];
+            const int ka = mq[M_K + a], ma = mq[M_M + a];
+            for (int gg = 0; gg < KSe; ++gg) {
+              const double *pw = P + (gg * Q + q) * n;
+              const double wk = ka >= 0 ? pw[ka] : 0.0, wm = ma >= 0 ? pw[ma] : 0.0;
+              y[a] = y[a] + (wk - wm);
+            }
           }
         }
 #pragma unroll
@@ -336,62 +504,75 @@ __global__ __launch_bounds__(kCompBS) void k_comp(DevCtx c, CompCtx cc, int64_t 
           double za = 0.0;
 #pragma unroll
           for (int b = 0; b < kCompMaxRank; ++b)
-            if (b < r) za = za + Kq[a * 4 + b] * y[b];
-          if (tid < n) {
-            const int ka = md->k[a], ma = md->m[a];
-            const double zk = ka >= 0 ? Z[(int64_t)ka * n + tid] : 0.0;
-            const double zm = ma >= 0 ? Z[(int64_t)ma * n + tid] : 0.0;
-            v = v - za * (zk - zm);
-          }
+            if (b < r) za = za + Kr[a * 4 + b] * y[b];
+          v = v - za * zq[a * n + i];
         }
       }
-      if (tid < n) X(q)[pi[q]] = v;
+      const uint16_t *pm = reinterpret_cast<const uint16_t *>(sl + S.perm);
+      reinterpret_cast<double *>(sl + S.x)[pm[n + i]] = v;
     }
-    lds_barrier();
+    step::lds_barrier();
     // record, branch update, next injections
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if (q >= nq) continue;
-      const ItemDesc *ip = c.items + cc.list[blk.q0 + q];
-      const double *x = X(q);
+    if (mine) {
       if (rec) {
-        double *row = rec + ((int64_t)ip->scen * nsteps + (s - n0 - 1)) * R;
-        const uint16_t *rnode = c.rnode + ip->rec, *rcol = c.rcolumn + ip->rec;
-        for (int e = tid; e < ip->n_rec; e += BS) row[rcol[e]] = x[rnode[e]];
+        double *row = rec + ((int64_t)uni(m32[M_SCEN]) * nsteps + (s - n0 - 1)) * R;
+        const int nrec = uni(m32[M_NREC]);
+        for (int e = jl; e < nrec; e += SB) row[rcol[e]] = x[rnode[e]];
       }
-      const bool sw = (s + 1 == next[q]);
-      double *st_i = nullptr, *st_u = nullptr;
-      if (s == n_end) {
-        st_i = c.si + ip->br;
-        st_u = c.su + ip->br;
+      const bool swn = (s + 1 == next);
+      const bool inj = s < n_end;
+      const int64_t ncoef = coef + (int64_t)(t + 1) * nbr;
+      double e_next = 0.0;
+      if (inj && jl < nsrc) e_next = src[3 * jl] * emf_cos(src[3 * jl + 1] * ((double)(s + 1) * c.dt) + src[3 * jl + 2]);
+      const int jo = opaque(jl);
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) {
+        const int b = jo + j * SB;
+        const double vk = x[pk[j] & kTermGround], vm = x[(pk[j] >> 15) & kTermGround];
+        const double e = j == 0 ? e0 : 0.0;
+        const double h = j == 0 ? h0 : -J[b];
+        const double u = (g[j] != 0.0) ? (vk - vm) - e : 0.0;
+        const double i = g[j] * u + h;
+        if (s == n_end) {
+          c.si[br + b] = i;
+          c.su[br + b] = u;
+        }
+        if (swn) {
+          g[j] = c.cg[ncoef + b];
+          be[j] = c.cb[ncoef + b];
+        }
+        const double hn = be[j] * i + step::gamma_of(pk[j], g[j]) * u;
+        if (j == 0) {
+          h0 = hn;
+          if (inj) J[b] = g[j] * e_next - hn;
+        } else if (inj) {
+          J[b] = -hn;
+        }
       }
-      const View<false> v = view(q, ip->n_src);
-      step::update_inject<BS, BPT, false, false>(c, v, L[q], nullptr, nullptr, st_i, st_u, sw,
-                                                 ip->coef + (int64_t)(t[q] + 1) * nbr, s < n_end, s);
-      if (sw) {
-        ++t[q];
-        const int64_t *topo = c.topo + ip->topo;
-        next[q] = (t[q] + 1 < ip->n_topo) ? topo[t[q] + 1] : step::kNever;
+      e0 = e_next;
+      if (swn) {
+        ++t;
+        const int64_t *topo = c.topo + uni64(m64[M64_TOPO]);
+        next = uni64((t + 1 < uni(m32[M_NTOPO])) ? topo[t + 1] : step::kNever);
+        load_corr(uni(m32[M_MOD0]), t);
       }
     }
-    lds_barrier();
+    step::lds_barrier();
   }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    if (q >= nq) continue;
-    const ItemDesc *ip = c.items + cc.list[blk.q0 + q];
-    for (int r = tid; r < n; r += BS) c.sv_state[ip->node + r] = X(q)[r];
+  if (mine) {
+    const int64_t node = uni64(m64[M64_NODE]);
+    for (int r = jl; r < n; r += SB) c.sv_state[node + r] = x[r];
   }
 }
 
-template <int BPT, int Q>
-hipError_t comp_launch(const DevCtx &c, const CompCtx &cc, int n_blocks, int64_t n0, int64_t ns, double *rec,
-                       size_t lds, hipStream_t st) {
-  auto k = k_comp<BPT, Q>;
+template <int SB, int BPT>
+hipError_t comp_launch(const DevCtx &c, const CompCtx &cc, int q, int lanes, int n_blocks, int64_t n0, int64_t ns,
+                       double *rec, size_t lds, hipStream_t st) {
+  auto k = k_comp<SB, BPT>;
   hipError_t e =
       hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n_blocks), dim3(kCompBS), lds, st, c, cc, n0, ns, rec);
+  hipLaunchKernelGGL(k, dim3(n_blocks), dim3(lanes), lds, st, c, cc, q, n0, ns, rec);
   return hipGetLastError();
 }
 
@@ -399,29 +580,34 @@ int blocks_of(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
 
-size_t comp_lds_bytes(int n, int nbr, int q) { return (size_t)q * comp_slot_bytes(n, nbr); }
+int comp_lanes(int n, int q, int sb) {
+  const int pairs = (n * q + 63) / 64 * 64;  // (item, node) pairs in whole waves
+  const int l = sb * q > pairs ? sb * q : pairs;
+  return l > 1024 ? 1024 : l;
+}
 
-// (branches per lane, items per workgroup) pairs with an instantiated kernel
-#define EMT_COMP_SHAPES(X)                                          \
-  X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(1, 5) X(1, 6)                   \
-  X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6)                   \
-  X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6)                   \
-  X(6, 1) X(6, 2) X(6, 3) X(6, 4) X(6, 5) X(6, 6)                   \
-  X(8, 1) X(8, 2) X(8, 3) X(8, 4) X(12, 1) X(12, 2) X(12, 3)        \
-  X(16, 1) X(16, 2)
+size_t comp_lds_bytes(int n, int nbr, int q, int ne, int nr, int ns, int sb) {
+  return comp_lds(n, nbr, ne, nr, ns, q, comp_lanes(n, q, sb));
+}
 
-bool comp_shape_exists(int bpt, int q) {
-#define EMT_CASE(B, Q) \
-  if (bpt == B && q == Q) return true;
+// (lanes per item, branch slots per lane) pairs with an instantiated kernel
+#define EMT_COMP_SB(X, SB) X(SB, 1) X(SB, 2) X(SB, 3) X(SB, 4) X(SB, 5) X(SB, 6) X(SB, 7) X(SB, 8)
+#define EMT_COMP_SHAPES(X) EMT_COMP_SB(X, 64) EMT_COMP_SB(X, 128) EMT_COMP_SB(X, 192) EMT_COMP_SB(X, 256)
+
+bool comp_shape_exists(int sb, int bpt, int q) {
+  if (q < 1 || q > kCompQMax || sb * q > 1024) return false;
+#define EMT_CASE(SB, B) \
+  if (sb == SB && bpt == B) return true;
   EMT_COMP_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return false;
 }
 
-hipError_t launch_comp(const DevCtx &c, const CompCtx &cc, int bpt, int q, int n_blocks, int64_t n0, int64_t ns,
-                       double *rec, size_t lds, hipStream_t st) {
-#define EMT_CASE(B, Q) \
-  if (bpt == B && q == Q) return comp_launch<B, Q>(c, cc, n_blocks, n0, ns, rec, lds, st);
+hipError_t launch_comp(const DevCtx &c, const CompCtx &cc, int sb, int bpt, int q, int lanes, int n_blocks,
+                       int64_t n0, int64_t ns, double *rec, size_t lds, hipStream_t st) {
+  if (!comp_shape_exists(sb, bpt, q) || lanes < sb * q || lanes > 1024 || lanes % 64) return hipErrorInvalidValue;
+#define EMT_CASE(SB, B) \
+  if (sb == SB && bpt == B) return comp_launch<SB, B>(c, cc, q, lanes, n_blocks, n0, ns, rec, lds, st);
   EMT_COMP_SHAPES(EMT_CASE)
 #undef EMT_CASE
   return hipErrorInvalidValue;

@@ -61,6 +61,8 @@ hipError_t launch_barrier_floor(int bs, int n_blocks, int phases, int64_t nsteps
     case 64: return floor_launch<64>(n_blocks, phases, nsteps, lds, out, st);
     case 256: return floor_launch<256>(n_blocks, phases, nsteps, lds, out, st);
     case 512: return floor_launch<512>(n_blocks, phases, nsteps, lds, out, st);
+    case 128: return floor_launch<128>(n_blocks, phases, nsteps, lds, out, st);
+    case 1024: return floor_launch<1024>(n_blocks, phases, nsteps, lds, out, st);
     default: return hipErrorInvalidValue;
   }
 }

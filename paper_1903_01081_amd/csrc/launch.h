@@ -100,13 +100,15 @@ hipError_t launch_steady(const DevCtx &c, int n_items, const int64_t *off_l, con
 
 hipError_t launch_or_flag(int32_t *dst, const int32_t *src, hipStream_t st);
 
-// Compensation solver (comp.hip): LDS of a step workgroup of q items, the
-// (branches per lane, items) shapes that have a kernel, the step launch, and
+// Compensation solver (comp.hip): lanes and LDS of a step workgroup of q
+// items (sb lanes each for their branch phase), the (lanes per item,
+// branches per lane, items) shapes that have a kernel, the step launch, and
 // the factor work (bases' inverses, parameter check, K per item and topology).
-size_t comp_lds_bytes(int n, int nbr, int q);
-bool comp_shape_exists(int bpt, int q);
-hipError_t launch_comp(const DevCtx &c, const CompCtx &cc, int bpt, int q, int n_blocks, int64_t n0, int64_t ns,
-                       double *rec, size_t lds, hipStream_t st);
+int comp_lanes(int n, int q, int sb);
+size_t comp_lds_bytes(int n, int nbr, int q, int ne, int nr, int ns, int sb);
+bool comp_shape_exists(int sb, int bpt, int q);
+hipError_t launch_comp(const DevCtx &c, const CompCtx &cc, int sb, int bpt, int q, int lanes, int n_blocks,
+                       int64_t n0, int64_t ns, double *rec, size_t lds, hipStream_t st);
 hipError_t launch_comp_factor(const DevCtx &c, const CompCtx &cc, hipStream_t st);
 
 // Latency floors (floor.hip; the split floor is launch_split with floor set).

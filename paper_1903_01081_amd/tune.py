@@ -10,7 +10,9 @@ The choices (all fields of emt_sim, see include/emt.h):
     workgroup, larger ones split by columns over 16- or 32-column
     workgroups (forward only, so skipped when checkpoints are asked for);
   * "auto" with a scenario's small components packed into shared
-    workgroups (pack_nodes 256 or 512), where that changes the work items.
+    workgroups (pack_nodes 256 or 512), where that changes the work items;
+  * solver "compensation" (scenarios that differ from the first one by a
+    few switched branches share its components' inverses; forward only).
 Every candidate factorises and runs the same prefix of `probe_steps` steps
 (recorded like the real run) twice; the second run's factorisation time
 plus n_steps times its time per step ranks it, so a long horizon is not
@@ -47,6 +49,8 @@ def candidates(checkpoint_every: int = 0) -> List[dict]:
     # packing changes the batch's work items)
     c += [dict(solver="auto", pack_nodes=p) for p in PACK_BUDGETS]
     c += [dict(solver="auto", block_size=256, dense_tail=64, pack_nodes=p) for p in PACK_BUDGETS]
+    if checkpoint_every == 0:
+        c.append(dict(solver="compensation"))
     return c
 
 
@@ -93,13 +97,15 @@ def _time_one(nets, dt, n_steps, checkpoint_every, shape, probe_steps, device):
 
 
 def tune(nets: Sequence, dt: float, n_steps: int, checkpoint_every: int = 0, probe_steps: int = 400,
-         shapes: Optional[List[dict]] = None, device=None) -> dict:
+         shapes: Optional[List[dict]] = None, device=None, exclude_solvers: Sequence[str] = ()) -> dict:
     """Returns {"shape": best shape (Simulator keyword arguments),
     "s_per_step": its time per step on the probe (forward, plus adjoint
     with checkpoints), "run_s": its estimated factorisation + n_steps time,
-    "trials": [...]}."""
+    "trials": [...]}. Solvers named in exclude_solvers are not tried."""
     trials = []
     for shape in (shapes if shapes is not None else candidates(checkpoint_every)):
+        if shape.get("solver") in exclude_solvers:
+            continue
         if shapes is None and not _packing_changes_items(nets, dt, n_steps, checkpoint_every, shape):
             continue
         try:

@@ -172,7 +172,7 @@ def test_comp_refusals(torch_cuda):
     from paper_1903_01081_amd.sim import EMTError, Simulator
     nets, cfg = small_n1()
     dt, T = cfg["dt"], cfg["n_steps"]
-    with pytest.raises(EMTError, match="256 lanes"):
+    with pytest.raises(EMTError, match="lanes per component"):
         Simulator(nets, dt, T, solver="compensation", block_size=512)
     with pytest.raises(EMTError, match="forward only"):
         Simulator(nets, dt, T, solver="compensation", checkpoint_every=100)

@@ -5,7 +5,7 @@ from paper_1903_01081_amd.tune import candidates
 def test_candidates_cover_every_solver_and_shape():
     c = candidates(0)
     solvers = {s["solver"] for s in c}
-    assert solvers == {"auto", "sparse", "dense"}
+    assert solvers == {"auto", "sparse", "dense", "compensation"}
     assert {s.get("block_size") for s in c if s["solver"] == "auto"} >= {0, 64, 256, 512}
     assert {s.get("dense_tail") for s in c if s["solver"] == "auto"} >= {64, 128}
     assert {s.get("split_cols") for s in c if s["solver"] == "dense"} == {16, 32}
@@ -28,3 +28,8 @@ def test_packing_candidates_only_where_they_change_the_items():
     assert not _packing_changes_items(big, cfg["dt"], 10, 0, shape)
     assert _packing_changes_items(small, cfg4["dt"], 10, 0, shape)
     assert _packing_changes_items(big, cfg["dt"], 10, 0, dict(solver="auto"))
+
+
+def test_compensation_candidate_only_without_checkpoints():
+    assert dict(solver="compensation") in candidates(0)
+    assert all(s["solver"] != "compensation" for s in candidates(500))
