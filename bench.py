@@ -120,6 +120,9 @@ KERNELS = {
                    "paper_1903_01081_amd/csrc/device.h"), "profiles/k_forward_grid1000.md"),
     "k_split": (("paper_1903_01081_amd/csrc/split.hip", "paper_1903_01081_amd/csrc/step.h",
                  "paper_1903_01081_amd/csrc/device.h"), "profiles/k_split_grid1000.md"),
+    "k_comp": (("paper_1903_01081_amd/csrc/comp.hip", "paper_1903_01081_amd/csrc/comp.h",
+                "paper_1903_01081_amd/csrc/step.h", "paper_1903_01081_amd/csrc/device.h"),
+               "profiles/k_comp_n1_grid200.md"),
 }
 KERNEL_SOURCES, TRAFFIC_PROFILE = KERNELS["k_forward"]
 
@@ -295,13 +298,15 @@ def comp_roofline_object(info, nets, time_steps, kernel_s):
     flops = 2 * sum(c * c for c in sizes) + 10 * info["total_branches"]
     tflops = flops * time_steps / kernel_s / 1e12
     z_bytes = info["comp_blocks"] * 8 * float(np.mean([c * c for c in fam]))
+    traffic = measured_traffic("k_comp")
     return {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": tflops / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": tflops / FP64_PEAK_TFLOPS, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": "k_comp", "kernel_s": kernel_s, "time_steps": time_steps,
             "fp64_flops_per_time_step": flops, "l2_z_bytes_per_time_step": z_bytes,
             "l2_gbs": z_bytes * time_steps / kernel_s / 1e9,
-            "comp_items": info["comp_items"], "comp_blocks": info["comp_blocks"]}
+            "comp_items": info["comp_items"], "comp_blocks": info["comp_blocks"],
+            "limiter": "L2 throughput of the Z stream (see l2_gbs)"}
 
 
 def batched_n1(torch, exclude_solvers=()):
