@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "analysis.h"
+#include "comp_plan.h"
 
 namespace {
 
@@ -94,6 +95,20 @@ int run(const char *label, const std::vector<emt_net> &nets, const emt_sim &sim)
   }
 }
 
+// The compensation solver's plan on top of the analysis (families, node
+// maps, branch matching, switched branches).
+int run_comp(const char *label, const std::vector<emt_net> &nets, const emt_sim &sim) {
+  try {
+    emt::Analysis a = emt::analyze(nets.data(), (int)nets.size(), sim);
+    emt::CompPlan p = emt::plan_compensation(a, nets.data(), sim);
+    std::printf("%s comp families %d rank %d mods %d\n", label, (int)p.fams.size(), p.max_rank, (int)p.mods.size());
+    return 0;
+  } catch (const emt::Error &e) {
+    std::printf("%s error %d\n", label, (int)e.status);
+    return (int)e.status;
+  }
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
@@ -130,6 +145,15 @@ int main(int argc, char **argv) {
         const int st = run(label, views, s);
         if (st != 0 && st != EMT_EINVAL) bad = 1;
       }
+  for (int K : {0, 50}) {
+    emt_sim s = base;
+    s.solver = EMT_SOLVER_COMPENSATION;
+    s.checkpoint_every = K;
+    char label[64];
+    std::snprintf(label, sizeof label, "compensation K %d", K);
+    const int st = run_comp(label, views, s);
+    if (st != 0 && st != EMT_EINVAL) bad = 1;
+  }
   for (int d : {0, 16, 48, 128}) {
     emt_sim s = base;
     s.dense_tail = d;

@@ -1,6 +1,7 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU):
 the network analysis of the library (validation, connected components,
-ordering, symbolic LDL^T, sweep levels, dense-tail choice) is built from its
+ordering, symbolic LDL^T, sweep levels, dense-tail choice, the compensation
+solver's plan) is built from its
 sources with g++ -fsanitize=address,undefined, errors fatal, and run on the
 seeded workloads' networks under every solver and launch-shape setting and
 on invalid inputs (tests/host_asan/analysis_driver.cpp)."""
@@ -49,6 +50,7 @@ def driver(tmp_path_factory):
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_1903_01081_amd", "csrc"),
            os.path.join(ROOT, "paper_1903_01081_amd", "csrc", "analysis.cpp"),
+           os.path.join(ROOT, "paper_1903_01081_amd", "csrc", "comp_plan.cpp"),
            os.path.join(ROOT, "tests", "host_asan", "analysis_driver.cpp"), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
@@ -59,6 +61,7 @@ BATCHES = {
     "nine_bus": lambda: netgen.config0(n_steps=400)[0],
     "grid_events": lambda: [netgen.small_grid(5, 40, fault_step=30, remove_series=2, remove_step=60, n_mon=8)],
     "n1_sample": lambda: netgen.config2(n_scen=6)[0],
+    "n1_events": lambda: netgen.config2(n_bus=20, n_scen=6, n_steps=400, event_step=100)[0],
     "uneven_sample": lambda: netgen.config4(n_inst=8, n_steps=400)[0],
     "grid1000": lambda: netgen.config1(n_steps=400)[0],
     "travelling_wave": lambda: [netgen.small_grid(7, 30, fault_step=30, travelling_wave_dt=20e-6),
@@ -80,3 +83,11 @@ def test_analysis_clean_under_sanitizers(driver, tmp_path, name):
     sizes = {tuple(s.split()[:4]) for s in ok}
     assert len(sizes) == 1, sizes
     assert sum("pack_nodes" in ln and " ok " in ln for ln in r.stdout.splitlines()) == 3, r.stdout
+    # the compensation plan: forward only; the N-1 batch plans
+    assert "compensation K 50 error 1" in r.stdout, r.stdout
+    if name == "n1_sample":
+        # (its events lie past the driver's 400-step horizon: one topology)
+        assert "compensation K 0 comp families 3 rank 0" in r.stdout, r.stdout
+    if name == "n1_events":
+        # a removed branch and a fault from step 100: two switched branches
+        assert "compensation K 0 comp families 3 rank 2" in r.stdout, r.stdout
