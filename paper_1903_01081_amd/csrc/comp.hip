@@ -420,18 +420,29 @@ __global__ __launch_bounds__(1024) void k_comp(DevCtx c, CompCtx cc, int Q, int6
       for (int q = 0; q < kCompQMax; ++q) w[q] = 0.0;
       const double *zc = Z + opaque(pr);
       constexpr int CH = 8;
-      const int kf = k0 + (k1 - k0) / CH * CH;
+      const int nch = (k1 - k0) / CH, kf = k0 + nch * CH;
+      // the workgroups of a family walk their chunks from different starts,
+      // so that they do not all ask the same L2 channels for the same rows
+      // at once
+      const int c0 = nch > 0 ? (int)(blockIdx.x % (unsigned)nch) : 0;
       double zb[CH];
-      if (kf > k0) {
+      if (nch > 0) {
+        const int ks = k0 + c0 * CH;
 #pragma unroll
-        for (int u = 0; u < CH; ++u) zb[u] = zc[(int64_t)(k0 + u) * n];
+        for (int u = 0; u < CH; ++u) zb[u] = zc[(int64_t)(ks + u) * n];
       }
-      for (int k = k0; k < kf; k += CH) {
+      for (int ci = 0; ci < nch; ++ci) {
+        int cc0 = c0 + ci;
+        if (cc0 >= nch) cc0 -= nch;
+        const int k = k0 + cc0 * CH;
+        int cn = cc0 + 1;
+        if (cn >= nch) cn -= nch;
+        const int kn = k0 + cn * CH;
         double zn[CH];
-        const bool more = k + CH < kf;
+        const bool more = ci + 1 < nch;
         if (more) {
 #pragma unroll
-          for (int u = 0; u < CH; ++u) zn[u] = zc[(int64_t)(k + CH + u) * n];
+          for (int u = 0; u < CH; ++u) zn[u] = zc[(int64_t)(kn + u) * n];
         }
 #pragma unroll
         for (int q = 0; q < kCompQMax; ++q) {
