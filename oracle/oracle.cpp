@@ -69,7 +69,7 @@
 
 namespace {
 
-enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4, K_LINE = 5, K_DIODE = 6 };
+enum { K_RL = 0, K_C = 1, K_R = 2, K_SWITCH = 3, K_SRC = 4, K_LINE = 5, K_DIODE = 6, K_CSWITCH = 7 };
 
 }  // namespace
 
@@ -94,6 +94,9 @@ struct OracleNet {
   // the mutual entries of each group's circulant R, L or C matrix
   const int32_t *group;
   const double *Rm, *Lm, *Cm;
+  // controlled switches (may be null if there is none): the measured node
+  // pair of each branch, [2 n_branches]
+  const int32_t *meas;
 };
 
 }  // extern "C"
@@ -331,7 +334,15 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
     const int k = net.k[b], m = net.m[b];
     if (k < -1 || k >= net.n_nodes || m < -1 || m >= net.n_nodes) return false;
     if (k < 0 && m < 0) return false;
-    if (net.kind[b] < 0 || net.kind[b] > 6) return false;
+    if (net.kind[b] < 0 || net.kind[b] > 7) return false;
+    if (net.kind[b] == K_CSWITCH) {
+      if (!(net.R[b] > 0) || !(net.L[b] >= 0) || !std::isfinite(net.L[b]) || !std::isfinite(net.C[b]) ||
+          !std::isfinite(net.E[b]) || !std::isfinite(net.omega[b]) || !std::isfinite(net.phase[b]) || !net.meas ||
+          net.line[b] >= 0 || (net.group && net.group[b] >= 0))
+        return false;
+      for (int e2 = 0; e2 < 2; ++e2)
+        if (net.meas[2 * b + e2] < -1 || net.meas[2 * b + e2] >= net.n_nodes) return false;
+    }
     if (net.kind[b] == K_DIODE && (!(net.R[b] > 0) || net.line[b] >= 0 || (net.group && net.group[b] >= 0)))
       return false;
     if (net.kind[b] == K_LINE &&
@@ -341,7 +352,9 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
   for (int j = 0; j < net.n_events; ++j) {
     if (net.ev_step[j] < 1) return false;
     if (net.ev_branch[j] < 0 || net.ev_branch[j] >= net.n_branches) return false;
-    if (net.kind[net.ev_branch[j]] == K_LINE || net.kind[net.ev_branch[j]] == K_DIODE) return false;
+    if (net.kind[net.ev_branch[j]] == K_LINE || net.kind[net.ev_branch[j]] == K_DIODE ||
+        net.kind[net.ev_branch[j]] == K_CSWITCH)
+      return false;
   }
   for (int r = 0; r < net.n_rec; ++r)
     if (net.rec_nodes && (net.rec_nodes[r] < 0 || net.rec_nodes[r] >= net.n_nodes)) return false;
@@ -376,9 +389,10 @@ bool valid(const OracleNet &net, double dt, int64_t T) {
 
 bool has_groups(const OracleNet &net) { return !group_members(net).empty(); }
 
+// Diodes and controlled switches: branches whose state the run itself sets.
 bool has_diodes(const OracleNet &net) {
   for (int b = 0; b < net.n_branches; ++b)
-    if (net.kind[b] == K_DIODE) return true;
+    if (net.kind[b] == K_DIODE || net.kind[b] == K_CSWITCH) return true;
   return false;
 }
 
@@ -552,6 +566,22 @@ int forward(const OracleNet &net, const T *theta, double dt, int64_t Tn,
         flipped = true;
       } else if (!ins[b] && re(vk - vm) > 0.0) {
         ins[b] = 1;
+        flipped = true;
+      }
+    }
+    // controlled switches: a hysteresis comparator on the measured voltage
+    // s = v_a - v_b of this step against the reference r = E cos(w t + phi)
+    // + C at this step's time sets the switch for the next step: on above
+    // the band (e = r - s > h), off below it (e < -h), unchanged inside
+    for (int b = 0; b < B; ++b) {
+      if (net.kind[b] != K_CSWITCH) continue;
+      const int a0 = net.meas[2 * b], a1 = net.meas[2 * b + 1];
+      const double sv = re(a0 >= 0 ? v[a0] : T(0)) - re(a1 >= 0 ? v[a1] : T(0));
+      const double r = net.E[b] * std::cos(net.omega[b] * ((double)n * dt) + net.phase[b]) + net.C[b];
+      const double err = r - sv, hw = net.L[b];
+      const uint8_t want = err > hw ? 1 : (err < -hw ? 0 : ins[b]);
+      if (want != ins[b]) {
+        ins[b] = want;
         flipped = true;
       }
     }

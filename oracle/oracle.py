@@ -40,6 +40,7 @@ class _Net(C.Structure):
         ("ev_in_service", C.c_void_p),
         ("n_rec", C.c_int32), ("rec_nodes", C.c_void_p),
         ("group", C.c_void_p), ("Rm", C.c_void_p), ("Lm", C.c_void_p), ("Cm", C.c_void_p),
+        ("meas", C.c_void_p),
     ]
 
 
@@ -120,6 +121,8 @@ class _Packed:
         grp = getattr(net, "group", None)
         for f, dt_ in (("group", np.int32), ("Rm", np.float64), ("Lm", np.float64), ("Cm", np.float64)):
             self.arrs[f] = None if grp is None else np.ascontiguousarray(getattr(net, f), dt_)
+        meas = getattr(net, "meas", None)
+        self.arrs["meas"] = None if meas is None else np.ascontiguousarray(meas, np.int32).reshape(-1)
         a = self.arrs
         self.n_rec = net.n_nodes if a["rec"] is None else int(a["rec"].shape[0])
         self.n_params = 3 * int(net.n_lines)
@@ -130,7 +133,7 @@ class _Packed:
                       _ptr(a["omega"]), _ptr(a["phase"]), _ptr(a["line"]), self.n_params,
                       _ptr(a["ins"]), n_ev, _ptr(a["ev_step"]), _ptr(a["ev_branch"]),
                       _ptr(a["ev_ins"]), self.n_rec, _ptr(a["rec"]), _ptr(a["group"]), _ptr(a["Rm"]),
-                      _ptr(a["Lm"]), _ptr(a["Cm"]))
+                      _ptr(a["Lm"]), _ptr(a["Cm"]), _ptr(a["meas"]))
 
     @property
     def ref(self):

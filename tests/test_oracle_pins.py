@@ -870,3 +870,94 @@ def test_diode_rejections(oracle_mod):
         oracle_mod.adjoint(net, 50e-6, 20, np.zeros((20, net.n_rec)))
     with pytest.raises(Exception):
         oracle_mod.steady_state(net, 50e-6)
+
+
+# ---------------------------------------------------------------------------
+# Controlled switches: one hysteresis comparator per switch (a control-system
+# vertex) reads the measured voltage of a step and sets the switch for the
+# next step: on when the reference exceeds it by more than the half-width h,
+# off when it falls short by more than h, unchanged in between.
+# ---------------------------------------------------------------------------
+
+from paper_1903_01081_amd.netgen import CSWITCH  # noqa: E402
+
+
+def _chopper(ref_E, ref_w, ref_phase, ref_C, h, meas, kind=CSWITCH, on=1, E=10.0, w=0.0, R_on=1e-2,
+             R_s=1.0, Cdc=1e-3, R_L=20.0):
+    # source -> (switch) -> node 1 with a capacitor and a load resistor
+    return netgen.circuit(2, [
+        dict(k=0, m=-1, kind=SRC, R=R_s, L=1e-4, E=E, omega=w, phase=0.0),
+        dict(k=0, m=1, kind=kind, R=R_on, E=ref_E, omega=ref_w, phase=ref_phase, C=ref_C, L=h, meas=meas,
+             ins=on),
+        dict(k=1, m=-1, kind=CAP, C=Cdc),
+        dict(k=1, m=-1, kind=RES, R=R_L),
+    ])
+
+
+def test_cswitch_open_loop_schedule_is_the_closed_form(oracle_mod):
+    # measuring ground against ground, the comparator sees only its
+    # reference: the switch state of every step follows from the reference
+    # alone, and the switch carries current exactly when that state is on
+    dt, T = 20e-6, 3000
+    E_r, w_r, ph, C_r, h = 1.0, 2 * math.pi * 50, 0.3, 0.1, 0.3
+    net = _chopper(E_r, w_r, ph, C_r, h, (-1, -1), E=10.0, w=2 * math.pi * 60)
+    _, vt, it, ut = oracle_mod.run(net, dt, T, trajectories=True)
+    state = np.zeros(T + 1, bool)
+    state[1] = True  # in service before step 1
+    for n in range(1, T):
+        e = E_r * math.cos(w_r * n * dt + ph) + C_r
+        state[n + 1] = True if e > h else (False if e < -h else state[n])
+    i_sw = it[1:, 1]
+    assert np.array_equal(i_sw != 0.0, state[1:])
+    assert np.count_nonzero(np.diff(state[1:].astype(int))) == 6  # three reference periods
+    on = state[1:]
+    assert np.max(np.abs(i_sw[on] - ut[1:, 1][on] / 1e-2)) <= 1e-12 * np.max(np.abs(i_sw))
+
+
+def test_cswitch_that_never_changes_is_a_fixed_branch(oracle_mod):
+    # a band wider than any error: the switch keeps its initial state and the
+    # run is, bit for bit, that of a resistor of R_on (on) or an open switch
+    dt, T = 20e-6, 1500
+    a = oracle_mod.run(_chopper(1.0, 0.0, 0.0, 0.0, 1e30, (1, -1)), dt, T)
+    b = oracle_mod.run(_chopper(1.0, 0.0, 0.0, 0.0, 1e30, (1, -1), kind=RES), dt, T)
+    assert np.array_equal(a, b)
+    a = oracle_mod.run(_chopper(1.0, 0.0, 0.0, 0.0, 1e30, (1, -1), on=0), dt, T)
+    b = oracle_mod.run(_chopper(1.0, 0.0, 0.0, 0.0, 1e30, (1, -1), kind=SWITCH, on=0), dt, T)
+    assert np.array_equal(a, b)
+
+
+def test_cswitch_feedback_holds_the_band(oracle_mod):
+    # bang-bang control of the capacitor voltage: 10 V through 1 ohm into
+    # 1 mF with a 20 ohm load, reference 5 V, half-width 0.2 V. Once the
+    # voltage reaches the band it stays within it, widened by what one step
+    # can change it (the decision acts one step late): |dv/dt| <= E / (R C)
+    # while charging and v / (R_L C) while discharging
+    dt, T = 20e-6, 20000
+    V_ref, h, E, R_s, Cdc, R_L = 5.0, 0.2, 10.0, 1.0, 1e-3, 20.0
+    net = _chopper(0.0, 0.0, 0.0, V_ref, h, (1, -1), E=E, R_s=R_s + 1e-2, Cdc=Cdc, R_L=R_L, on=1)
+    _, vt, it, _ = oracle_mod.run(net, dt, T, trajectories=True)
+    v = vt[:, 1]
+    first = int(np.argmax(v >= V_ref - h))
+    assert first > 0
+    d = dt * E * (1.0 / ((R_s + 1e-2) * Cdc) + 1.0 / (R_L * Cdc))
+    assert np.all(v[first:] >= V_ref - h - d) and np.all(v[first:] <= V_ref + h + d)
+    toggles = np.count_nonzero(np.diff((it[first:, 1] != 0.0).astype(int)))
+    assert toggles > 20
+    # a reversed comparator (reference below what it measures by construction)
+    # would leave the switch open for good: here the mean stays near V_ref
+    assert abs(np.mean(v[first:]) - V_ref) < h + d
+
+
+def test_cswitch_rejections(oracle_mod):
+    net = _chopper(1.0, 0.0, 0.0, 0.0, 0.1, (1, -1))
+    with pytest.raises(Exception):
+        oracle_mod.adjoint(net, 50e-6, 20, np.zeros((20, net.n_rec)))
+    with pytest.raises(Exception):
+        oracle_mod.steady_state(net, 50e-6)
+    bad = _chopper(1.0, 0.0, 0.0, 0.0, -0.1, (1, -1))  # negative half-width
+    with pytest.raises(Exception):
+        oracle_mod.run(bad, 50e-6, 20)
+    ev = _chopper(1.0, 0.0, 0.0, 0.0, 0.1, (1, -1))
+    ev.ev_step, ev.ev_branch, ev.ev_in_service = np.array([5]), np.array([1], np.int32), np.array([0], np.uint8)
+    with pytest.raises(Exception):
+        oracle_mod.run(ev, 50e-6, 20)
