@@ -74,7 +74,8 @@ typedef enum {
 } emt_status;
 
 typedef enum {
-  EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5, EMT_DIODE = 6
+  EMT_RL = 0, EMT_C = 1, EMT_R = 2, EMT_SWITCH = 3, EMT_SRC = 4, EMT_LINE = 5, EMT_DIODE = 6,
+  EMT_CSWITCH = 7
 } emt_kind;
 
 typedef enum {
@@ -111,6 +112,19 @@ typedef enum {
  *              rule rings when a diode interrupts an inductor's current, so
  *              a diode can chatter after it blocks (no damping step is
  *              added).
+ *              CSWITCH (a switch driven by a control-system vertex: the
+ *              control graph of Sec. III-A's basic processes reduced to one
+ *              hysteresis comparator per switch): R = its on-resistance > 0;
+ *              the comparator's reference r(t) = E cos(omega t + phase) + C
+ *              (E, omega, phase, C finite) and half-width h = L >= 0; it
+ *              measures s = v_a - v_b, the nodes a = meas[2b], b = meas[2b+1]
+ *              (-1 = ground; in the switch's connected component). After
+ *              step n, with e = r(n dt) - s(n): the switch conducts from
+ *              step n+1 on if e > h, is open if e < -h, else keeps its state
+ *              (the one-step delay breaks the algebraic loop between the
+ *              controller and the network it measures); in_service0 is its
+ *              state before step 1. Like diodes: refactorised inside the
+ *              loop, no events, forward only, sweep solvers.
  *   E, omega, phase  source EMF E cos(omega t + phase); read for EMT_SRC only.
  *   line       pi-section line index l of the branch, or -1. Line parameters
  *              theta[3l + {0,1,2}] = (R_l, L_l, C_l) are the series R and L
@@ -123,6 +137,8 @@ typedef enum {
  *              ignored) branch ev_branch[j] goes in service
  *              (ev_in_service[j] = 1) or out (0).
  *   rec_nodes  the n_rec recorded nodes (NULL = all nodes, n_rec = n_nodes).
+ *   meas       [2 n_branches] the measured node pairs of CSWITCH branches
+ *              (read for CSWITCH only; NULL if there is none).
  *   group, Rm, Lm, Cm  coupled three-phase groups (NULL = none; the
  *              per-component Norton equivalents of Sec. III-A's first basic
  *              process with 3 x 3 blocks): group[b] = g >= 0 puts branch b in
@@ -155,6 +171,7 @@ typedef struct {
   const int32_t *rec_nodes;
   const int32_t *group;
   const double *Rm, *Lm, *Cm;
+  const int32_t *meas;
 } emt_net;
 
 /* Simulation settings shared by all scenarios of a context.

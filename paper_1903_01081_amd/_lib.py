@@ -47,6 +47,7 @@ class EmtNet(C.Structure):
         ("ev_in_service", C.c_void_p),
         ("n_rec", C.c_int32), ("rec_nodes", C.c_void_p),
         ("group", C.c_void_p), ("Rm", C.c_void_p), ("Lm", C.c_void_p), ("Cm", C.c_void_p),
+        ("meas", C.c_void_p),
     ]
 
 
@@ -160,6 +161,8 @@ class PackedNets:
             grp = getattr(net, "group", None)
             for f, t in (("group", np.int32), ("Rm", np.float64), ("Lm", np.float64), ("Cm", np.float64)):
                 a[f] = None if grp is None else np.ascontiguousarray(getattr(net, f), t)
+            meas = getattr(net, "meas", None)
+            a["meas"] = None if meas is None else np.ascontiguousarray(meas, np.int32).reshape(-1)
             self.keep.append(a)
             n_rec = int(net.n_nodes) if a["rec"] is None else int(a["rec"].shape[0])
             structs.append(EmtNet(
@@ -167,7 +170,7 @@ class PackedNets:
                 _ptr(a["R"]), _ptr(a["L"]), _ptr(a["C"]), _ptr(a["E"]), _ptr(a["omega"]),
                 _ptr(a["phase"]), _ptr(a["line"]), 3 * int(net.n_lines), _ptr(a["ins"]), n_ev,
                 _ptr(a["ev_step"]), _ptr(a["ev_branch"]), _ptr(a["ev_ins"]), n_rec, _ptr(a["rec"]),
-                _ptr(a["group"]), _ptr(a["Rm"]), _ptr(a["Lm"]), _ptr(a["Cm"])))
+                _ptr(a["group"]), _ptr(a["Rm"]), _ptr(a["Lm"]), _ptr(a["Cm"]), _ptr(a["meas"])))
         self.array = (EmtNet * len(structs))(*structs)
         self.n = len(structs)
 

@@ -41,7 +41,7 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
     if (k < -1 || k >= n.n_nodes || m < -1 || m >= n.n_nodes)
       fail(EMT_EINVAL, where(s, "branch terminal out of range", b));
     if (k == m) fail(EMT_EINVAL, where(s, "branch with both terminals equal (or both ground)", b));
-    if (kd < EMT_RL || kd > EMT_DIODE) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
+    if (kd < EMT_RL || kd > EMT_CSWITCH) fail(EMT_EINVAL, where(s, "unknown branch kind", b));
     const double R = n.R[b], L = n.L[b], C = n.C[b];
     switch (kd) {
       case EMT_RL:
@@ -65,6 +65,26 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
           fail(EMT_EINVAL, where(s, "diodes need the sweep solvers (auto or sparse), refactorised in the loop", b));
         if (n.group && n.group[b] >= 0) fail(EMT_EINVAL, where(s, "a diode cannot belong to a coupled group", b));
         break;
+      case EMT_CSWITCH: {
+        if (!finite(R) || !(R > 0))
+          fail(EMT_EINVAL, where(s, "a controlled switch needs its on-resistance R > 0", b));
+        if (!finite(L) || !(L >= 0))
+          fail(EMT_EINVAL, where(s, "a controlled switch needs its hysteresis half-width L >= 0", b));
+        if (!finite(C)) fail(EMT_EINVAL, where(s, "a controlled switch's reference offset C must be finite", b));
+        if (!n.E || !n.omega || !n.phase || !finite(n.E[b]) || !finite(n.omega[b]) || !finite(n.phase[b]))
+          fail(EMT_EINVAL, where(s, "a controlled switch's reference E, omega, phase must be finite", b));
+        if (!n.meas) fail(EMT_EINVAL, where(s, "controlled switches need meas (their measured nodes)", b));
+        for (int e2 = 0; e2 < 2; ++e2)
+          if (n.meas[2 * b + e2] < -1 || n.meas[2 * b + e2] >= n.n_nodes)
+            fail(EMT_EINVAL, where(s, "a controlled switch's measured node is out of range", b));
+        if (sim.checkpoint_every > 0)
+          fail(EMT_EINVAL, where(s, "controlled switches run forward only (no checkpoints)", b));
+        if (sim.solver == EMT_SOLVER_DENSE)
+          fail(EMT_EINVAL, where(s, "controlled switches need the sweep solvers, refactorised in the loop", b));
+        if (n.group && n.group[b] >= 0)
+          fail(EMT_EINVAL, where(s, "a controlled switch cannot belong to a coupled group", b));
+        break;
+      }
       case EMT_LINE:
         if (k < 0 || m < 0) fail(EMT_EINVAL, where(s, "a line joins two nodes (neither end at ground)", b));
         if (!finite(R) || !(R > 0)) fail(EMT_EINVAL, where(s, "a line needs its surge impedance R > 0", b));
@@ -95,6 +115,8 @@ void validate(const emt_net &n, int s, const emt_sim &sim) {
       fail(EMT_EINVAL, where(s, "distributed-parameter lines take no switching events", j));
     if (n.kind[n.ev_branch[j]] == EMT_DIODE)
       fail(EMT_EINVAL, where(s, "diodes switch by their own state, not by events", j));
+    if (n.kind[n.ev_branch[j]] == EMT_CSWITCH)
+      fail(EMT_EINVAL, where(s, "controlled switches switch by their controller, not by events", j));
   }
   if (n.group) {
     if (!n.Rm || !n.Lm || !n.Cm) fail(EMT_EINVAL, where(s, "coupled groups need Rm, Lm and Cm"));
@@ -483,7 +505,7 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       for (int b = 0; b < B; ++b) ever[b] |= sc.ins[t][b];
     // a diode may conduct at any step, whatever its initial state
     for (int b = 0; b < B; ++b)
-      if (net.kind[b] == EMT_DIODE) ever[b] = 1;
+      if (net.kind[b] == EMT_DIODE || net.kind[b] == EMT_CSWITCH) ever[b] = 1;
     DSU d(N);
     for (int b = 0; b < B; ++b)
       if (ever[b] && net.k[b] >= 0 && net.m[b] >= 0) d.join(net.k[b], net.m[b]);
@@ -709,6 +731,16 @@ Analysis analyze(const emt_net *nets, int n_scen, const emt_sim &sim) {
       }
       sc.items.push_back(item_id);
       A.items.push_back(std::move(it_));
+    }
+    // A controlled switch's controller reads nodes of its own component
+    // (the workgroup that steps it holds their voltages).
+    for (int b = 0; b < B; ++b) {
+      if (net.kind[b] != EMT_CSWITCH) continue;
+      for (int e2 = 0; e2 < 2; ++e2) {
+        const int a = net.meas[2 * b + e2];
+        if (a >= 0 && sc.node_item[a] != sc.br_item[b])
+          fail(EMT_EINVAL, where(s, "a controlled switch measures a node outside its connected component", b));
+      }
     }
     // Recorded nodes -> (item, local node, column).
     for (int r = 0; r < sc.n_rec; ++r) {

@@ -175,7 +175,8 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
       const int kind = net.kind[b];
       bkind.push_back(kind);
       bline.push_back(net.line ? net.line[b] : -1);
-      const bool src = kind == EMT_SRC;
+      // a source's EMF, or a controlled switch's comparator reference
+      const bool src = kind == EMT_SRC || kind == EMT_CSWITCH;
       bE.push_back(src ? net.E[b] : 0.0);
       bw.push_back(src ? net.omega[b] : 0.0);
       bph.push_back(src ? net.phase[b] : 0.0);
@@ -715,7 +716,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   for (const Item &it : A.items) {
     if (!it.line_bk.empty() || !it.grp_b.empty()) c.ks.ext = true;
     for (int b : it.br)
-      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) c.ks.ext = true;
+      if (b >= 0 && (nets[it.scen].kind[b] == EMT_DIODE || nets[it.scen].kind[b] == EMT_CSWITCH)) c.ks.ext = true;
   }
   c.ks.dmax = tail_max(bs);
   // Pad every item's branch list to whole lane slots with inert branches, so
@@ -752,7 +753,8 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   for (int q = 0; q < NI; ++q) {
     const Item &it = A.items[q];
     for (int b : it.br)
-      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) sym_diode[it.sym] = 1;
+      if (b >= 0 && (nets[it.scen].kind[b] == EMT_DIODE || nets[it.scen].kind[b] == EMT_CSWITCH))
+        sym_diode[it.sym] = 1;
   }
   for (size_t q = 0; q < A.syms.size(); ++q) {
     const int n = A.syms[q].n;
@@ -958,7 +960,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.seg = seg_off;
     d.n_diodes = 0;
     for (int b : it.br)
-      if (b >= 0 && nets[it.scen].kind[b] == EMT_DIODE) d.n_diodes++;
+      if (b >= 0 && (nets[it.scen].kind[b] == EMT_DIODE || nets[it.scen].kind[b] == EMT_CSWITCH)) d.n_diodes++;
     d.dyn = dyn_off;
     if (d.n_diodes > 0) dyn_off += (int64_t)it.n_br + S.nnz() + 2 * (int64_t)it.n + plans[it.sym].nsv();
     d.n_groups = (int32_t)(it.grp_b.size() / 3);
@@ -1148,6 +1150,28 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
   if (dyn_off > 0) {
     dc.dyn = c.alloc<double>(dyn_off);
     dc.dstate = c.alloc<int32_t>(c.nbr_total);
+    // controlled switches' measured node pairs, item-local (ground: n)
+    bool any_cs = false;
+    std::vector<int32_t> bmeas(2 * (size_t)c.nbr_total, 0);
+    for (int q = 0; q < NI; ++q) {
+      const Item &it = A.items[q];
+      const Scenario &sc = A.scens[it.scen];
+      const emt_net &net = nets[it.scen];
+      for (int j = 0; j < it.n_br; ++j) {
+        const int b = it.br[j];
+        const int64_t gb = c.items[q].br + j;
+        bmeas[2 * gb] = bmeas[2 * gb + 1] = it.n;
+        if (b < 0 || net.kind[b] != EMT_CSWITCH) continue;
+        any_cs = true;
+        for (int e2 = 0; e2 < 2; ++e2) {
+          const int a = net.meas[2 * b + e2];
+          if (a >= 0 && sc.node_item[a] != q)
+            throw Error{EMT_EDEVICE, "internal: a controlled switch measures a node of another work item"};
+          bmeas[2 * gb + e2] = a >= 0 ? sc.node_local[a] : it.n;
+        }
+      }
+    }
+    if (any_cs) dc.bmeas = c.upload(bmeas);
   }
   if (!group_tab.empty()) {
     // per-branch mutual values and member flags, in the branch arrays' order
@@ -1618,7 +1642,8 @@ emt_status emt_steady_state(emt_ctx *ctx, void *stream) {
     for (const emt::Item &it : ctx->A.items)
       if (!it.line_bk.empty())
         return set_error(EMT_EINVAL, "distributed-parameter lines start from rest (no steady state)");
-    if (ctx->dc.dyn) return set_error(EMT_EINVAL, "diodes switch by their own state (no steady state)");
+    if (ctx->dc.dyn)
+      return set_error(EMT_EINVAL, "diodes and controlled switches switch by their own state (no steady state)");
     for (size_t q = 0; q < ctx->scen_mixed_freq.size(); ++q)
       if (ctx->scen_mixed_freq[q])
         return set_error(EMT_EINVAL, "scenario " + std::to_string(q) +

@@ -269,8 +269,8 @@ __global__ void k_reset(DevCtx c, const int32_t *bitem, const int32_t *blocal, i
     c.ck_i[it.ck + b] = 0.0;
     c.ck_u[it.ck + b] = u;
   }
-  // a diode starts in its initial state
-  if (c.dstate && c.bkind[gb] == KIND_DIODE) c.dstate[gb] = on ? 1 : 0;
+  // a diode or a controlled switch starts in its initial state
+  if (c.dstate && (c.bkind[gb] == KIND_DIODE || c.bkind[gb] == KIND_CSWITCH)) c.dstate[gb] = on ? 1 : 0;
 }
 
 __global__ void k_fill_f64(double *p, int64_t n, double v) {

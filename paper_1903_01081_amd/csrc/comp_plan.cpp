@@ -42,7 +42,8 @@ CompPlan plan_compensation(const Analysis &A, const emt_net *nets, const emt_sim
     const emt_net &net = nets[s];
     for (int b = 0; b < net.n_branches; ++b) {
       if (net.kind[b] == EMT_LINE) fail("distributed-parameter lines are not supported");
-      if (net.kind[b] == EMT_DIODE) fail("diodes are not supported (they refactorise inside the loop)");
+      if (net.kind[b] == EMT_DIODE || net.kind[b] == EMT_CSWITCH)
+        fail("diodes and controlled switches are not supported (they refactorise inside the loop)");
       if (net.group && net.group[b] >= 0) fail("coupled three-phase groups are not supported");
     }
   }

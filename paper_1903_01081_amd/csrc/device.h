@@ -8,7 +8,9 @@
 
 namespace emt {
 
-enum : int { KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4, KIND_LINE = 5, KIND_DIODE = 6 };
+enum : int {
+  KIND_RL = 0, KIND_C = 1, KIND_R = 2, KIND_SWITCH = 3, KIND_SRC = 4, KIND_LINE = 5, KIND_DIODE = 6, KIND_CSWITCH = 7
+};
 
 // Packed branch descriptor for the step kernels: local terminals in 15 bits
 // each (a grounded terminal holds the node count n: the step kernels keep a
@@ -180,10 +182,13 @@ struct DevCtx {
   const double *bRm, *bLm, *bCm;
   const int32_t *bgrp;
   double *cgo, *cbo;
-  // ideal diodes: the dynamic factor slots and the conducting state per
-  // branch (meaningful for diode branches)
+  // ideal diodes and controlled switches: the dynamic factor slots and the
+  // conducting state per branch (meaningful for those branches)
   double *dyn;
   int32_t *dstate;
+  // controlled switches: per item-branch the measured node pair, item-local
+  // (the ground is the item's zero node slot n); null when there is none
+  const int32_t *bmeas;
 };
 
 }  // namespace emt

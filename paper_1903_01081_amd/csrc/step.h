@@ -612,21 +612,34 @@ __device__ __forceinline__ void group_pass(const DevCtx &c, const ItemDesc &it, 
 // state lives in c.dstate and changes after a step (a conducting diode whose
 // current g u went negative blocks, a blocking one whose voltage v_k - v_m
 // went positive conducts), taking effect from the next step. dmask marks a
-// lane's diode slots. Returns the slots that change; their new state is
-// stored at once, their conductance only after the branch update of this
-// step (which still uses the old one).
+// lane's diode and controlled-switch slots, cmask the latter: a controlled
+// switch's hysteresis comparator measures s = v_a - v_b of step n against
+// its reference r = E cos(omega n dt + phase) + C and, with e = r - s,
+// conducts from the next step if e > h, opens if e < -h, else keeps its
+// state (h in the branch's L). Returns the slots that change; their new
+// state is stored at once, their conductance only after the branch update
+// of this step (which still uses the old one).
 template <int BS, int BPT, bool SM>
 __device__ __forceinline__ uint32_t diode_flips(const DevCtx &c, const ItemDesc &it, const View<SM> &v,
-                                                const Lane<BPT> &L, uint32_t dmask) {
+                                                const Lane<BPT> &L, uint32_t dmask, uint32_t cmask, int64_t n) {
   uint32_t fl = 0;
   const int tid = lane_id();
 #pragma unroll
   for (int j = 0; j < BPT; ++j) {
     if (!((dmask >> j) & 1u)) continue;
-    const uint32_t pk = L.pk[j];
-    const double du = v.x[pk & kTermGround] - v.x[(pk >> 15) & kTermGround];
     const bool on = L.g[j] != 0.0;
-    const bool next = on ? !(L.g[j] * du < 0.0) : (du > 0.0);
+    bool next;
+    if ((cmask >> j) & 1u) {
+      const int64_t gb = it.br + tid + j * BS;
+      const double s = v.x[c.bmeas[2 * gb]] - v.x[c.bmeas[2 * gb + 1]];
+      const double r = c.bE[gb] * emf_cos(c.bw[gb] * ((double)n * c.dt) + c.bph[gb]) + c.bC[gb];
+      const double e = r - s, h = c.bL[gb];
+      next = e > h ? true : (e < -h ? false : on);
+    } else {
+      const uint32_t pk = L.pk[j];
+      const double du = v.x[pk & kTermGround] - v.x[(pk >> 15) & kTermGround];
+      next = on ? !(L.g[j] * du < 0.0) : (du > 0.0);
+    }
     if (next != on) {
       fl |= 1u << j;
       c.dstate[it.br + tid + j * BS] = next ? 1 : 0;
@@ -790,12 +803,15 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
   double w[WPT];
   load_lane<BS, BPT>(c, it, L);
   load_coefs<BS, BPT>(c, it, t, L.g, L.be);
-  const bool diodes = EXT && it.n_diodes > 0;
-  uint32_t dmask = 0;
+  const bool diodes = EXT && it.n_diodes > 0;  // diodes or controlled switches
+  uint32_t dmask = 0, cmask = 0;
   if (diodes) {
 #pragma unroll
-    for (int j = 0; j < BPT; ++j)
-      if (c.bkind[it.br + threadIdx.x + j * BS] == KIND_DIODE) dmask |= 1u << j;
+    for (int j = 0; j < BPT; ++j) {
+      const int kd = c.bkind[it.br + threadIdx.x + j * BS];
+      if (kd == KIND_DIODE || kd == KIND_CSWITCH) dmask |= 1u << j;
+      if (kd == KIND_CSWITCH) cmask |= 1u << j;
+    }
     diode_conductances<BS, BPT>(c, it, L, dmask);
   }
   history_from_state<BS, BPT, SM>(c.si + it.br, c.su + it.br, L, v);
@@ -825,7 +841,7 @@ __global__ __launch_bounds__(BS) void k_forward(DevCtx c, const int32_t *order, 
       for (int q = lane_id(); q < v.nrec; q += BS) row[v.rcolumn[q]] = v.x[v.rnode[q]];
     }
     const bool sw = (n + 1 == next);
-    const uint32_t fl = diodes ? diode_flips<BS, BPT, SM>(c, it, v, L, dmask) : 0u;
+    const uint32_t fl = diodes ? diode_flips<BS, BPT, SM>(c, it, v, L, dmask, cmask, n) : 0u;
     double *ck_i = nullptr, *ck_u = nullptr, *st_i = nullptr, *st_u = nullptr;
     if (c.K > 0 && n % c.K == 0) {
       const int64_t o = it.ck + (n / c.K) * (int64_t)v.nbr;

@@ -39,8 +39,10 @@ import numpy as np
 # distributed-parameter (travelling-wave) line: R = surge impedance Z,
 # L = travel time tau. DIODE is an ideal diode (state-dependent switch):
 # R = on-resistance, conducting from k to m while its current is positive,
-# blocking while its voltage v_k - v_m is not.
-RL, CAP, RES, SWITCH, SRC, LINE, DIODE = 0, 1, 2, 3, 4, 5, 6
+# blocking while its voltage v_k - v_m is not. CSWITCH is a switch set by a
+# hysteresis comparator: R = on-resistance, reference E cos(omega t + phase)
+# + C, half-width L, measuring the voltage between the node pair meas.
+RL, CAP, RES, SWITCH, SRC, LINE, DIODE, CSWITCH = 0, 1, 2, 3, 4, 5, 6, 7
 
 F_HZ = 60.0
 R_SRC = 0.5          # Thevenin source resistance per phase [ohm]
@@ -90,6 +92,9 @@ class Network:
     Rm: Optional[np.ndarray] = None
     Lm: Optional[np.ndarray] = None
     Cm: Optional[np.ndarray] = None
+    # controlled switches: meas[b] = (a, b) the node pair whose voltage the
+    # switch's controller measures; None when the network has none
+    meas: Optional[np.ndarray] = None
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -125,17 +130,21 @@ class _Builder:
     def __init__(self, n_nodes: int):
         self.n_nodes = n_nodes
         self.cols = {c: [] for c in ("k", "m", "kind", "R", "L", "C", "E",
-                                     "omega", "phase", "line", "ins", "group", "Rm", "Lm", "Cm")}
+                                     "omega", "phase", "line", "ins", "group", "Rm", "Lm", "Cm", "meas")}
         self.n_groups = 0
+        self.n_cswitch = 0
 
     def add(self, k, m, kind, R=0.0, L=0.0, C=0.0, E=0.0, omega=0.0,
-            phase=0.0, line=-1, ins=1, group=-1, Rm=0.0, Lm=0.0, Cm=0.0) -> int:
+            phase=0.0, line=-1, ins=1, group=-1, Rm=0.0, Lm=0.0, Cm=0.0, meas=(-1, -1)) -> int:
         c = self.cols
         c["k"].append(k); c["m"].append(m); c["kind"].append(kind)
         c["R"].append(R); c["L"].append(L); c["C"].append(C)
         c["E"].append(E); c["omega"].append(omega); c["phase"].append(phase)
         c["line"].append(line); c["ins"].append(ins)
         c["group"].append(group); c["Rm"].append(Rm); c["Lm"].append(Lm); c["Cm"].append(Cm)
+        c["meas"].append(tuple(meas))
+        if kind == CSWITCH:
+            self.n_cswitch += 1
         return len(c["k"]) - 1
 
     def new_group(self) -> int:
@@ -160,6 +169,7 @@ class _Builder:
             ev_in_service=np.asarray([e[2] for e in ev], np.uint8),
             rec_nodes=None if rec_nodes is None else np.asarray(rec_nodes, np.int32),
             n_lines=n_lines, meta=meta,
+            meas=None if self.n_cswitch == 0 else np.asarray(c["meas"], np.int32).reshape(-1, 2),
             **({} if self.n_groups == 0 else dict(
                 group=np.asarray(c["group"], np.int32), Rm=np.asarray(c["Rm"], np.float64),
                 Lm=np.asarray(c["Lm"], np.float64), Cm=np.asarray(c["Cm"], np.float64))))
