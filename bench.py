@@ -344,6 +344,7 @@ def extras(torch, args):
     out.update(extras_lines(torch, with_cpu=not args.no_cpu))
     out.update(extras_coupled(torch, with_cpu=not args.no_cpu))
     out.update(extras_rectifiers(torch, with_cpu=not args.no_cpu))
+    out.update(extras_choppers(torch, with_cpu=not args.no_cpu))
     return out
 
 
@@ -388,6 +389,49 @@ def extras_rectifiers(torch, with_cpu=True):
                       f"same grid (a dense refactorisation at every diode change); median of 3 runs "
                       f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
     return {"diode_rectifiers": out}
+
+
+CHOPPER_WORKLOAD = ("grid200-chop20: a 200-bus grid whose first 20 loads also feed controlled choppers (20 "
+                    "switches each set by a hysteresis comparator of its DC voltage, refactorised inside the loop), "
+                    "620 nodes, 15000 steps at 20 us, three-phase fault at step 7500, all nodes recorded")
+
+
+def extras_choppers(torch, with_cpu=True):
+    """The 200-bus grid with controlled-chopper loads: forward node-steps/s in
+    its tuned launch shape (every switch change refactorises its component
+    inside the loop), the changes per step, latency, and the oracle's rate."""
+    from paper_1903_01081_amd import netgen
+    from paper_1903_01081_amd.sim import Simulator
+    from paper_1903_01081_amd.tune import tune
+    log("extras: controlled choppers")
+    nets, cfg = netgen.config1(n_bus=200, n_steps=15000, choppers=20)
+    net = nets[0]
+    N, T = net.n_nodes, cfg["n_steps"]
+    shape = tune(nets, cfg["dt"], T, probe_steps=400)["shape"]
+    sim = Simulator(nets, cfg["dt"], T, **shape)
+    info = sim.info()
+    rec = torch.empty((1, sim.n_steps, sim.R), dtype=torch.float64, device=sim.device)
+    runs = [time_simulation(torch, sim, rec, 1, 1 if k == 0 else 0) for k in range(3)]
+    wall, kern = sorted(runs)[1]
+    roof = roofline_object(info, net.n_rec, T, "k_forward", kern)
+    lat = latency_object(sim, "k_forward", kern / T * 1e6, info)
+    sim.close()
+    del rec
+    out = {"workload": CHOPPER_WORKLOAD, "value": N * T / wall, "unit": "node-steps/s", "seconds": wall,
+           "kernel_s": kern, "launch_shape": shape, "controlled_switches": int(np.sum(net.kind == netgen.CSWITCH)),
+           "roofline": roof, "latency": lat,
+           "note": "roofline bytes exclude the factorisations inside the loop (their count depends on the run)"}
+    if with_cpu:
+        from oracle import oracle as O
+        O.use_native_build()
+        k = 3000
+        med, ts = median_time(lambda: O.run(net, cfg["dt"], k))
+        out["cpu_baseline"] = {
+            "value": N * k / med, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (g++ -O3 -march=native, 1 thread) on the first {k} of the 15,000 steps of the "
+                      f"same grid (a dense refactorisation at every switch change); median of 3 runs "
+                      f"({', '.join(f'{t:.2f}' for t in ts)} s)"}
+    return {"controlled_choppers": out}
 
 
 COUPLED_WORKLOAD = ("grid200-coupled: a 200-bus grid with coupled three-phase lines (300 series R-L and 600 "
@@ -731,8 +775,8 @@ def main():
                     help="only the adjoint kernels in fixed launch shapes, two runs each (for rocprofv3): "
                          "the one-workgroup adjoint (grid100 and the uneven batch) or the pipelined one (grid100)")
     ap.add_argument("--only-lines", action="store_true",
-                    help="run only the grids with travelling-wave lines, coupled three-phase lines and "
-                         "diode-bridge loads (one line)")
+                    help="run only the grids with travelling-wave lines, coupled three-phase lines, "
+                         "diode-bridge loads and controlled-chopper loads (one line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     ap.add_argument("--solver", choices=["tuned", "auto", "dense", "sparse"], default="tuned",
@@ -760,6 +804,7 @@ def main():
             out = extras_lines(torch, with_cpu=not args.no_cpu)
             out.update(extras_coupled(torch, with_cpu=not args.no_cpu))
             out.update(extras_rectifiers(torch, with_cpu=not args.no_cpu))
+            out.update(extras_choppers(torch, with_cpu=not args.no_cpu))
             print(json.dumps(out), flush=True)
         elif args.only_adjoint:
             print(json.dumps(extras_adjoint(torch)), flush=True)

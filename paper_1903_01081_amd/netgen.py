@@ -50,6 +50,7 @@ L_SRC = 10e-3        # Thevenin source inductance per phase [H]
 R_FAULT = 1e-3       # closed fault switch resistance [ohm]
 # diode-bridge loads: diode on-resistance, DC capacitor, DC-side reference
 R_DIODE_ON, C_DC, R_DC_REF = 1e-2, 100e-6, 1e6
+CHOP_V_REF, CHOP_H, CHOP_C, CHOP_R = 0.08, 0.01, 200e-6, 40.0
 # coupled three-phase lines: mutual / self ratios of the circulant series R,
 # L and (negative) shunt C matrices
 COUPLING_R, COUPLING_L, COUPLING_C = 0.25, 0.4, 0.2
@@ -207,7 +208,7 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
                      n_gen: int, n_load: int, *, fault_bus: Optional[int] = None,
                      fault_step: int = 0, rec_nodes=None, with_fault_switch=True,
                      travelling_wave_dt: Optional[float] = None, coupled: bool = False,
-                     rectifiers: int = 0):
+                     rectifiers: int = 0, choppers: int = 0):
     """Draw one grid. Returns (builder, bookkeeping) so callers can add events.
 
     Branch order: for each line its 3 series R-L branches, then the 3 shunt
@@ -219,6 +220,12 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
     resistor of twice the load's R in parallel with 100 uF, referenced to
     ground through 1 MOhm at its negative node; each bridge adds two DC
     nodes after the 3 n_bus AC nodes. No extra random draws.
+
+    choppers: the first this many loads also feed, from their phase a, a
+    controlled switch (10 mOhm on, starting on) into a DC node with 200 uF
+    and 40 ohm to ground, its hysteresis comparator holding the DC voltage
+    at 0.08 +- 0.01 (CHOP_V_REF, CHOP_H); one DC node each after the bridges'.
+    No extra random draws.
 
     coupled: every line's three phases are coupled: its series R-L
     branches form one group with mutual Rm = 0.25 R, Lm = 0.4 L, and the
@@ -235,7 +242,7 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
     pi-sections; it is then not part of the parameter vector.
     """
     edges = random_lines(rng, n_bus, n_lines)
-    n_nodes = 3 * n_bus + 2 * rectifiers
+    n_nodes = 3 * n_bus + 2 * rectifiers + choppers
     bld = _Builder(n_nodes)
     series = np.zeros((n_lines, 3), np.int32)
     for l, (a, b) in enumerate(edges):
@@ -287,6 +294,11 @@ def three_phase_grid(rng: np.random.Generator, n_bus: int, n_lines: int,
             bld.add(P, N, RES, R=2.0 * R)
             bld.add(P, N, CAP, C=C_DC)
             bld.add(N, -1, RES, R=R_DC_REF)
+        if q < choppers:
+            d = 3 * n_bus + 2 * rectifiers + q
+            bld.add(3 * int(ld), d, CSWITCH, R=R_DIODE_ON, C=CHOP_V_REF, L=CHOP_H, meas=(d, -1), ins=1)
+            bld.add(d, -1, CAP, C=CHOP_C)
+            bld.add(d, -1, RES, R=CHOP_R)
     fault_sw = []
     if with_fault_switch:
         if fault_bus is None:
@@ -324,14 +336,15 @@ def config0(seed: int = 0, n_steps: int = 4000):
 
 def config1(seed: int = 1, n_bus: int = 1000, n_steps: int = 50000,
             fault_step: Optional[int] = None, travelling_wave: bool = False,
-            coupled: bool = False, rectifiers: int = 0):
+            coupled: bool = False, rectifiers: int = 0, choppers: int = 0):
     """1000-bus grid (3000 nodes), 1500 lines, 200 sources, 600 loads,
     dt = 20 us, 1 s, one fault at mid-horizon, all nodes recorded.
     travelling_wave: the same draw with every line whose travel time is at
     least one step entered as distributed-parameter lines (see
     three_phase_grid). coupled: the same draw with coupled three-phase
     lines (one component of 3 n_bus nodes). rectifiers: the same draw with
-    that many loads also feeding diode bridges."""
+    that many loads also feeding diode bridges; choppers: with that many
+    loads also feeding controlled choppers."""
     rng = np.random.default_rng(seed)
     dt = 20e-6
     n_lines = int(round(1.5 * n_bus))
@@ -339,9 +352,9 @@ def config1(seed: int = 1, n_bus: int = 1000, n_steps: int = 50000,
     bld, info = three_phase_grid(rng, n_bus, n_lines, int(round(0.2 * n_bus)),
                                  int(round(0.6 * n_bus)),
                                  travelling_wave_dt=dt if travelling_wave else None, coupled=coupled,
-                                 rectifiers=rectifiers)
+                                 rectifiers=rectifiers, choppers=choppers)
     name = (f"grid{n_bus}" + ("-tw" if travelling_wave else "") + ("-coupled" if coupled else "")
-            + (f"-rect{rectifiers}" if rectifiers else ""))
+            + (f"-rect{rectifiers}" if rectifiers else "") + (f"-chop{choppers}" if choppers else ""))
     net = bld.network(_fault_events(info, ev), None, n_lines, dict(info, name=name))
     return [net], dict(dt=dt, n_steps=n_steps)
 

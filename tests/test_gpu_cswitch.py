@@ -183,3 +183,34 @@ def test_cswitch_refusals(torch_cuda):
         dict(k=2, m=3, kind=RES, R=1.0), dict(k=3, m=-1, kind=RES, R=1.0)])
     with pytest.raises(EMTError, match="outside its connected component"):
         Simulator([other], 20e-6, 50)
+
+
+def test_grid200_choppers_full_size(torch_cuda, oracle_mod):
+    """The benchmarked grid with controlled-chopper loads (200 buses, 20
+    controlled switches, 620 nodes, 15,000 steps) in the launch bench.py
+    times: the first 3000 steps element by element (every comparator
+    decision there clears its threshold by more than 1e-10 of the
+    quantities involved), and at the last step KCL at every node."""
+    from paper_1903_01081_amd.sim import Simulator
+    nets, cfg = netgen.config1(n_bus=200, n_steps=15000, choppers=20)
+    net, dt, T = nets[0], cfg["dt"], cfg["n_steps"]
+    say("grid200 with 20 controlled choppers, 15000 steps")
+    sim = Simulator(nets, dt, T)
+    sim.factor()
+    rec = sim.step(T).cpu().numpy()[0]
+    sim.sync()
+    T0 = 3000
+    assert decision_margin(oracle_mod, net, dt, T0) > 1e-10
+    err = rel(rec[:T0], oracle_mod.run(net, dt, T0))
+    say("prefix rel err", err)
+    assert err < TOL
+    v, i = sim.get_state(0)
+    inj = np.zeros(net.n_nodes)
+    mag = np.zeros(net.n_nodes)
+    for arr, sgn in ((net.k, 1.0), (net.m, -1.0)):
+        ok = arr >= 0
+        np.add.at(inj, arr[ok], sgn * i[ok])
+        np.add.at(mag, arr[ok], np.abs(i[ok]))
+    assert np.max(np.abs(inj)) <= 1e-9 * np.max(mag)
+    assert np.allclose(rec[-1], v, rtol=0, atol=0)
+    sim.close()
