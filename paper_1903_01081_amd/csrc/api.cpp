@@ -212,10 +212,9 @@ static void fill_branch_params(emt_ctx &c, const emt_net *nets, std::vector<int3
   c.scen_br_off.push_back((int64_t)br_ids.size());
 }
 
-static emt::LdsShape shape_of(const emt::Item &it, const emt::Symbolic &S, const emt::SweepPlan &P) {
-  (void)S;
+static emt::LdsShape shape_of(const emt::Item &it, const emt::Symbolic &S, const emt::SweepPlan &P, bool dyn) {
   return emt::LdsShape{it.n, P.d, P.ns, it.n_br, it.n_src, P.nsv(), (int)P.fdesc.size(), (int)P.bdesc.size(),
-                       it.nptr[it.n], (int)it.rec_node.size()};
+                       it.nptr[it.n], (int)it.rec_node.size(), S.levels_f(), dyn};
 }
 
 // log2 of the lanes that share one row in a sweep pass: enough lanes that
@@ -749,12 +748,12 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     if (c.is_split[q]) sym_split[A.items[q].sym] = 1;
   // items with diodes refactorise inside the time loop: sweeps only (the
   // dense tail's inverse would have to be recomputed there too)
-  std::vector<char> sym_diode(A.syms.size(), 0);
+  std::vector<char> sym_diode(A.syms.size(), 0), item_diode(NI, 0);
   for (int q = 0; q < NI; ++q) {
     const Item &it = A.items[q];
     for (int b : it.br)
       if (b >= 0 && (nets[it.scen].kind[b] == EMT_DIODE || nets[it.scen].kind[b] == EMT_CSWITCH))
-        sym_diode[it.sym] = 1;
+        sym_diode[it.sym] = item_diode[q] = 1;
   }
   for (size_t q = 0; q < A.syms.size(); ++q) {
     const int n = A.syms[q].n;
@@ -774,7 +773,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     plans[q] = plan_sweeps(A.syms[q], d);
   }
   auto item_lds = [&](const Item &it, bool adj) {
-    return lds_bytes(shape_of(it, A.syms[it.sym], plans[it.sym]), true, adj);
+    return lds_bytes(shape_of(it, A.syms[it.sym], plans[it.sym], item_diode[&it - &A.items[0]]), true, adj);
   };
   if (solver == EMT_SOLVER_AUTO) {
     for (const Item &it : A.items) {
@@ -791,7 +790,7 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     wpt = 1;
     for (const Item &it : A.items) {
       if (c.is_split[&it - &A.items[0]]) continue;
-      const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym]);
+      const LdsShape sh = shape_of(it, A.syms[it.sym], plans[it.sym], item_diode[&it - &A.items[0]]);
       f_sm = std::max(f_sm, lds_bytes(sh, true, false));
       a_sm = std::max(a_sm, lds_bytes(sh, true, true));
       f_gl = std::max(f_gl, lds_bytes(sh, false, false));
@@ -902,6 +901,35 @@ static void upload_all(emt_ctx &c, const emt_net *nets) {
     d.fcol = puth(P.fcol);
     d.brow = puth(P.brow);
     d.bpos = puth(P.bpos);
+    d.rent = d.rpair = -1;
+    if (sym_diode[q]) {
+      // update pairs of the factorisation inside the loop, level entry by
+      // level entry, columns ascending (the order of a merge of the rows)
+      std::vector<int> rent, rpair;
+      for (size_t p = 0; p < S.fent.size(); ++p) {
+        const int e = S.fent[p], i = S.lcol_row[e], pos = S.lcol_pos[e], j = S.lrow_col[pos];
+        rent.push_back(pos);
+        rent.push_back((int)rpair.size());
+        int qi = S.lrow_ptr[i], qj = S.lrow_ptr[j];
+        while (qi < S.lrow_ptr[i + 1] && qj < S.lrow_ptr[j + 1]) {
+          const int ci = S.lrow_col[qi], cj = S.lrow_col[qj];
+          if (ci >= j) break;
+          if (ci == cj) {
+            rpair.push_back((int)((uint32_t)qi | ((uint32_t)qj << 16)));
+            ++qi;
+            ++qj;
+          } else if (ci < cj) {
+            ++qi;
+          } else {
+            ++qj;
+          }
+        }
+      }
+      rent.push_back(0);
+      rent.push_back((int)rpair.size());
+      d.rent = put(rent);
+      d.rpair = put(rpair);
+    }
     d.fdesc = (int64_t)symd.size();
     symd.insert(symd.end(), P.fdesc.begin(), P.fdesc.end());
     d.bdesc = (int64_t)symd.size();

@@ -376,6 +376,9 @@ size_t lds_bytes(const LdsShape &s, bool sm, bool adjoint) {
   if (sm) {
     b += arr(s.nsv, 8) + arr(s.ns, 8) + arr(s.nfdesc, 8) + arr(s.nbdesc, 8) + arr(s.n + 1, 4) +
          arr(adjoint ? s.n + 1 : 0, 4) + 3 * arr(s.nsv, 2) + arr(s.nent, 2) + 2 * arr(s.nrec, 2);
+    // the factorisation's own structure for the refactorisations inside the
+    // loop: row pointers, level pointers (rows, entries) and level rows
+    if (s.dyn) b += arr(s.n + 1, 4) + 2 * arr(s.nlev + 1, 4) + arr(s.n, 2);
   }
   return b;
 }

@@ -41,6 +41,11 @@ struct SymDesc {
   int64_t fcol, brow, bpos;
   // uint64 (symd): row descriptors (row | first << 16 | count << 32)
   int64_t fdesc, bdesc;
+  // int32 (symi), symbolics refactorised inside the time loop (else -1):
+  // per level entry (in fent order) its CSR position and the start of its
+  // update pairs, nnz+1 of them; the pairs (qi | qj << 16), the CSR
+  // positions of L_ik and L_jk for every column k < j common to rows i and j
+  int64_t rent, rpair;
 };
 
 struct ItemDesc {

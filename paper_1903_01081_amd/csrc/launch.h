@@ -15,6 +15,8 @@ namespace emt {
 // Sizes that decide an item's LDS footprint in the step kernels.
 struct LdsShape {
   int n, d, ns, nbr, nsrc, nsv, nfdesc, nbdesc, nent, nrec;
+  int nlev = 0;      // factor levels
+  bool dyn = false;  // refactorised inside the loop (diodes, controlled switches)
 };
 
 // Launch shape of the step kernels, chosen once per context.

@@ -115,6 +115,10 @@ struct View {
   Lds<double> x, J, cD, dv, sv_s, dinv_s;  // x has n+1 entries, x[n] = 0
   Lds<int32_t> flag;                       // adjoint: a word for broadcasts
   Ref<double, SM> sv, dinv;
+  // SM, items refactorised inside the loop: the factorisation's row
+  // pointers, level pointers (rows, entries) and level rows
+  Lds<int32_t> rf_rowptr, rf_flev, rf_fent_ptr;
+  Lds<uint16_t> rf_rows;
 };
 
 // Tail rows are split into tpr lanes of contiguous columns: tpr = the
@@ -131,9 +135,18 @@ __device__ __forceinline__ void copy_to(uint32_t off, const T *src, int cnt) {
   for (int q = threadIdx.x; q < cnt; q += BS) dst[q] = src[q];
 }
 
+// Copy of int32 values below 65536 into uint16 LDS.
+template <int BS>
+__device__ __forceinline__ void copy_to_u16(uint32_t off, const int32_t *src, int cnt) {
+  uint16_t *dst = reinterpret_cast<uint16_t *>(emt_lds + off);
+  for (int q = threadIdx.x; q < cnt; q += BS) dst[q] = (uint16_t)src[q];
+}
+
 // LDS layout (byte offsets from emt_lds, each array 16-byte aligned):
 // cD, x, J, [dv], then under SM sv, dinv, fdesc, bdesc, nptr, [rptr],
-// fcol, brow, bpos, nent, rnode, rcolumn. Must match lds_bytes() on the host.
+// fcol, brow, bpos, nent, rnode, rcolumn, and for an item with diodes or
+// controlled switches rf_rowptr, rf_flev, rf_fent_ptr, rf_rows.
+// Must match lds_bytes() on the host.
 template <int BS, bool SM>
 __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint) {
   const SymDesc sd = c.syms[it.sym];
@@ -195,6 +208,16 @@ __device__ View<SM> make_view(const DevCtx &c, const ItemDesc &it, bool adjoint)
     copy_to<BS>(v.nent.off, g_nent, nent_cnt);
     copy_to<BS>(v.rnode.off, g_rnode, v.nrec);
     copy_to<BS>(v.rcolumn.off, g_rcolumn, v.nrec);
+    if (it.n_diodes > 0) {
+      v.rf_rowptr.off = take(v.n + 1, 4);
+      v.rf_flev.off = take(sd.nlev + 1, 4);
+      v.rf_fent_ptr.off = take(sd.nlev + 1, 4);
+      v.rf_rows.off = take(v.n, 2);
+      copy_to<BS>(v.rf_rowptr.off, c.symi + sd.rowptr, v.n + 1);
+      copy_to<BS>(v.rf_flev.off, c.symi + sd.flevptr, sd.nlev + 1);
+      copy_to<BS>(v.rf_fent_ptr.off, c.symi + sd.fentptr, sd.nlev + 1);
+      copy_to_u16<BS>(v.rf_rows.off, c.symi + sd.flevrows, v.n);
+    }
     v.sv.off = v.sv_s.off;
     v.dinv.off = v.dinv_s.off;
   } else {
@@ -671,6 +694,127 @@ __device__ __forceinline__ void wg_sync() {
     __syncthreads();
 }
 
+// log2 of the lanes that share one row or entry of a factorisation level
+// with cnt of them: as many as fill the workgroup, at most 16 (one DPP row).
+template <int BS>
+__device__ __forceinline__ int team_log2(int cnt) {
+  int lg = 0;
+  while (lg < 4 && (cnt << (lg + 1)) <= BS) ++lg;
+  return lg;
+}
+
+// A lane's first entry of a factorisation level: its CSR position and the
+// range of its share of the entry's update pairs (start already offset by
+// the lane's index in its team), fetched one level ahead, and its first
+// PC pairs, fetched at the start of the level, so that neither global
+// load waits inside the level. Pairs are read PC at a time.
+template <int PC>
+struct LevelEntry {
+  int p, pos, r, r1, lg;
+  uint32_t pr[PC];
+};
+
+template <int BS, int PC, class LV>
+__device__ __forceinline__ LevelEntry<PC> first_entry(const LV &fent_ptr, int l, const int32_t *rent) {
+  const int e0 = fent_ptr[l], e1 = fent_ptr[l + 1];
+  LevelEntry<PC> f;
+  f.lg = team_log2<BS>(e1 - e0);
+  f.p = e0 + ((int)threadIdx.x >> f.lg);
+  f.pos = 0;
+  f.r = f.r1 = 0;
+  if (f.p < e1) {
+    f.pos = rent[2 * f.p];
+    f.r = rent[2 * f.p + 1] + ((int)threadIdx.x & ((1 << f.lg) - 1));
+    f.r1 = rent[2 * f.p + 3];
+  }
+  return f;
+}
+
+template <int PC>
+__device__ __forceinline__ void load_pairs(uint32_t (&pr)[PC], const uint32_t *rpair, int r, int r1, int g) {
+#pragma unroll
+  for (int u = 0; u < PC; ++u) pr[u] = (r + u * g < r1) ? rpair[r + u * g] : 0u;
+}
+
+// LDL^T of the assembled G (D and Lr hold its diagonal and strictly lower
+// entries on entry) by the factorisation's levels; the columns of one
+// elimination-tree level depend only on lower levels:
+//   D_j  = G_jj - sum_{k<j} L_jk^2 D_k
+//   L_ij = (G_ij - sum_{k<j} L_ik D_k L_jk) / D_j
+// Each row (first phase) and each entry (second phase) of a level is shared
+// by a team of 2^lg adjacent lanes, lg from the level's width: the top of
+// the elimination tree is a chain of one-row levels with long rows, which
+// one lane per row would walk serially. An entry's terms come from its list
+// of update pairs (the CSR positions of L_ik and L_jk for every common
+// column k, precomputed on the host), so no lane searches the two rows; the
+// team's partial sums meet in a fixed DPP scan. The structure comes through
+// accessors (LDS copies or global arrays): row pointers and columns of L by
+// rows, per level its rows and the range of its entries. Non-positive
+// pivots are counted in *bad.
+template <int BS, bool SM, int PC, class RP, class LV, class RW, class RC>
+__device__ __forceinline__ void ldl_levels(int nlev, const RP &rowptr, const LV &flev, const RW &rows,
+                                           const LV &fent_ptr, const RC &rowcol, const int32_t *rent,
+                                           const uint32_t *rpair, double *Lr, double *D, int32_t *bad) {
+  const int tid = (int)threadIdx.x;
+  LevelEntry<PC> next = first_entry<BS, PC>(fent_ptr, 0, rent);
+  for (int l = 0; l < nlev; ++l) {
+    LevelEntry<PC> cur = next;
+    load_pairs(cur.pr, rpair, cur.r, cur.r1, 1 << cur.lg);
+    if (l + 1 < nlev) next = first_entry<BS, PC>(fent_ptr, l + 1, rent);
+    {
+      const int p0 = flev[l], p1 = flev[l + 1];
+      const int lg = team_log2<BS>(p1 - p0), g = 1 << lg, sub = tid & (g - 1);
+      for (int p = p0 + (tid >> lg); p < p1; p += BS >> lg) {
+        const int j = rows[p];
+        const int q1 = rowptr[j + 1];
+        double acc = 0.0;
+        for (int q = rowptr[j] + sub; q < q1; q += g) {
+          const double ljk = Lr[q];
+          acc = acc + ljk * ljk * D[rowcol[q]];
+        }
+        acc = group_sum(acc, lg, sub);
+        if (sub == g - 1) {
+          const double d = D[j] - acc;
+          D[j] = d;
+          if (!(d > 0.0) || !isfinite(d)) atomicAdd(bad, 1);
+        }
+      }
+    }
+    wg_sync<SM>();
+    {
+      const int p1 = fent_ptr[l + 1];
+      const int lg = team_log2<BS>(p1 - fent_ptr[l]), g = 1 << lg, sub = tid & (g - 1);
+      for (int p = cur.p; p < p1; p += BS >> lg) {
+        int pos = cur.pos, r = cur.r, r1 = cur.r1;
+        uint32_t pr[PC];
+#pragma unroll
+        for (int u = 0; u < PC; ++u) pr[u] = cur.pr[u];
+        if (p != cur.p) {
+          pos = rent[2 * p];
+          r = rent[2 * p + 1] + sub;
+          r1 = rent[2 * p + 3];
+          load_pairs(pr, rpair, r, r1, g);
+        }
+        double acc = 0.0;
+        while (r < r1) {
+#pragma unroll
+          for (int u = 0; u < PC; ++u) {
+            if (r + u * g < r1) {
+              const int qi = (int)(pr[u] & 0xFFFFu), qj = (int)(pr[u] >> 16);
+              acc = acc + Lr[qi] * D[rowcol[qj]] * Lr[qj];
+            }
+          }
+          r += PC * g;
+          if (r < r1) load_pairs(pr, rpair, r, r1, g);
+        }
+        acc = group_sum(acc, lg, sub);
+        if (sub == g - 1) Lr[pos] = (Lr[pos] - acc) / D[rowcol[pos]];
+      }
+    }
+    wg_sync<SM>();
+  }
+}
+
 // The factor of an item with diodes for its current conductances (the
 // lanes' L.g), computed inside the time loop into the item's dynamic slot:
 // G on the item's symbolic pattern (with any coupled groups' mutual
@@ -686,8 +830,9 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
   // Under SM the factorisation runs in LDS: without a dense tail the sweep
   // values are exactly L's nonzeros in row order (sv index = CSR position),
   // so L is built in place in the staged sweep values and D in the staged
-  // 1/D, which is inverted at the end. Otherwise in the dynamic slot in
-  // global memory.
+  // 1/D, which is inverted at the end; the structure is read from LDS too
+  // (the sweeps' column, row and position arrays are then L's by rows and
+  // by columns). Otherwise in the dynamic slot in global memory.
   double *Lr, *D;
   if constexpr (SM) {
     Lr = reinterpret_cast<double *>(emt_lds + v.sv_s.off);
@@ -698,23 +843,26 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
   }
   double *sv = gcur + it.n_br + sd.nnz + n;
   double *di = sv + sd.nsv;
-  const int32_t *rowptr = c.symi + sd.rowptr, *rowcol = c.symi + sd.rowcol;
-  const int32_t *colrow = c.symi + sd.colrow, *colpos = c.symi + sd.colpos;
-  const int32_t *flevptr = c.symi + sd.flevptr, *flevrows = c.symi + sd.flevrows;
-  const int32_t *fentptr = c.symi + sd.fentptr, *fent = c.symi + sd.fent;
-  const int32_t *svmap = c.symi + sd.svmap;
-  const int32_t *nptr = c.nptr + it.nptr;
-  const uint16_t *nent = c.nent + it.nent;
+  const int32_t *g_rowptr = c.symi + sd.rowptr;
   const int32_t *bk = c.bk + it.br, *bm = c.bm + it.br, *gpos = c.bgpos + it.br;
   const int tid = lane_id();
 #pragma unroll
   for (int j = 0; j < BPT; ++j) gcur[tid + j * BS] = L.g[j];
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += BS) {
-    for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) Lr[q] = 0.0;
+    int q0, q1;
+    if constexpr (SM) {
+      q0 = v.rf_rowptr[r];
+      q1 = v.rf_rowptr[r + 1];
+    } else {
+      q0 = g_rowptr[r];
+      q1 = g_rowptr[r + 1];
+    }
+    for (int q = q0; q < q1; ++q) Lr[q] = 0.0;
     double d = 0.0;
-    for (int e = nptr[r]; e < nptr[r + 1]; ++e) {
-      const int ent = nent[e];
+    const int e1 = v.nptr[r + 1];
+    for (int e = v.nptr[r]; e < e1; ++e) {
+      const int ent = v.nent[e];
       const int b = ent >> 1;
       const double gv = gcur[b];
       d = d + gv;
@@ -734,50 +882,22 @@ __device__ void refactor_dynamic(const DevCtx &c, const ItemDesc &it, View<SM> &
     }
   }
   wg_sync<SM>();
-  for (int l = 0; l < sd.nlev; ++l) {
-    for (int p = flevptr[l] + threadIdx.x; p < flevptr[l + 1]; p += BS) {
-      const int j = flevrows[p];
-      double d = D[j];
-      for (int q = rowptr[j]; q < rowptr[j + 1]; ++q) {
-        const double ljk = Lr[q];
-        d = d - ljk * ljk * D[rowcol[q]];
-      }
-      D[j] = d;
-      if (!(d > 0.0) || !isfinite(d)) atomicAdd(c.flags + 4, 1);
-    }
-    wg_sync<SM>();
-    for (int p = fentptr[l] + threadIdx.x; p < fentptr[l + 1]; p += BS) {
-      const int e = fent[p];
-      const int i = colrow[e];
-      const int pos = colpos[e];
-      const int j = rowcol[pos];
-      double s = Lr[pos];
-      int qi = rowptr[i], qj = rowptr[j];
-      const int qi1 = rowptr[i + 1], qj1 = rowptr[j + 1];
-      while (qi < qi1 && qj < qj1) {
-        const int ci = rowcol[qi], cj = rowcol[qj];
-        if (ci >= j) break;
-        if (ci == cj) {
-          s = s - Lr[qi] * D[ci] * Lr[qj];
-          ++qi;
-          ++qj;
-        } else if (ci < cj) {
-          ++qi;
-        } else {
-          ++qj;
-        }
-      }
-      Lr[pos] = s / D[j];
-    }
-    wg_sync<SM>();
-  }
+  constexpr int kPC = 2;  // pairs per load round (more measured no faster)
+  const int32_t *rent = c.symi + sd.rent;
+  const uint32_t *rpair = reinterpret_cast<const uint32_t *>(c.symi + sd.rpair);
   if constexpr (SM) {
-    (void)svmap;
+    ldl_levels<BS, SM, kPC>(sd.nlev, v.rf_rowptr, v.rf_flev, v.rf_rows, v.rf_fent_ptr, v.fcol, rent, rpair, Lr, D,
+                       c.flags + 4);
     (void)sv;
     (void)di;
     for (int r = threadIdx.x; r < n; r += BS) D[r] = 1.0 / D[r];
     lds_barrier();
   } else {
+    const int32_t *rowcol = c.symi + sd.rowcol;
+    const int32_t *flevptr = c.symi + sd.flevptr, *flevrows = c.symi + sd.flevrows;
+    const int32_t *fentptr = c.symi + sd.fentptr;
+    const int32_t *svmap = c.symi + sd.svmap;
+    ldl_levels<BS, SM, kPC>(sd.nlev, g_rowptr, flevptr, flevrows, fentptr, rowcol, rent, rpair, Lr, D, c.flags + 4);
     for (int q = threadIdx.x; q < sd.nsv; q += BS) sv[q] = Lr[svmap[q]];
     for (int r = threadIdx.x; r < n; r += BS) di[r] = 1.0 / D[r];
     __syncthreads();

@@ -136,6 +136,25 @@ def test_grid_with_bridge_loads_chunks_and_reset(torch_cuda, oracle_mod):
     assert rel(again, ref) < TOL
 
 
+@pytest.mark.parametrize("block_size,from_global", [(64, False), (512, False), (256, True)])
+def test_grid_with_bridge_loads_launch_variants(torch_cuda, oracle_mod, block_size, from_global):
+    # The factorisation inside the loop shares each level's rows and entries
+    # among teams of lanes whose width follows the block size; its structure
+    # is read from LDS or, with the sweep data in global memory, from there.
+    from paper_1903_01081_amd.sim import Simulator
+    net = grid_with_bridges(60, 14, [1, 5, 9], fault_step=400)
+    dt, T = 20e-6, 900
+    assert decision_margin(oracle_mod, net, dt, T) > 1e-10
+    say(f"grid with three diode-bridge loads, block size {block_size}, global structure {from_global}")
+    sim = Simulator([net], dt, T, solver="sparse", block_size=block_size, sweep_from_global=from_global)
+    sim.factor()
+    got = sim.step(T).cpu().numpy()[0]
+    sim.sync()
+    err = rel(got, oracle_mod.run(net, dt, T))
+    say("rel err", err)
+    assert err < TOL
+
+
 def test_diode_batch_vs_oracle(torch_cuda, oracle_mod):
     from paper_1903_01081_amd.sim import Simulator
     dt, T = 20e-6, 1200
